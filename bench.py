@@ -1,0 +1,180 @@
+"""Throughput of the rotational-alignment path on one GPU.
+
+A step is one pass of the whole path -- coefficient assembly, SOFFT search, frequency
+march and selection -- over one batch of synthetic particles already resident in HBM.
+Prints one JSON line (see the fields below).
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "particles/sec rotationally refined at L=32, batched vs plain; % of roofline"
+# FP32 VALU peak without packed-FP32 instructions: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+
+
+def wedge_terms(L):
+    """(l, wedge pair) recurrence steps of one evaluation at band L: sum_{l<=L} (l+1)^2."""
+    return (L + 1) * (L + 2) * (2 * L + 3) // 6
+
+
+def march_flops_per_particle(levels, L, steps, Kc):
+    """Algorithmic FP32 flops of the march for one particle (FMA = 2 flops).
+
+    Per wedge term and candidate: value + 2 derivative recurrences (16 flops) and 12
+    complex-by-real accumulations (24) for a derivative evaluation; 12 flops for the
+    value-only evaluation at the final point.  Per pair and candidate: the two phase
+    products, the real / imaginary parts and the 10 weighted sums (~100 flops; 40 for the
+    value only)."""
+    sched = [x for x in levels if x < L] + [L]
+    f = 0
+    for Lj in sched:
+        f += steps * (40 * wedge_terms(Lj) + 100 * (Lj + 1) ** 2)
+    f += 12 * wedge_terms(L) + 40 * (L + 1) ** 2
+    return Kc * f
+
+
+def cpu_baseline(b, wl, budget_s=15.0):
+    import oracle as O
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    threads = max(1, min(threads, os.cpu_count() or 1))
+    t0 = time.time()
+    O.align_batch(b, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps, particles=[0])
+    t1 = time.time() - t0
+    n = int(max(threads, min(b.n_particles, round(budget_s / max(t1, 1e-3) * threads))))
+    sample = np.linspace(0, b.n_particles - 1, n).astype(int)
+    t0 = time.time()
+    O.align_batch(b, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps, particles=sample)
+    dt = time.time() - t0
+    return {"value": n / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n} particles of the same workload spread over the batch, whole path "
+                      f"(assembly, SOFFT, march, selection) in FP64, OpenMP over particles, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="L32_R32_B12_K16")
+    ap.add_argument("--particles", type=int, default=None)
+    ap.add_argument("--plain", type=int, default=32, help="particles timed on the one-particle path")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); particles shard across GPUs "
+              "with no exchange in the forward path, so run one process per GPU.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2603_15285_amd import matcha as M
+    from paper_2603_15285_amd import synth as S
+
+    log = (lambda *a: None) if args.quiet else (lambda *a: print(*a, file=sys.stderr, flush=True))
+    wl = S.WORKLOADS[args.workload]
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    b = S.make_workload(args.workload, n_particles=args.particles)
+    log(f"generated {b.n_particles} particles in {time.time() - t0:.1f} s")
+    P = b.n_particles
+    ctx = M.Context(0)
+    ctx.prepare(int(b.L.max()), wl.B, wl.n_grid)
+    batch = M.Batch.make(b.L, b.R, b.L_h, b.R_h, f_offset=b.f_offset)
+    f = torch.from_numpy(b.f_flat.astype(np.complex64).view(np.float32)).cuda()
+    h = torch.from_numpy(b.h.astype(np.complex64).view(np.float32).reshape(-1)).cuda()
+    w = torch.from_numpy(b.w.astype(np.float32)).cuda()
+    bufs = {}
+    stream = torch.cuda.current_stream()
+
+    def step(ev=None):
+        C = M.coeff_assemble(ctx, batch, f, h, w, C=bufs.get("C"))
+        cand, status = M.soft_search(ctx, batch, C, wl.B, wl.n_grid, wl.Kc, cand=bufs.get("cand"),
+                                     status=bufs.get("status"))
+        if ev is not None:
+            ev[0].record(stream)
+        best, bi, status = M.march_newton(ctx, batch, C, wl.levels, wl.steps, cand, status, best=bufs.get("best"),
+                                          best_idx=bufs.get("best_idx"))
+        if ev is not None:
+            ev[1].record(stream)
+        bufs.update(C=C, cand=cand, status=status, best=best, best_idx=bi)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record(stream)
+    for k in range(args.steps):
+        step(evs[k])
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t_start.elapsed_time(t_end)
+    ms_step = ms_total / args.steps
+    ms_march = float(np.mean([a.elapsed_time(z) for a, z in evs]))
+    value = P / (ms_step / 1e3)
+    log(f"batched: {ms_step:.3f} ms/step, march {ms_march:.3f} ms, {value:.0f} particles/s")
+
+    best = bufs["best"].cpu().numpy().astype(np.float64)
+    err = S.geodesic_deg(b.R_true(), S.euler_zyz_to_matrix(best[:, 0], best[:, 1], best[:, 2]))
+
+    # plain path: one particle per call sequence, same kernels, no graph
+    n_plain = min(args.plain, P)
+    singles = []
+    for p in range(n_plain):
+        sb = M.Batch.make(b.L[p:p + 1], b.R[p:p + 1], b.L_h, b.R_h, f_offset=[0])
+        o, sz = int(b.f_offset[p]), int(b.R[p]) * (int(b.L[p]) + 1) ** 2
+        singles.append((sb, f[2 * o: 2 * (o + sz)], {}))
+
+    def plain_one(sb, fp, bb):
+        M.align(ctx, sb, fp, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, bufs=bb)
+
+    for sb, fp, bb in singles[:2]:
+        plain_one(sb, fp, bb)
+    torch.cuda.synchronize()
+    p0, p1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    p0.record(stream)
+    for sb, fp, bb in singles:
+        plain_one(sb, fp, bb)
+    p1.record(stream)
+    torch.cuda.synchronize()
+    plain_value = n_plain / (p0.elapsed_time(p1) / 1e3)
+    log(f"plain: {plain_value:.0f} particles/s over {n_plain} particles")
+
+    flops = sum(march_flops_per_particle(wl.levels, int(Lp), wl.steps, wl.Kc) for Lp in b.L)
+    achieved = flops / (ms_march / 1e3) / 1e12
+    out = {
+        "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "particles": P, "L": int(b.L.max()), "shells": int(b.R.max()),
+                   "B": wl.B, "n_grid": wl.n_grid, "Kc": wl.Kc, "levels": list(wl.levels),
+                   "newton_steps_per_level": wl.steps, "snr": list(wl.snr) if isinstance(wl.snr, tuple) else wl.snr},
+        "roofline": {"kernel": "k_march (frequency march: value, gradient, Hessian, Newton, selection)",
+                     "bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": None, "ms_per_launch": ms_march},
+        "plain": {"value": plain_value, "unit": "particles/s", "particles": n_plain},
+        "batched_over_plain": value / plain_value,
+        "rot_err_vs_truth_deg": {"median": float(np.median(err)), "p90": float(np.percentile(err, 90)),
+                                 "max": float(err.max())},
+    }
+    if not args.no_cpu:
+        log("cpu baseline ...")
+        out["cpu_baseline"] = cpu_baseline(b, wl)
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,199 @@
+/*
+ * matcha.h -- C ABI of libmatcha, the MI355X (gfx950) implementation of the
+ * rotational-alignment path of "Matcha: Fast Volume Alignment by
+ * Frequency-Marched Newton Method":
+ *
+ *   coefficient assembly  (Sec. 2.1, eq. sigmalmm)
+ *   -> low-bandwidth SOFFT search keeping the strongest local maxima (Sec. 2.3)
+ *   -> frequency-marched Newton refinement and final selection (Sec. 2.2, 2.4, Alg. 1)
+ *   and the adjoint of the selected objective value with respect to the inputs.
+ *
+ * Conventions (App. A.3-A.5).  Rotations use the ZYZ chart
+ * g(a, b, c) = r_z(a) r_y(b) r_z(c) (eq. Euler), angles in radians, a and c in
+ * [0, 2pi), b in [0, pi].  D^l_mn(a, b, c) = e^{-ima} d^l_mn(b) e^{-inc}
+ * (eq. wigner-D) with d^l_mn(b) = <l m| exp(-i b J_y) |l n>.  The objective is
+ *   C_L(g) = Re sum_{l<=L} sum_{m,n} C^l_mn conj(D^l_mn(g)),
+ *   C^l_mn = sum_r w_r f_lm(r) conj(h_ln(r)),
+ * i.e. <f, g o h> with (g o h)_l = D^l(g) h_l; the conjugation of D is the
+ * "conjugation absorbed into the coefficients" of App. A.5.
+ *
+ * Memory.  Every pointer is a device pointer unless its comment says (host).
+ * The caller allocates every input, output and workspace buffer; the library
+ * keeps no pointer after the enqueued work completes.  A context owns only
+ * read-only tables (recurrence coefficients, SOFFT node data) that it builds on
+ * the first call that needs them or in matcha_prepare().  Every call validates its
+ * arguments synchronously on the host and then enqueues its kernels on `stream`
+ * (a hipStream_t passed as void*); nothing waits on the device.  A context is not
+ * thread-safe.
+ *
+ * Errors.  Invalid arguments return MATCHA_ERR_INVALID_ARG and enqueue nothing.
+ * Launch failures return MATCHA_ERR_HIP.  Numerical conditions never fail a call;
+ * they set per-particle status bits (MATCHA_ST_*).  No C++ exception crosses the ABI.
+ *
+ * Layouts.
+ *   complex      : interleaved (re, im), float32 unless stated.
+ *   f (particle) : particle p at element offset f_offset[p]: [R_p][(L_p+1)^2],
+ *                  lm = l*l + l + m.  h (template): [R_h][(L_h+1)^2].  Inputs must be
+ *                  Hermitian-symmetric, c_{l,-m} = (-1)^m conj(c_lm) (real volumes);
+ *                  kernels read only the m >= 0 half.
+ *   C (wedge)    : particle p at element offset C_offset[p], matcha_c_elems(L_p)
+ *                  complex values.  For l = 0..L_p, for every "wedge pair"
+ *                  (m, n) with 0 <= |n| <= m <= l, in the order q = m*m + m + n,
+ *                  two values: C^l_mn and C^l_{m'n'} of its partner
+ *                  (m', n') = (n, m) if n >= 0, (-n, -m) if n < 0.
+ *                  Row l starts at 2 * l(l+1)(2l+1)/6 complex values.  The wedge and
+ *                  its partners cover {m > 0} and {m = 0, n >= 0}; the other half
+ *                  follows from C^l_{-m,-n} = (-1)^{m-n} conj(C^l_mn).
+ *   candidates   : float4 (a, b, c, value) per candidate, [P][Kc].
+ */
+#ifndef MATCHA_H
+#define MATCHA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MATCHA_OK = 0,
+    MATCHA_ERR_INVALID_ARG = -1,
+    MATCHA_ERR_UNSUPPORTED = -2,
+    MATCHA_ERR_HIP = -3,
+    MATCHA_ERR_WORKSPACE = -4
+} matcha_status;
+
+typedef enum {
+    MATCHA_FP32 = 0,        /* FP32 storage and arithmetic                                  */
+    MATCHA_BF16_FP32ACC = 1 /* BF16 f/h storage, MFMA products with FP32 accumulation      */
+} matcha_precision;
+
+/* per-particle status bits (numerical conditions; never an error) */
+#define MATCHA_ST_NONFINITE 1u   /* a non-finite objective value or derivative was met   */
+#define MATCHA_ST_INDEFINITE 2u  /* a Newton step was taken with H not negative definite */
+#define MATCHA_ST_SINGULAR 4u    /* |det H| <= 1e-30 max|H|^3: the step was skipped       */
+#define MATCHA_ST_NEAR_POLE 8u   /* sin b < 1e-3 after a step (chart singular at b = 0, pi) */
+#define MATCHA_ST_FEW_MAXIMA 16u /* the SOFFT grid had fewer than Kc local maxima         */
+#define MATCHA_ST_EARLY_STOP 32u /* early stopping ended a level before M_iter steps      */
+
+/* Limits of this build. */
+#define MATCHA_MAX_L 64
+#define MATCHA_MAX_KC 64
+#define MATCHA_MAX_LEVELS 16
+
+typedef struct matcha_ctx matcha_ctx;
+
+/* A batch of particles.  Per-particle band limits L_p <= L_max and shell counts
+ * R_p <= R_h are given twice: on the host (validation, launch sizing) and on the
+ * device (kernels).  Particle p uses template shells 0..R_p-1 and degrees l <= L_p. */
+typedef struct {
+    int32_t n_particles;
+    int32_t L_max;              /* max_p L_p                                    */
+    const int32_t *L_host;      /* (host) [P]                                   */
+    const int32_t *R_host;      /* (host) [P]                                   */
+    const int32_t *L_dev;       /* [P]                                          */
+    const int32_t *R_dev;       /* [P]                                          */
+    const int64_t *f_offset;    /* [P] complex-element offsets of particles in f */
+    const int64_t *C_offset;    /* [P] complex-element offsets in C              */
+    int32_t L_h, R_h;           /* template extents: h is [R_h][(L_h+1)^2]       */
+} matcha_batch;
+
+/* SOFFT search (Sec. 2.3): grid of n_grid^3 rotations a_j = 2 pi j/n,
+ * b_i = pi (2i+1)/(2n), c_k = 2 pi k/n; band B = L0 (the paper's oversampling K
+ * gives n_grid = 2 K B); keep the Kc strongest local maxima (the paper's P). */
+typedef struct {
+    int32_t B;
+    int32_t n_grid;
+    int32_t Kc;
+} matcha_soft_cfg;
+
+/* Frequency march (Alg. 1).  levels (host) is the global schedule; particle p
+ * runs every level < L_p and then L_p.  steps = M_iter Newton steps per level.
+ * max_step > 0 clips the largest component of a Newton step (0: pure Newton, as
+ * in the paper).  early_stop enables the Sec. 2.4 tolerances. */
+typedef struct {
+    const int32_t *levels; /* (host) strictly increasing, levels[0] >= 1 */
+    int32_t n_levels;
+    int32_t steps;
+    double max_step;
+    int32_t early_stop;
+    double tol_grad, tol_step, tol_rel;
+} matcha_march_cfg;
+
+/* ---- context ---------------------------------------------------------- */
+/* Creates a context on HIP device `device`.  out receives the handle. */
+matcha_status matcha_create(int device, matcha_ctx **out);
+matcha_status matcha_destroy(matcha_ctx *ctx);
+/* Builds the read-only tables for band limits up to L_max and (if n_grid > 0) the
+ * SOFFT band B on an n_grid^3 grid, so that later calls allocate nothing (needed
+ * before stream capture).  Synchronous. */
+matcha_status matcha_prepare(matcha_ctx *ctx, int32_t L_max, int32_t B, int32_t n_grid);
+const char *matcha_status_string(matcha_status s);
+
+/* ---- sizes -------------------------------------------------------------- */
+/* Complex values of one particle's wedge-layout C for band limit L:
+ * 2 * (L+1)(L+2)(2L+3)/6.  Returns -1 if L is outside [0, MATCHA_MAX_L]. */
+int64_t matcha_c_elems(int32_t L);
+/* Complex values of one particle's f: R (L+1)^2. */
+int64_t matcha_f_elems(int32_t L, int32_t R);
+/* Bytes of workspace needed by matcha_soft_search / matcha_march_newton /
+ * matcha_grad_template for this batch (0 when none). */
+size_t matcha_workspace_size(const matcha_batch *batch, int32_t Kc);
+
+/* ---- the path ------------------------------------------------------------ */
+/* Coefficient assembly, eq. sigmalmm (Sec. 2.1, App. A.5) with shells in place of
+ * the radial index:  C^l_mn = sum_{r < R_p} w_r f_lm(r) conj(h_ln(r)), l <= L_p.
+ * f, h: complex float32 (MATCHA_FP32) or complex bfloat16 (MATCHA_BF16_FP32ACC,
+ * interleaved (re, im) bf16 pairs); w: float32 [R_h]; C: complex float32, wedge
+ * layout.  Accumulation is FP32 in both modes. */
+matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
+                                    const float *w, float *C, matcha_precision prec, void *stream);
+
+/* SOFFT search at band B (Sec. 2.3; Alg. 1 lines 1-2): evaluates C_B on the
+ * n_grid^3 grid (Wigner-d transform over l, then a 2-D inverse DFT over (a, c)),
+ * finds the nodes that beat all 26 neighbours (a, c periodic; b neighbours outside
+ * the grid absent; equal values: the smaller linear index i n^2 + j n + k wins),
+ * ranks them by (value desc, index asc) and writes the first Kc to cand
+ * [P][Kc] float4 (a_j, b_i, c_k, value).  With fewer than Kc maxima the list is
+ * filled with the best remaining nodes and MATCHA_ST_FEW_MAXIMA is set.
+ * status [P] is overwritten.  Requires 1 <= B <= min_p L_p, 4 <= n_grid <= 256,
+ * 1 <= Kc <= MATCHA_MAX_KC. */
+matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
+                                 const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream);
+
+/* Frequency-marched Newton refinement and selection (Alg. 1 lines 3-8, Sec. 2.2):
+ * for every candidate, M_iter Newton steps theta <- theta - H^{-1} grad C_L on
+ * each level of the particle's schedule, the 3x3 system inverted explicitly in
+ * FP64; then C_{L_p} at each final point, and the candidate with the largest value
+ * (ties: lowest index; non-finite values never win).
+ * cand [P][Kc] float4 in/out: in = start points, out = (final angles, C_{L_p}).
+ * best [P] float4 (a, b, c, C_{L_p}) of the selected candidate; best_idx [P];
+ * status [P] in/out: the selected candidate's bits are OR-ed into it. */
+matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
+                                  const matcha_march_cfg *cfg, int32_t Kc, float *cand, float *best,
+                                  int32_t *best_idx, uint32_t *status, void *stream);
+
+/* Objective only: value, gradient and Hessian of C_{L_eval} at one rotation per
+ * particle.  theta [P] float4 (a, b, c, unused); out [P][10] float:
+ * F, F_a, F_b, F_c, F_aa, F_ab, F_ac, F_bb, F_bc, F_cc (Sec. 2.2, App. A.4).
+ * L_eval <= L_p for every particle. */
+matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const float *C, int32_t L_eval,
+                              const float *theta, float *out, void *stream);
+
+/* Adjoint of sum_p g_p C_{L_p}(R_p*) at fixed rotations R_p* = best[p]
+ * (envelope theorem), as d/dRe + i d/dIm of the full complex arrays:
+ *   grad_h[r][l,n] = sum_p g_p w_r sum_m f_p,lm(r) conj(D^l_mn(R_p*))
+ *   grad_f_p[r][l,m] = g_p w_r sum_n D^l_mn(R_p*) h_ln(r)
+ * grad_h: complex float32 [R_h][(L_h+1)^2] (entries outside every particle's
+ * range are zeroed); grad_f: same layout as f; either may be NULL.  The sum over
+ * particles is deterministic (fixed-order tree, no floating-point atomics).
+ * ws: workspace of matcha_workspace_size() bytes. */
+matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, const float *f, const float *h,
+                                   const float *w, const float *best, const float *g, float *grad_h, float *grad_f,
+                                   void *ws, size_t ws_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MATCHA_H */

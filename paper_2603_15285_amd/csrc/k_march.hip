@@ -1,0 +1,510 @@
+// k_march.hip -- objective, gradient and Hessian of the band-limited correlation and the
+// frequency-marched Newton refinement (Sec. 2.2, 2.4, Alg. 1).
+//
+// Work decomposition.  A wave owns NC candidates of one particle.  Its 64 lanes walk the
+// "wedge" pairs (m, n), 0 <= |n| <= m <= L, in tiles of 64; each lane runs the Wigner-d
+// three-term recurrence in l for its pair, with its first and second b-derivatives,
+// for all NC candidates at once (the recurrence coefficients and the C loads are shared
+// by the candidates).  For real inputs C^l_{-m,-n} = (-1)^{m-n} conj(C^l_mn), and
+// d_mn = (-1)^{m-n} d_nm = d_{-n,-m}, so one recurrence step serves four terms of the
+// full sum: the pair, its partner (n, m) or (-n, -m), and their Hermitian mirrors.
+//
+// Per lane and candidate the l-sums U_s = sum_l C^l P_l D^l_s (s = value, d/db, d2/db2)
+// are accumulated for the pair and its partner; the e^{i(ma+nc)} phase, constant in l,
+// is applied once per pair afterwards, together with the m and n weights of the
+// a / c derivatives.  D^l = d^l / P_l is the recurrence normalised so that its
+// three-term relation has unit coefficient on D^{l-2} (P_l is tabulated per pair).
+#include "matcha_launch.hpp"
+
+namespace matcha {
+
+
+// Phase tables and reduction scratch share one LDS region per wave.
+template <int NC>
+struct __align__(16) WaveScratch {
+    union {
+        struct {
+            float2 ea[NC][kMaxL + 1];  // e^{i k a_c}
+            float2 eg[NC][kMaxL + 1];  // e^{i k c_c}
+        } ph;
+        float red[10 * NC][16];
+    };
+};
+
+template <int NC>
+struct WaveState {
+    BetaConst bc[NC];
+    double th[NC][3];
+    float tot[NC][10];
+    uint32_t st[NC];
+    int frozen[NC];
+    float fprev[NC];
+};
+
+__device__ inline void fill_phases(double a, double c, int L, float2 *ea, float2 *eg, int lane)
+{
+    for (int k = lane; k <= L; k += kWave) {
+        double ta = fmod((double)k * a, kTwoPi), tc = fmod((double)k * c, kTwoPi);
+        float sa, ca, sc, cc;
+        sincosf((float)ta, &sa, &ca);
+        sincosf((float)tc, &sc, &cc);
+        ea[k] = make_float2(ca, sa);
+        eg[k] = make_float2(cc, sc);
+    }
+}
+
+// One recurrence row for NC candidates.  On entry X = D^{l-1}, Y = D^{l-2} (X1, Y1: first
+// b-derivative; X2, Y2: half the second b-derivative); on exit Y holds row l.  tb = (A, AC, PW,
+// PWT) of row l, cc = (C^l_pair, C^l_partner).  U[c] accumulates sum_l C^l PW_l D^l for the pair
+// (0, 1) and C^l PWT_l D^l for the partner (2, 3), then the same for D' (4..7) and D''/2 (8..11).
+// With u = A cos b - AC, v = A sin b, h = A cos b / 2 the differentiated relations read
+//   D'^l = u D'^{l-1} - v D^{l-1} - D'^{l-2},  (D''/2)^l = u (D''/2)^{l-1} - v D'^{l-1} - h D^{l-1} - (D''/2)^{l-2}.
+template <int NC, bool DERIV>
+__device__ __forceinline__ void row_step(const float4 tb, const float4 cc, const float *cbv, const float *sbv,
+                                         const float *chv, float (&X)[NC], float (&Y)[NC], float (&X1)[NC],
+                                         float (&Y1)[NC], float (&X2)[NC], float (&Y2)[NC],
+                                         float (&U)[NC][DERIV ? 12 : 4])
+{
+    const float s0r = cc.x * tb.z, s0i = cc.y * tb.z, s1r = cc.z * tb.w, s1i = cc.w * tb.w;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const float u = fmaf(tb.x, cbv[c], -tb.y);
+        const float dn = fmaf(u, X[c], -Y[c]);
+        U[c][0] = fmaf(s0r, dn, U[c][0]);
+        U[c][1] = fmaf(s0i, dn, U[c][1]);
+        U[c][2] = fmaf(s1r, dn, U[c][2]);
+        U[c][3] = fmaf(s1i, dn, U[c][3]);
+        if (DERIV) {
+            const float v = tb.x * sbv[c];
+            const float h = tb.x * chv[c];
+            const float d1n = fmaf(u, X1[c], fmaf(-v, X[c], -Y1[c]));
+            const float d2n = fmaf(u, X2[c], fmaf(-v, X1[c], fmaf(-h, X[c], -Y2[c])));
+            Y1[c] = d1n;
+            Y2[c] = d2n;
+            U[c][4] = fmaf(s0r, d1n, U[c][4]);
+            U[c][5] = fmaf(s0i, d1n, U[c][5]);
+            U[c][6] = fmaf(s1r, d1n, U[c][6]);
+            U[c][7] = fmaf(s1i, d1n, U[c][7]);
+            U[c][8] = fmaf(s0r, d2n, U[c][8]);
+            U[c][9] = fmaf(s0i, d2n, U[c][9]);
+            U[c][10] = fmaf(s1r, d2n, U[c][10]);
+            U[c][11] = fmaf(s1i, d2n, U[c][11]);
+        }
+        Y[c] = dn;
+    }
+}
+
+__device__ __forceinline__ float4 ld_row(const float4 *base, int row, uint32_t lane_bytes)
+{
+    const char *p = reinterpret_cast<const char *>(base + row);
+    return *reinterpret_cast<const float4 *>(p + lane_bytes);
+}
+
+// Sum over all wedge pairs of one level for NC candidates.  acc[c][0..9] receive the
+// (positive-sign, undoubled) sums described at the top of the file; with DERIV == false
+// only acc[c][0] (the value) is formed.
+template <int NC, bool DERIV>
+__device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restrict__ tab,
+                           const PairInfo *__restrict__ pinfo, int L, const BetaConst *bc, const WaveScratch<NC> &ws,
+                           float (&acc)[NC][10], int lane)
+{
+    constexpr int NU = DERIV ? 12 : 4;
+    float cbv[NC], sbv[NC], chv[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        cbv[c] = bcast(bc[c].cb);
+        sbv[c] = bcast(bc[c].sb);
+        chv[c] = 0.5f * cbv[c];
+#pragma unroll
+        for (int v = 0; v < 10; ++v) acc[c][v] = 0.f;
+    }
+    const int npairs = (L + 1) * (L + 1);
+    const int ntiles = (npairs + kWave - 1) / kWave;
+    for (int t = 0; t < ntiles; ++t) {
+        const int q0 = t * kWave;
+        const int q = q0 + lane;
+        const bool valid = q < npairs;
+        const int qe = valid ? q : npairs - 1;
+        const PairInfo pi = pinfo[qe];
+        const int m = pi.m, n = pi.n;
+        const int mlo = isqrt_dev(q0);
+        const int mhi = isqrt_dev(min(q0 + kWave - 1, npairs - 1));
+
+        float D[NC], Dm[NC], D1[NC], D1m[NC], D2[NC], D2m[NC];
+        float U[NC][NU];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            D[c] = Dm[c] = D1[c] = D1m[c] = D2[c] = D2m[c] = 0.f;
+#pragma unroll
+            for (int v = 0; v < NU; ++v) U[c][v] = 0.f;
+        }
+
+        // rows where some lanes of the tile are still before their edge l = m
+        int row = (int)wedge_row(mlo);
+        for (int l = mlo; l <= mhi; ++l) {
+            const bool act = valid && m <= l;
+            float4 tb = make_float4(0.f, 0.f, 0.f, 0.f), cc = tb;
+            if (act) {
+                tb = tab[row + q];
+                cc = Cp[row + q];
+            }
+            row += (l + 1) * (l + 1);
+            const float s0r = cc.x * tb.z, s0i = cc.y * tb.z, s1r = cc.z * tb.w, s1i = cc.w * tb.w;
+            const bool seed = (m == l);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                float sd0 = 0.f, sd1 = 0.f, sd2 = 0.f;
+                if (seed) edge_seed(m, n, pi.lbh2, bc[c], sd0, sd1, sd2);
+                const float u = fmaf(tb.x, cbv[c], -tb.y);
+                float dn = seed ? sd0 : fmaf(u, D[c], -Dm[c]);
+                U[c][0] = fmaf(s0r, dn, U[c][0]);
+                U[c][1] = fmaf(s0i, dn, U[c][1]);
+                U[c][2] = fmaf(s1r, dn, U[c][2]);
+                U[c][3] = fmaf(s1i, dn, U[c][3]);
+                if (DERIV) {
+                    const float v = tb.x * sbv[c];
+                    const float h = tb.x * chv[c];
+                    float d1n = seed ? sd1 : fmaf(u, D1[c], fmaf(-v, D[c], -D1m[c]));
+                    float d2n = seed ? 0.5f * sd2 : fmaf(u, D2[c], fmaf(-v, D1[c], fmaf(-h, D[c], -D2m[c])));
+                    D1m[c] = D1[c];
+                    D1[c] = d1n;
+                    D2m[c] = D2[c];
+                    D2[c] = d2n;
+                    U[c][4] = fmaf(s0r, d1n, U[c][4]);
+                    U[c][5] = fmaf(s0i, d1n, U[c][5]);
+                    U[c][6] = fmaf(s1r, d1n, U[c][6]);
+                    U[c][7] = fmaf(s1i, d1n, U[c][7]);
+                    U[c][8] = fmaf(s0r, d2n, U[c][8]);
+                    U[c][9] = fmaf(s0i, d2n, U[c][9]);
+                    U[c][10] = fmaf(s1r, d2n, U[c][10]);
+                    U[c][11] = fmaf(s1i, d2n, U[c][11]);
+                }
+                Dm[c] = D[c];
+                D[c] = dn;
+            }
+        }
+        // rows where every lane of the tile is past its edge: two rows per trip, the state
+        // ping-pongs between (D, Dm) and the next rows' loads are in flight meanwhile.  Loads
+        // past row L re-read row L (never used), so they need no branch.
+        {
+            const uint32_t lb = (uint32_t)qe * 16u;
+            const int rowL = (int)wedge_row(L);
+            int l = mhi + 1;
+            int r0 = min(row, rowL);
+            float4 tb0 = ld_row(tab, r0, lb), cc0 = ld_row(Cp, r0, lb);
+            row += (l + 1) * (l + 1);
+            int r1 = min(row, rowL);
+            float4 tb1 = ld_row(tab, r1, lb), cc1 = ld_row(Cp, r1, lb);
+            row += (l + 2) * (l + 2);
+            for (; l + 1 <= L; l += 2) {
+                row_step<NC, DERIV>(tb0, cc0, cbv, sbv, chv, D, Dm, D1, D1m, D2, D2m, U);
+                r0 = min(row, rowL);
+                tb0 = ld_row(tab, r0, lb);
+                cc0 = ld_row(Cp, r0, lb);
+                row += (l + 3) * (l + 3);
+                row_step<NC, DERIV>(tb1, cc1, cbv, sbv, chv, Dm, D, D1m, D1, D2m, D2, U);
+                r1 = min(row, rowL);
+                tb1 = ld_row(tab, r1, lb);
+                cc1 = ld_row(Cp, r1, lb);
+                row += (l + 4) * (l + 4);
+            }
+            if (l <= L) row_step<NC, DERIV>(tb0, cc0, cbv, sbv, chv, D, Dm, D1, D1m, D2, D2m, U);
+        }
+        if (!valid) continue;
+        // phases and the m, n weights of the a / c derivatives
+        const int an = n >= 0 ? n : -n;
+        const float a1 = (float)m, b1 = (float)n;
+        const float a2 = n >= 0 ? (float)n : (float)(-n), b2 = n >= 0 ? (float)m : (float)(-m);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const float2 am = ws.ph.ea[c][m], aN = ws.ph.ea[c][an];
+            float2 gm = ws.ph.eg[c][m], gN = ws.ph.eg[c][an];
+            if (n < 0) {
+                gN = cconj(gN);
+                gm = cconj(gm);
+            }
+            const float2 p1 = cmul(am, gN);  // e^{i(m a + n c)}
+            const float2 p2 = cmul(aN, gm);  // e^{i(a2 a + b2 c)}
+            const float R0 = p1.x * U[c][0] - p1.y * U[c][1];
+            const float T0 = p2.x * U[c][2] - p2.y * U[c][3];
+            acc[c][0] += R0 + T0;
+            if (DERIV) {
+                const float I0 = p1.x * U[c][1] + p1.y * U[c][0];
+                const float J0 = p2.x * U[c][3] + p2.y * U[c][2];
+                const float R1 = p1.x * U[c][4] - p1.y * U[c][5];
+                const float I1 = p1.x * U[c][5] + p1.y * U[c][4];
+                const float T1 = p2.x * U[c][6] - p2.y * U[c][7];
+                const float J1 = p2.x * U[c][7] + p2.y * U[c][6];
+                const float R2 = 2.f * (p1.x * U[c][8] - p1.y * U[c][9]);
+                const float T2 = 2.f * (p2.x * U[c][10] - p2.y * U[c][11]);
+                acc[c][1] += a1 * I0 + a2 * J0;
+                acc[c][2] += R1 + T1;
+                acc[c][3] += b1 * I0 + b2 * J0;
+                acc[c][4] += a1 * a1 * R0 + a2 * a2 * T0;
+                acc[c][5] += a1 * I1 + a2 * J1;
+                acc[c][6] += a1 * b1 * R0 + a2 * b2 * T0;
+                acc[c][7] += R2 + T2;
+                acc[c][8] += b1 * I1 + b2 * J1;
+                acc[c][9] += b1 * b1 * R0 + b2 * b2 * T0;
+            }
+        }
+    }
+}
+
+// Lane-sums of the wave's NC x NV accumulators: two xor-shuffle stages fold the 64 lanes
+// onto 16, the 16 partial sums go through LDS, and lane v < NC*NV ends with total v in
+// st.tot.
+template <int NC, int NV>
+__device__ void wave_reduce(float (&acc)[NC][10], WaveScratch<NC> &ws, WaveState<NC> &st, int lane)
+{
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            float x = acc[c][v];
+            x += __shfl_xor(x, 32);
+            x += __shfl_xor(x, 16);
+            if (lane < 16) ws.red[c * NV + v][lane] = x;
+        }
+    __syncthreads();
+    for (int v = lane; v < NC * NV; v += kWave) {
+        const float4 *row = reinterpret_cast<const float4 *>(ws.red[v]);
+        const float4 x0 = row[0], x1 = row[1], x2 = row[2], x3 = row[3];
+        st.tot[v / NV][v % NV] = ((x0.x + x0.y) + (x0.z + x0.w)) + ((x1.x + x1.y) + (x1.z + x1.w)) +
+                                 (((x2.x + x2.y) + (x2.z + x2.w)) + ((x3.x + x3.y) + (x3.z + x3.w)));
+    }
+    __syncthreads();
+}
+
+__device__ inline double wrap2pi(double x)
+{
+    x = fmod(x, kTwoPi);
+    return x < 0.0 ? x + kTwoPi : x;
+}
+
+// Newton step theta <- theta - H^{-1} grad in FP64 with the explicit 3x3 inverse; the
+// readings for indefinite / singular H, clipping and chart wrapping are those of the
+// interface documentation.  e = F, Fa, Fb, Fc, Faa, Fab, Fac, Fbb, Fbc, Fcc.
+__device__ uint32_t newton_step(const double *e, double max_step, double *th, double *step_inf)
+{
+    for (int i = 0; i < 10; ++i)
+        if (!isfinite(e[i])) {
+            *step_inf = 0.0;
+            return 1u;
+        }
+    const double h00 = e[4], h01 = e[5], h02 = e[6], h11 = e[7], h12 = e[8], h22 = e[9];
+    const double c00 = h11 * h22 - h12 * h12, c01 = h02 * h12 - h01 * h22, c02 = h01 * h12 - h02 * h11;
+    const double c11 = h00 * h22 - h02 * h02, c12 = h02 * h01 - h00 * h12, c22 = h00 * h11 - h01 * h01;
+    const double det = h00 * c00 + h01 * c01 + h02 * c02;
+    double hmax = fmax(fmax(fabs(h00), fabs(h01)), fmax(fmax(fabs(h02), fabs(h11)), fmax(fabs(h12), fabs(h22))));
+    uint32_t st = 0;
+    if (!(-h00 > 0.0 && c22 > 0.0 && -det > 0.0)) st |= 2u;
+    if (!(fabs(det) > 1e-30 * hmax * hmax * hmax)) {
+        *step_inf = 0.0;
+        return st | 4u;
+    }
+    const double g0 = e[1], g1 = e[2], g2 = e[3];
+    double d0 = -(c00 * g0 + c01 * g1 + c02 * g2) / det;
+    double d1 = -(c01 * g0 + c11 * g1 + c12 * g2) / det;
+    double d2 = -(c02 * g0 + c12 * g1 + c22 * g2) / det;
+    double mx = fmax(fabs(d0), fmax(fabs(d1), fabs(d2)));
+    if (max_step > 0.0 && mx > max_step) {
+        const double s = max_step / mx;
+        d0 *= s;
+        d1 *= s;
+        d2 *= s;
+        mx = max_step;
+    }
+    *step_inf = mx;
+    double a = th[0] + d0, b = th[1] + d1, c = th[2] + d2;
+    b = wrap2pi(b);
+    if (b > kPi) {
+        b = kTwoPi - b;
+        a += kPi;
+        c += kPi;
+    }
+    th[0] = wrap2pi(a);
+    th[1] = b;
+    th[2] = wrap2pi(c);
+    return st;
+}
+
+template <int NC>
+__device__ void prepare_step(WaveState<NC> &st, WaveScratch<NC> &ws, int L, int lane)
+{
+    if (lane < NC) st.bc[lane] = beta_const(st.th[lane][1]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) fill_phases(st.th[c][0], st.th[c][2], L, ws.ph.ea[c], ws.ph.eg[c], lane);
+    __syncthreads();
+}
+
+template <int NC>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 3 : 2, 8))) k_march(MarchArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int p = blockIdx.x;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int G = blockDim.x / kWave;
+    WaveScratch<NC> &ws = reinterpret_cast<WaveScratch<NC> *>(smem)[wave];
+    WaveState<NC> &st = reinterpret_cast<WaveState<NC> *>(smem + G * sizeof(WaveScratch<NC>))[wave];
+    float *fin = reinterpret_cast<float *>(smem + G * (sizeof(WaveScratch<NC>) + sizeof(WaveState<NC>)));
+    uint32_t *fst = reinterpret_cast<uint32_t *>(fin + G * NC);
+
+    const int Lp = a.Lp[p];
+    const float4 *Cp = a.C + a.C_off[p] / 2;
+    if (lane < NC) {
+        const int k = wave * NC + lane;
+        float4 c0 = k < a.Kc ? a.cand[(int64_t)p * a.Kc + k] : make_float4(0.f, 1.5707964f, 0.f, 0.f);
+        st.th[lane][0] = c0.x;
+        st.th[lane][1] = c0.y;
+        st.th[lane][2] = c0.z;
+        st.st[lane] = 0;
+        st.frozen[lane] = 0;
+        st.fprev[lane] = 0.f;
+    }
+    __syncthreads();
+
+    float acc[NC][10];
+    // schedule: every global level below Lp, then Lp
+    int ns = 1;
+    for (int j = 0; j < a.n_levels; ++j) ns += a.levels[j] < Lp;
+    for (int j = 0; j < ns; ++j) {
+        const int L = j + 1 < ns ? a.levels[j] : Lp;
+        if (lane < NC) st.frozen[lane] = 0;
+        for (int s = 0; s < a.steps; ++s) {
+            prepare_step<NC>(st, ws, L, lane);
+            eval_level<NC, true>(Cp, a.tab, a.pinfo, L, st.bc, ws, acc, lane);
+            wave_reduce<NC, 10>(acc, ws, st, lane);
+            if (lane < NC && !st.frozen[lane]) {
+                double e[10];
+                const float *tv = st.tot[lane];
+                e[0] = 2.0 * tv[0];
+                e[1] = -2.0 * tv[1];
+                e[2] = 2.0 * tv[2];
+                e[3] = -2.0 * tv[3];
+                e[4] = -2.0 * tv[4];
+                e[5] = -2.0 * tv[5];
+                e[6] = -2.0 * tv[6];
+                e[7] = 2.0 * tv[7];
+                e[8] = -2.0 * tv[8];
+                e[9] = -2.0 * tv[9];
+                bool stop = false;
+                if (a.early_stop) {
+                    const double gn = sqrt(e[1] * e[1] + e[2] * e[2] + e[3] * e[3]);
+                    if (gn <= a.tol_grad * fabs(e[0]) || (s > 0 && fabs(e[0] - st.fprev[lane]) <= a.tol_rel * fabs(e[0])))
+                        stop = true;
+                }
+                st.fprev[lane] = (float)e[0];
+                if (stop) {
+                    st.st[lane] |= 32u;
+                    st.frozen[lane] = 1;
+                } else {
+                    double sinf_ = 0.0;
+                    st.st[lane] |= newton_step(e, a.max_step, st.th[lane], &sinf_);
+                    if (sin(st.th[lane][1]) < 1e-3) st.st[lane] |= 8u;
+                    if (a.early_stop && sinf_ <= a.tol_step) {
+                        st.st[lane] |= 32u;
+                        st.frozen[lane] = 1;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // value at the final points on the last level, then selection
+    prepare_step<NC>(st, ws, Lp, lane);
+    eval_level<NC, false>(Cp, a.tab, a.pinfo, Lp, st.bc, ws, acc, lane);
+    wave_reduce<NC, 1>(acc, ws, st, lane);
+    if (lane < NC) {
+        const int k = wave * NC + lane;
+        const float F = 2.f * st.tot[lane][0];
+        uint32_t s = st.st[lane];
+        if (!isfinite(F)) s |= 1u;
+        fin[wave * NC + lane] = F;
+        fst[wave * NC + lane] = s;
+        if (k < a.Kc)
+            a.cand[(int64_t)p * a.Kc + k] = make_float4((float)st.th[lane][0], (float)st.th[lane][1],
+                                                        (float)st.th[lane][2], F);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int b = 0;
+        for (int k = 1; k < a.Kc; ++k) {
+            const float F = fin[k], Fb = fin[b];
+            if (isfinite(F) && (!isfinite(Fb) || F > Fb)) b = k;
+        }
+        a.best[p] = a.cand[(int64_t)p * a.Kc + b];
+        a.best_idx[p] = b;
+        a.status[p] |= fst[b];
+    }
+}
+
+// Objective, gradient and Hessian at one rotation per particle (one wave per particle).
+__global__ void __launch_bounds__(64) k_evaluate(EvalArgs a)
+{
+    __shared__ WaveScratch<1> ws;
+    __shared__ WaveState<1> st;
+    const int p = blockIdx.x, lane = threadIdx.x;
+    const float4 *Cp = a.C + 0;
+    Cp = a.C + a.C_off[p] / 2;
+    if (lane == 0) {
+        const float4 t = a.theta[p];
+        st.th[0][0] = t.x;
+        st.th[0][1] = t.y;
+        st.th[0][2] = t.z;
+    }
+    __syncthreads();
+    prepare_step<1>(st, ws, a.L, lane);
+    float acc[1][10];
+    eval_level<1, true>(Cp, a.tab, a.pinfo, a.L, st.bc, ws, acc, lane);
+    wave_reduce<1, 10>(acc, ws, st, lane);
+    if (lane < 10) {
+        const float sgn = (lane == 0 || lane == 2 || lane == 7) ? 2.f : -2.f;
+        a.out[(int64_t)p * 10 + lane] = sgn * st.tot[0][lane];
+    }
+}
+
+template <int NC>
+size_t march_smem_bytes(int G)
+{
+    return (size_t)G * (sizeof(WaveScratch<NC>) + sizeof(WaveState<NC>)) + (size_t)G * NC * 8;
+}
+
+template <int NC>
+hipError_t launch_march(const MarchArgs &a, int P, hipStream_t s)
+{
+    const int G = (a.Kc + NC - 1) / NC;
+    const size_t sm = march_smem_bytes<NC>(G);
+    hipLaunchKernelGGL(k_march<NC>, dim3(P), dim3(G * kWave), sm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_march_any(const MarchArgs &a, int P, int nc, hipStream_t s)
+{
+    switch (nc) {
+    case 1: return launch_march<1>(a, P, s);
+    case 2: return launch_march<2>(a, P, s);
+    case 4: return launch_march<4>(a, P, s);
+    case 8: return launch_march<8>(a, P, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+size_t march_smem_any(int Kc, int nc)
+{
+    switch (nc) {
+    case 1: return march_smem_bytes<1>((Kc + 0) / 1);
+    case 2: return march_smem_bytes<2>((Kc + 1) / 2);
+    case 4: return march_smem_bytes<4>((Kc + 3) / 4);
+    case 8: return march_smem_bytes<8>((Kc + 7) / 8);
+    default: return 0;
+    }
+}
+
+hipError_t launch_evaluate(const EvalArgs &a, int P, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_evaluate, dim3(P), dim3(kWave), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace matcha

@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports what include/matcha.h declares (no GPU needed)."""
+import ctypes as ct
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "matcha.h")
+
+
+def _lib():
+    from paper_2603_15285_amd import matcha as M
+    if not os.path.exists(M.LIB_PATH):
+        from paper_2603_15285_amd import build
+        build.build()
+    return M, M.lib()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(matcha_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for f in ["matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton", "matcha_grad_template"]:
+        assert f in names
+
+
+def test_every_declared_symbol_is_exported():
+    M, L = _lib()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+    assert sorted(M.EXPORTED) == declared_functions()
+
+
+def test_sizes_are_closed_forms():
+    M, L = _lib()
+    for Lb in range(0, 65):
+        # two complex values per (l, wedge pair), sum_{l<=L} (l+1)^2 pairs
+        assert M.c_elems(Lb) == 2 * sum((l + 1) ** 2 for l in range(Lb + 1))
+        assert M.c_elems(Lb) % 2 == 0
+    assert M.c_elems(-1) == -1 and M.c_elems(65) == -1
+    assert M.f_elems(32, 32) == 32 * 33 * 33
+
+
+def test_status_strings_and_null_context_rejected():
+    M, L = _lib()
+    for code in (0, -1, -2, -3, -4):
+        assert len(L.matcha_status_string(code)) > 0
+    assert L.matcha_create(0, None) == M.ERR_INVALID_ARG
+    assert L.matcha_destroy(None) == M.ERR_INVALID_ARG
+    assert L.matcha_prepare(None, 8, 4, 16) == M.ERR_INVALID_ARG
+    assert L.matcha_soft_search(None, None, None, None, None, None, None) == M.ERR_INVALID_ARG
+    assert L.matcha_march_newton(None, None, None, None, 4, None, None, None, None, None) == M.ERR_INVALID_ARG
+
+
+def test_wedge_layout_covers_the_half_plane_once():
+    """The wedge pairs and their partners cover {m > 0} U {m = 0, n >= 0} exactly once
+    (diagonal pairs are their own partners)."""
+    from paper_2603_15285_amd import matcha as M
+    for Lb in [0, 1, 5, 12]:
+        l, m, n, pm, pn = M.wedge_index(Lb)
+        assert l.size == M.c_elems(Lb) // 2
+        for lv in range(Lb + 1):
+            sel = l == lv
+            seen = set()
+            for a, b_, c, d in zip(m[sel], n[sel], pm[sel], pn[sel]):
+                seen.add((int(a), int(b_)))
+                seen.add((int(c), int(d)))
+            half = {(a, b_) for a in range(-lv, lv + 1) for b_ in range(-lv, lv + 1) if a > 0 or (a == 0 and b_ >= 0)}
+            assert seen == half

@@ -93,37 +93,46 @@ def main():
     f = torch.from_numpy(b.f_flat.astype(np.complex64).view(np.float32)).cuda()
     h = torch.from_numpy(b.h.astype(np.complex64).view(np.float32).reshape(-1)).cuda()
     w = torch.from_numpy(b.w.astype(np.float32)).cuda()
-    bufs = {}
     stream = torch.cuda.current_stream()
+    if int(b.L.max()) != int(b.L.min()):
+        batch.set_lpt_order(wl.levels, wl.steps)
+    fp64_above = 40 if int(b.L.max()) > 40 else 0
 
-    def step(ev=None):
-        C = M.coeff_assemble(ctx, batch, f, h, w, C=bufs.get("C"))
-        cand, status = M.soft_search(ctx, batch, C, wl.B, wl.n_grid, wl.Kc, cand=bufs.get("cand"),
-                                     status=bufs.get("status"))
-        if ev is not None:
-            ev[0].record(stream)
-        best, bi, status = M.march_newton(ctx, batch, C, wl.levels, wl.steps, cand, status, best=bufs.get("best"),
-                                          best_idx=bufs.get("best_idx"))
-        if ev is not None:
-            ev[1].record(stream)
-        bufs.update(C=C, cand=cand, status=status, best=best, best_idx=bi)
+    # tune the launch shapes on this batch, then capture the whole path in a HIP graph
+    C0 = M.coeff_assemble(ctx, batch, f, h, w)
+    tuning = M.autotune(ctx, batch, C0, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1, fp64_above=fp64_above)
+    del C0
+    log(f"tuning: {tuning}")
+    graph = M.AlignGraph(ctx, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, fp64_above=fp64_above)
+    bufs = graph.bufs
 
     for _ in range(args.warmup):
-        step()
+        graph.launch()
     torch.cuda.synchronize()
     log("warmup done")
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
     t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t_start.record(stream)
     for k in range(args.steps):
-        step(evs[k])
+        graph.launch()
     t_end.record(stream)
     torch.cuda.synchronize()
     ms_total = t_start.elapsed_time(t_end)
     ms_step = ms_total / args.steps
-    ms_march = float(np.mean([a.elapsed_time(z) for a, z in evs]))
     value = P / (ms_step / 1e3)
+
+    # the march alone, timed with events on the stream its kernel runs on
+    cand0 = bufs["cand"].clone()
+    mev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for k in range(args.steps):
+        M.soft_search(ctx, batch, bufs["C"], wl.B, wl.n_grid, wl.Kc, cand=bufs["cand"], status=bufs["status"])
+        mev[k][0].record(stream)
+        M.march_newton(ctx, batch, bufs["C"], wl.levels, wl.steps, bufs["cand"], bufs["status"], best=bufs["best"],
+                       best_idx=bufs["best_idx"], fp64_above=fp64_above)
+        mev[k][1].record(stream)
+    torch.cuda.synchronize()
+    ms_march = float(np.mean([a.elapsed_time(z) for a, z in mev]))
+    del cand0
     log(f"batched: {ms_step:.3f} ms/step, march {ms_march:.3f} ms, {value:.0f} particles/s")
 
     best = bufs["best"].cpu().numpy().astype(np.float64)
@@ -136,9 +145,11 @@ def main():
         sb = M.Batch.make(b.L[p:p + 1], b.R[p:p + 1], b.L_h, b.R_h, f_offset=[0])
         o, sz = int(b.f_offset[p]), int(b.R[p]) * (int(b.L[p]) + 1) ** 2
         singles.append((sb, f[2 * o: 2 * (o + sz)], {}))
+    plain_tuning = ctx.get_tuning()
+    ctx.set_tuning(0, 0)  # the one-particle path runs the library's default launch shapes
 
     def plain_one(sb, fp, bb):
-        M.align(ctx, sb, fp, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, bufs=bb)
+        M.align(ctx, sb, fp, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, fp64_above=fp64_above, bufs=bb)
 
     for sb, fp, bb in singles[:2]:
         plain_one(sb, fp, bb)
@@ -151,6 +162,27 @@ def main():
     torch.cuda.synchronize()
     plain_value = n_plain / (p0.elapsed_time(p1) / 1e3)
     log(f"plain: {plain_value:.0f} particles/s over {n_plain} particles")
+    ctx.set_tuning(plain_tuning["march_nc"], plain_tuning["soft_threads"])
+
+    # batched with BF16 coefficients on the matrix cores (FP32 accumulation, FP32 march)
+    f16 = f.to(torch.bfloat16)
+    h16 = h.to(torch.bfloat16)
+    g16 = M.AlignGraph(ctx, batch, f16, h16, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, prec=M.BF16_FP32ACC,
+                       fp64_above=fp64_above)
+    g16.launch()
+    torch.cuda.synchronize()
+    q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    q0.record(stream)
+    for k in range(args.steps):
+        g16.launch()
+    q1.record(stream)
+    torch.cuda.synchronize()
+    bf16_value = P / (q0.elapsed_time(q1) / args.steps / 1e3)
+    b16 = g16.bufs["best"].cpu().numpy().astype(np.float64)
+    err16 = S.geodesic_deg(b.R_true(), S.euler_zyz_to_matrix(b16[:, 0], b16[:, 1], b16[:, 2]))
+    d16 = S.geodesic_deg(S.euler_zyz_to_matrix(best[:, 0], best[:, 1], best[:, 2]),
+                         S.euler_zyz_to_matrix(b16[:, 0], b16[:, 1], b16[:, 2]))
+    log(f"batched bf16: {bf16_value:.0f} particles/s")
 
     flops = sum(march_flops_per_particle(wl.levels, int(Lp), wl.steps, wl.Kc) for Lp in b.L)
     achieved = flops / (ms_march / 1e3) / 1e12
@@ -166,6 +198,11 @@ def main():
                      "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": None, "ms_per_launch": ms_march},
         "plain": {"value": plain_value, "unit": "particles/s", "particles": n_plain},
         "batched_over_plain": value / plain_value,
+        "batched_bf16": {"value": bf16_value, "unit": "particles/s", "over_plain": bf16_value / plain_value,
+                         "rot_diff_vs_fp32_deg": {"median": float(np.median(d16)), "p99": float(np.percentile(d16, 99)),
+                                                  "n_over_0.05": int(np.sum(d16 > 0.05))},
+                         "rot_err_vs_truth_deg": {"median": float(np.median(err16)), "p90": float(np.percentile(err16, 90))}},
+        "tuning": tuning,
         "rot_err_vs_truth_deg": {"median": float(np.median(err)), "p90": float(np.percentile(err, 90)),
                                  "max": float(err.max())},
     }

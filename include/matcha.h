@@ -97,6 +97,9 @@ typedef struct {
     const int64_t *f_offset;    /* [P] complex-element offsets of particles in f */
     const int64_t *C_offset;    /* [P] complex-element offsets in C              */
     int32_t L_h, R_h;           /* template extents: h is [R_h][(L_h+1)^2]       */
+    const int32_t *order;       /* [P] nullable: processing order of the particles for the
+                                   march (e.g. longest first from matcha_lpt_order); the
+                                   hardware starts workgroups in this order as slots free up */
 } matcha_batch;
 
 /* SOFFT search (Sec. 2.3): grid of n_grid^3 rotations a_j = 2 pi j/n,
@@ -119,7 +122,17 @@ typedef struct {
     double max_step;
     int32_t early_stop;
     double tol_grad, tol_step, tol_rel;
+    int32_t fp64_above;    /* levels above this degree run the Wigner-d recurrence and its l-sums
+                              in FP64 (FP64 coefficient table); 0 or >= MATCHA_MAX_L: FP32 only */
 } matcha_march_cfg;
+
+/* Launch shapes.  Zero fields mean "library default".  march_nc: candidates per wavefront
+ * of the march kernel (1, 2, 4 or 8; a workgroup holds ceil(Kc / march_nc) <= 8 waves).
+ * soft_threads: threads per SOFFT workgroup (256, 512 or 1024). */
+typedef struct {
+    int32_t march_nc;
+    int32_t soft_threads;
+} matcha_tuning;
 
 /* ---- context ---------------------------------------------------------- */
 /* Creates a context on HIP device `device`.  out receives the handle. */
@@ -130,6 +143,9 @@ matcha_status matcha_destroy(matcha_ctx *ctx);
  * before stream capture).  Synchronous. */
 matcha_status matcha_prepare(matcha_ctx *ctx, int32_t L_max, int32_t B, int32_t n_grid);
 const char *matcha_status_string(matcha_status s);
+/* Sets / reads the launch shapes used by later calls on this context. */
+matcha_status matcha_set_tuning(matcha_ctx *ctx, const matcha_tuning *t);
+matcha_status matcha_get_tuning(const matcha_ctx *ctx, matcha_tuning *t);
 
 /* ---- sizes -------------------------------------------------------------- */
 /* Complex values of one particle's wedge-layout C for band limit L:
@@ -140,6 +156,10 @@ int64_t matcha_f_elems(int32_t L, int32_t R);
 /* Bytes of workspace needed by matcha_soft_search / matcha_march_newton /
  * matcha_grad_template for this batch (0 when none). */
 size_t matcha_workspace_size(const matcha_batch *batch, int32_t Kc);
+
+/* Longest-processing-time order (host): particle indices sorted by decreasing march cost
+ * Kc * steps * sum over the particle's schedule of (L_j+1)(L_j+2)(2L_j+3)/6, ties by index. */
+matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg *cfg, int32_t *order_host);
 
 /* ---- the path ------------------------------------------------------------ */
 /* Coefficient assembly, eq. sigmalmm (Sec. 2.1, App. A.5) with shells in place of
@@ -177,9 +197,9 @@ matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, co
 /* Objective only: value, gradient and Hessian of C_{L_eval} at one rotation per
  * particle.  theta [P] float4 (a, b, c, unused); out [P][10] float:
  * F, F_a, F_b, F_c, F_aa, F_ab, F_ac, F_bb, F_bc, F_cc (Sec. 2.2, App. A.4).
- * L_eval <= L_p for every particle. */
+ * 1 <= L_eval <= L_p for every particle, or L_eval = 0 for each particle's own L_p. */
 matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const float *C, int32_t L_eval,
-                              const float *theta, float *out, void *stream);
+                              int32_t fp64_above, const float *theta, float *out, void *stream);
 
 /* Adjoint of sum_p g_p C_{L_p}(R_p*) at fixed rotations R_p* = best[p]
  * (envelope theorem), as d/dRe + i d/dIm of the full complex arrays:
@@ -192,6 +212,29 @@ matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const 
 matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, const float *f, const float *h,
                                    const float *w, const float *best, const float *g, float *grad_h, float *grad_f,
                                    void *ws, size_t ws_bytes, void *stream);
+
+/* ---- batching: graphs and tuning ------------------------------------------ */
+typedef struct matcha_graph matcha_graph;
+
+/* Records matcha_coeff_assemble + matcha_soft_search + matcha_march_newton for these exact
+ * buffers into a HIP graph (captured on a private stream) and instantiates it.  Later replays
+ * run the whole path with one launch call and read the buffers' contents at replay time.
+ * The context must stay alive; tables are built before capture.  Synchronous. */
+matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
+                                        const float *w, float *C, matcha_precision prec, const matcha_soft_cfg *soft,
+                                        const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
+                                        uint32_t *status, matcha_graph **out);
+/* Replays the graph on `stream` (asynchronous). */
+matcha_status matcha_graph_launch(matcha_graph *g, void *stream);
+matcha_status matcha_graph_destroy(matcha_graph *g);
+
+/* Autotuner: times every supported launch shape of the SOFFT search and of the march on this
+ * batch (hipEvents, `reps` repetitions each, after one warm-up), keeps the fastest in the
+ * context (later calls use it) and returns it in *best_tuning (host).  cand / best / best_idx /
+ * status / C are used as scratch and hold the last trial's (valid) results.  Synchronous. */
+matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *soft,
+                              const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
+                              uint32_t *status, int32_t reps, matcha_tuning *best_tuning);
 
 #ifdef __cplusplus
 }

@@ -53,42 +53,42 @@ __device__ inline void fill_phases(double a, double c, int L, float2 *ea, float2
     }
 }
 
-// One recurrence row for NC candidates.  On entry X = D^{l-1}, Y = D^{l-2} (X1, Y1: first
-// b-derivative; X2, Y2: half the second b-derivative); on exit Y holds row l.  tb = (A, AC, PW,
-// PWT) of row l, cc = (C^l_pair, C^l_partner).  U[c] accumulates sum_l C^l PW_l D^l for the pair
-// (0, 1) and C^l PWT_l D^l for the partner (2, 3), then the same for D' (4..7) and D''/2 (8..11).
-// With u = A cos b - AC, v = A sin b, h = A cos b / 2 the differentiated relations read
+// One recurrence row for NC candidates in arithmetic T (float, or double above the FP64
+// threshold).  On entry X = D^{l-1}, Y = D^{l-2} (X1, Y1: first b-derivative; X2, Y2: half the
+// second b-derivative); on exit Y holds row l.  (A, AC) are the row's recurrence coefficients,
+// (PW, PWT) = (tb.z, tb.w) its weights, cc = (C^l_pair, C^l_partner).  U[c] accumulates
+// sum_l C^l PW_l D^l for the pair (0, 1) and C^l PWT_l D^l for the partner (2, 3), then the same
+// for D' (4..7) and D''/2 (8..11).  With u = A cos b - AC, v = A sin b, h = A cos b / 2:
 //   D'^l = u D'^{l-1} - v D^{l-1} - D'^{l-2},  (D''/2)^l = u (D''/2)^{l-1} - v D'^{l-1} - h D^{l-1} - (D''/2)^{l-2}.
-template <int NC, bool DERIV>
-__device__ __forceinline__ void row_step(const float4 tb, const float4 cc, const float *cbv, const float *sbv,
-                                         const float *chv, float (&X)[NC], float (&Y)[NC], float (&X1)[NC],
-                                         float (&Y1)[NC], float (&X2)[NC], float (&Y2)[NC],
-                                         float (&U)[NC][DERIV ? 12 : 4])
+template <int NC, bool DERIV, typename T>
+__device__ __forceinline__ void row_step(const T A, const T AC, const float4 tb, const float4 cc, const T *cbv,
+                                         const T *sbv, const T *chv, T (&X)[NC], T (&Y)[NC], T (&X1)[NC],
+                                         T (&Y1)[NC], T (&X2)[NC], T (&Y2)[NC], T (&U)[NC][DERIV ? 12 : 4])
 {
-    const float s0r = cc.x * tb.z, s0i = cc.y * tb.z, s1r = cc.z * tb.w, s1i = cc.w * tb.w;
+    const T s0r = (T)(cc.x * tb.z), s0i = (T)(cc.y * tb.z), s1r = (T)(cc.z * tb.w), s1i = (T)(cc.w * tb.w);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        const float u = fmaf(tb.x, cbv[c], -tb.y);
-        const float dn = fmaf(u, X[c], -Y[c]);
-        U[c][0] = fmaf(s0r, dn, U[c][0]);
-        U[c][1] = fmaf(s0i, dn, U[c][1]);
-        U[c][2] = fmaf(s1r, dn, U[c][2]);
-        U[c][3] = fmaf(s1i, dn, U[c][3]);
+        const T u = fma(A, cbv[c], -AC);
+        const T dn = fma(u, X[c], -Y[c]);
+        U[c][0] = fma(s0r, dn, U[c][0]);
+        U[c][1] = fma(s0i, dn, U[c][1]);
+        U[c][2] = fma(s1r, dn, U[c][2]);
+        U[c][3] = fma(s1i, dn, U[c][3]);
         if (DERIV) {
-            const float v = tb.x * sbv[c];
-            const float h = tb.x * chv[c];
-            const float d1n = fmaf(u, X1[c], fmaf(-v, X[c], -Y1[c]));
-            const float d2n = fmaf(u, X2[c], fmaf(-v, X1[c], fmaf(-h, X[c], -Y2[c])));
+            const T v = A * sbv[c];
+            const T h = A * chv[c];
+            const T d1n = fma(u, X1[c], fma(-v, X[c], -Y1[c]));
+            const T d2n = fma(u, X2[c], fma(-v, X1[c], fma(-h, X[c], -Y2[c])));
             Y1[c] = d1n;
             Y2[c] = d2n;
-            U[c][4] = fmaf(s0r, d1n, U[c][4]);
-            U[c][5] = fmaf(s0i, d1n, U[c][5]);
-            U[c][6] = fmaf(s1r, d1n, U[c][6]);
-            U[c][7] = fmaf(s1i, d1n, U[c][7]);
-            U[c][8] = fmaf(s0r, d2n, U[c][8]);
-            U[c][9] = fmaf(s0i, d2n, U[c][9]);
-            U[c][10] = fmaf(s1r, d2n, U[c][10]);
-            U[c][11] = fmaf(s1i, d2n, U[c][11]);
+            U[c][4] = fma(s0r, d1n, U[c][4]);
+            U[c][5] = fma(s0i, d1n, U[c][5]);
+            U[c][6] = fma(s1r, d1n, U[c][6]);
+            U[c][7] = fma(s1i, d1n, U[c][7]);
+            U[c][8] = fma(s0r, d2n, U[c][8]);
+            U[c][9] = fma(s0i, d2n, U[c][9]);
+            U[c][10] = fma(s1r, d2n, U[c][10]);
+            U[c][11] = fma(s1i, d2n, U[c][11]);
         }
         Y[c] = dn;
     }
@@ -100,23 +100,77 @@ __device__ __forceinline__ float4 ld_row(const float4 *base, int row, uint32_t l
     return *reinterpret_cast<const float4 *>(p + lane_bytes);
 }
 
-// Sum over all wedge pairs of one level for NC candidates.  acc[c][0..9] receive the
-// (positive-sign, undoubled) sums described at the top of the file; with DERIV == false
-// only acc[c][0] (the value) is formed.
-template <int NC, bool DERIV>
+__device__ __forceinline__ double2 ld_row(const double2 *base, int row, uint32_t lane_bytes)
+{
+    const char *p = reinterpret_cast<const char *>(base + row);
+    return *reinterpret_cast<const double2 *>(p + lane_bytes);
+}
+
+// Recurrence coefficients of a row in arithmetic T: the FP32 table, or the FP64 table for the
+// double recurrence.
+template <typename T>
+struct Coef;
+template <>
+struct Coef<float> {
+    __device__ static void get(const float4 tb, const double2 *, int, uint32_t, float &A, float &AC)
+    {
+        A = tb.x;
+        AC = tb.y;
+    }
+};
+template <>
+struct Coef<double> {
+    __device__ static void get(const float4, const double2 *t64, int row, uint32_t lb, double &A, double &AC)
+    {
+        const double2 c = ld_row(t64, row, 2 * lb);
+        A = c.x;
+        AC = c.y;
+    }
+};
+
+template <typename T>
+__device__ inline void seed_T(int m, int n, double lbh2, const BetaConst &k, T &d0, T &d1, T &d2);
+template <>
+__device__ inline void seed_T<float>(int m, int n, double lbh2, const BetaConst &k, float &d0, float &d1, float &d2)
+{
+    edge_seed(m, n, lbh2, k, d0, d1, d2);
+}
+template <>
+__device__ inline void seed_T<double>(int m, int n, double lbh2, const BetaConst &k, double &d0, double &d1, double &d2)
+{
+    edge_seed_d(m, n, lbh2, k, d0, d1, d2);
+}
+
+template <typename T>
+__device__ inline T bcastT(T x);
+template <>
+__device__ inline float bcastT<float>(float x) { return bcast(x); }
+template <>
+__device__ inline double bcastT<double>(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll)), hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over all wedge pairs of one level for the NC candidates c0 .. c0+NC-1 of a wave that owns
+// NCW.  acc[c0+c][0..9] receive the (positive-sign, undoubled) sums described at the top of the
+// file; with DERIV == false only acc[.][0] (the value) is formed.  T is the arithmetic of the
+// recurrence and the l-sums.
+template <int NC, int NCW, bool DERIV, typename T>
 __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restrict__ tab,
-                           const PairInfo *__restrict__ pinfo, int L, const BetaConst *bc, const WaveScratch<NC> &ws,
-                           float (&acc)[NC][10], int lane)
+                           const double2 *__restrict__ tab64, const PairInfo *__restrict__ pinfo, int L,
+                           const BetaConst *bc, const WaveScratch<NCW> &ws, float (&acc)[NCW][10], int c0, int lane)
 {
     constexpr int NU = DERIV ? 12 : 4;
-    float cbv[NC], sbv[NC], chv[NC];
+    T cbv[NC], sbv[NC], chv[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        cbv[c] = bcast(bc[c].cb);
-        sbv[c] = bcast(bc[c].sb);
-        chv[c] = 0.5f * cbv[c];
+        cbv[c] = bcastT<T>((T)bc[c0 + c].cbd);
+        sbv[c] = bcastT<T>((T)bc[c0 + c].sbd);
+        chv[c] = (T)0.5 * cbv[c];
 #pragma unroll
-        for (int v = 0; v < 10; ++v) acc[c][v] = 0.f;
+        for (int v = 0; v < 10; ++v) acc[c0 + c][v] = 0.f;
     }
     const int npairs = (L + 1) * (L + 1);
     const int ntiles = (npairs + kWave - 1) / kWave;
@@ -125,59 +179,94 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         const int q = q0 + lane;
         const bool valid = q < npairs;
         const int qe = valid ? q : npairs - 1;
+        const uint32_t lb = (uint32_t)qe * 16u;
         const PairInfo pi = pinfo[qe];
         const int m = pi.m, n = pi.n;
-        const int mlo = isqrt_dev(q0);
-        const int mhi = isqrt_dev(min(q0 + kWave - 1, npairs - 1));
+        // lane 0 holds the tile's smallest m, the last valid lane its largest
+        const int mlo = __builtin_amdgcn_readfirstlane(m);
+        const int mhi = __shfl(m, min(npairs - 1 - q0, kWave - 1));
 
-        float D[NC], Dm[NC], D1[NC], D1m[NC], D2[NC], D2m[NC];
-        float U[NC][NU];
+        // edge values of every lane's pair, computed once per tile without divergence
+        T sd0[NC], sd1[NC], sd2[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            D[c] = Dm[c] = D1[c] = D1m[c] = D2[c] = D2m[c] = 0.f;
-#pragma unroll
-            for (int v = 0; v < NU; ++v) U[c][v] = 0.f;
+            seed_T<T>(m, n, pi.lbh2, bc[c0 + c], sd0[c], sd1[c], sd2[c]);
+            sd2[c] *= (T)0.5;
         }
 
-        // rows where some lanes of the tile are still before their edge l = m
+        // first row l = mlo: only lanes with m == mlo start; everything else is zero
+        T D[NC], Dm[NC], D1[NC], D1m[NC], D2[NC], D2m[NC];
+        T U[NC][NU];
         int row = (int)wedge_row(mlo);
-        for (int l = mlo; l <= mhi; ++l) {
-            const bool act = valid && m <= l;
+        {
+            const bool act = valid && m == mlo;
             float4 tb = make_float4(0.f, 0.f, 0.f, 0.f), cc = tb;
             if (act) {
                 tb = tab[row + q];
                 cc = Cp[row + q];
             }
+            row += (mlo + 1) * (mlo + 1);
+            const T s0r = (T)(cc.x * tb.z), s0i = (T)(cc.y * tb.z), s1r = (T)(cc.z * tb.w), s1i = (T)(cc.w * tb.w);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                D[c] = act ? sd0[c] : (T)0;
+                D1[c] = act ? sd1[c] : (T)0;
+                D2[c] = act ? sd2[c] : (T)0;
+                Dm[c] = D1m[c] = D2m[c] = (T)0;
+                U[c][0] = s0r * D[c];
+                U[c][1] = s0i * D[c];
+                U[c][2] = s1r * D[c];
+                U[c][3] = s1i * D[c];
+                if (DERIV) {
+                    U[c][4] = s0r * D1[c];
+                    U[c][5] = s0i * D1[c];
+                    U[c][6] = s1r * D1[c];
+                    U[c][7] = s1i * D1[c];
+                    U[c][8] = s0r * D2[c];
+                    U[c][9] = s0i * D2[c];
+                    U[c][10] = s1r * D2[c];
+                    U[c][11] = s1i * D2[c];
+                }
+            }
+        }
+        // rows where some lanes of the tile are still before their edge l = m
+        for (int l = mlo + 1; l <= mhi; ++l) {
+            const bool act = valid && m <= l;
+            float4 tb = make_float4(0.f, 0.f, 0.f, 0.f), cc = tb;
+            T A = (T)0, AC = (T)0;
+            if (act) {
+                tb = tab[row + q];
+                cc = Cp[row + q];
+                Coef<T>::get(tb, tab64, row, (uint32_t)q * 16u, A, AC);
+            }
             row += (l + 1) * (l + 1);
-            const float s0r = cc.x * tb.z, s0i = cc.y * tb.z, s1r = cc.z * tb.w, s1i = cc.w * tb.w;
+            const T s0r = (T)(cc.x * tb.z), s0i = (T)(cc.y * tb.z), s1r = (T)(cc.z * tb.w), s1i = (T)(cc.w * tb.w);
             const bool seed = (m == l);
 #pragma unroll
             for (int c = 0; c < NC; ++c) {
-                float sd0 = 0.f, sd1 = 0.f, sd2 = 0.f;
-                if (seed) edge_seed(m, n, pi.lbh2, bc[c], sd0, sd1, sd2);
-                const float u = fmaf(tb.x, cbv[c], -tb.y);
-                float dn = seed ? sd0 : fmaf(u, D[c], -Dm[c]);
-                U[c][0] = fmaf(s0r, dn, U[c][0]);
-                U[c][1] = fmaf(s0i, dn, U[c][1]);
-                U[c][2] = fmaf(s1r, dn, U[c][2]);
-                U[c][3] = fmaf(s1i, dn, U[c][3]);
+                const T u = fma(A, cbv[c], -AC);
+                const T dn = seed ? sd0[c] : fma(u, D[c], -Dm[c]);
+                U[c][0] = fma(s0r, dn, U[c][0]);
+                U[c][1] = fma(s0i, dn, U[c][1]);
+                U[c][2] = fma(s1r, dn, U[c][2]);
+                U[c][3] = fma(s1i, dn, U[c][3]);
                 if (DERIV) {
-                    const float v = tb.x * sbv[c];
-                    const float h = tb.x * chv[c];
-                    float d1n = seed ? sd1 : fmaf(u, D1[c], fmaf(-v, D[c], -D1m[c]));
-                    float d2n = seed ? 0.5f * sd2 : fmaf(u, D2[c], fmaf(-v, D1[c], fmaf(-h, D[c], -D2m[c])));
+                    const T v = A * sbv[c];
+                    const T h = A * chv[c];
+                    const T d1n = seed ? sd1[c] : fma(u, D1[c], fma(-v, D[c], -D1m[c]));
+                    const T d2n = seed ? sd2[c] : fma(u, D2[c], fma(-v, D1[c], fma(-h, D[c], -D2m[c])));
                     D1m[c] = D1[c];
                     D1[c] = d1n;
                     D2m[c] = D2[c];
                     D2[c] = d2n;
-                    U[c][4] = fmaf(s0r, d1n, U[c][4]);
-                    U[c][5] = fmaf(s0i, d1n, U[c][5]);
-                    U[c][6] = fmaf(s1r, d1n, U[c][6]);
-                    U[c][7] = fmaf(s1i, d1n, U[c][7]);
-                    U[c][8] = fmaf(s0r, d2n, U[c][8]);
-                    U[c][9] = fmaf(s0i, d2n, U[c][9]);
-                    U[c][10] = fmaf(s1r, d2n, U[c][10]);
-                    U[c][11] = fmaf(s1i, d2n, U[c][11]);
+                    U[c][4] = fma(s0r, d1n, U[c][4]);
+                    U[c][5] = fma(s0i, d1n, U[c][5]);
+                    U[c][6] = fma(s1r, d1n, U[c][6]);
+                    U[c][7] = fma(s1i, d1n, U[c][7]);
+                    U[c][8] = fma(s0r, d2n, U[c][8]);
+                    U[c][9] = fma(s0i, d2n, U[c][9]);
+                    U[c][10] = fma(s1r, d2n, U[c][10]);
+                    U[c][11] = fma(s1i, d2n, U[c][11]);
                 }
                 Dm[c] = D[c];
                 D[c] = dn;
@@ -187,28 +276,32 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         // ping-pongs between (D, Dm) and the next rows' loads are in flight meanwhile.  Loads
         // past row L re-read row L (never used), so they need no branch.
         {
-            const uint32_t lb = (uint32_t)qe * 16u;
             const int rowL = (int)wedge_row(L);
             int l = mhi + 1;
             int r0 = min(row, rowL);
             float4 tb0 = ld_row(tab, r0, lb), cc0 = ld_row(Cp, r0, lb);
+            T A0, AC0, A1, AC1;
+            Coef<T>::get(tb0, tab64, r0, lb, A0, AC0);
             row += (l + 1) * (l + 1);
             int r1 = min(row, rowL);
             float4 tb1 = ld_row(tab, r1, lb), cc1 = ld_row(Cp, r1, lb);
+            Coef<T>::get(tb1, tab64, r1, lb, A1, AC1);
             row += (l + 2) * (l + 2);
             for (; l + 1 <= L; l += 2) {
-                row_step<NC, DERIV>(tb0, cc0, cbv, sbv, chv, D, Dm, D1, D1m, D2, D2m, U);
+                row_step<NC, DERIV, T>(A0, AC0, tb0, cc0, cbv, sbv, chv, D, Dm, D1, D1m, D2, D2m, U);
                 r0 = min(row, rowL);
                 tb0 = ld_row(tab, r0, lb);
                 cc0 = ld_row(Cp, r0, lb);
+                Coef<T>::get(tb0, tab64, r0, lb, A0, AC0);
                 row += (l + 3) * (l + 3);
-                row_step<NC, DERIV>(tb1, cc1, cbv, sbv, chv, Dm, D, D1m, D1, D2m, D2, U);
+                row_step<NC, DERIV, T>(A1, AC1, tb1, cc1, cbv, sbv, chv, Dm, D, D1m, D1, D2m, D2, U);
                 r1 = min(row, rowL);
                 tb1 = ld_row(tab, r1, lb);
                 cc1 = ld_row(Cp, r1, lb);
+                Coef<T>::get(tb1, tab64, r1, lb, A1, AC1);
                 row += (l + 4) * (l + 4);
             }
-            if (l <= L) row_step<NC, DERIV>(tb0, cc0, cbv, sbv, chv, D, Dm, D1, D1m, D2, D2m, U);
+            if (l <= L) row_step<NC, DERIV, T>(A0, AC0, tb0, cc0, cbv, sbv, chv, D, Dm, D1, D1m, D2, D2m, U);
         }
         if (!valid) continue;
         // phases and the m, n weights of the a / c derivatives
@@ -217,37 +310,57 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         const float a2 = n >= 0 ? (float)n : (float)(-n), b2 = n >= 0 ? (float)m : (float)(-m);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const float2 am = ws.ph.ea[c][m], aN = ws.ph.ea[c][an];
-            float2 gm = ws.ph.eg[c][m], gN = ws.ph.eg[c][an];
+            const int cw = c0 + c;
+            const float2 am = ws.ph.ea[cw][m], aN = ws.ph.ea[cw][an];
+            float2 gm = ws.ph.eg[cw][m], gN = ws.ph.eg[cw][an];
             if (n < 0) {
                 gN = cconj(gN);
                 gm = cconj(gm);
             }
             const float2 p1 = cmul(am, gN);  // e^{i(m a + n c)}
             const float2 p2 = cmul(aN, gm);  // e^{i(a2 a + b2 c)}
-            const float R0 = p1.x * U[c][0] - p1.y * U[c][1];
-            const float T0 = p2.x * U[c][2] - p2.y * U[c][3];
-            acc[c][0] += R0 + T0;
+            float u[NU];
+#pragma unroll
+            for (int v = 0; v < NU; ++v) u[v] = (float)U[c][v];
+            const float R0 = p1.x * u[0] - p1.y * u[1];
+            const float T0 = p2.x * u[2] - p2.y * u[3];
+            acc[cw][0] += R0 + T0;
             if (DERIV) {
-                const float I0 = p1.x * U[c][1] + p1.y * U[c][0];
-                const float J0 = p2.x * U[c][3] + p2.y * U[c][2];
-                const float R1 = p1.x * U[c][4] - p1.y * U[c][5];
-                const float I1 = p1.x * U[c][5] + p1.y * U[c][4];
-                const float T1 = p2.x * U[c][6] - p2.y * U[c][7];
-                const float J1 = p2.x * U[c][7] + p2.y * U[c][6];
-                const float R2 = 2.f * (p1.x * U[c][8] - p1.y * U[c][9]);
-                const float T2 = 2.f * (p2.x * U[c][10] - p2.y * U[c][11]);
-                acc[c][1] += a1 * I0 + a2 * J0;
-                acc[c][2] += R1 + T1;
-                acc[c][3] += b1 * I0 + b2 * J0;
-                acc[c][4] += a1 * a1 * R0 + a2 * a2 * T0;
-                acc[c][5] += a1 * I1 + a2 * J1;
-                acc[c][6] += a1 * b1 * R0 + a2 * b2 * T0;
-                acc[c][7] += R2 + T2;
-                acc[c][8] += b1 * I1 + b2 * J1;
-                acc[c][9] += b1 * b1 * R0 + b2 * b2 * T0;
+                const float I0 = p1.x * u[1] + p1.y * u[0];
+                const float J0 = p2.x * u[3] + p2.y * u[2];
+                const float R1 = p1.x * u[4] - p1.y * u[5];
+                const float I1 = p1.x * u[5] + p1.y * u[4];
+                const float T1 = p2.x * u[6] - p2.y * u[7];
+                const float J1 = p2.x * u[7] + p2.y * u[6];
+                const float R2 = 2.f * (p1.x * u[8] - p1.y * u[9]);
+                const float T2 = 2.f * (p2.x * u[10] - p2.y * u[11]);
+                acc[cw][1] += a1 * I0 + a2 * J0;
+                acc[cw][2] += R1 + T1;
+                acc[cw][3] += b1 * I0 + b2 * J0;
+                acc[cw][4] += a1 * a1 * R0 + a2 * a2 * T0;
+                acc[cw][5] += a1 * I1 + a2 * J1;
+                acc[cw][6] += a1 * b1 * R0 + a2 * b2 * T0;
+                acc[cw][7] += R2 + T2;
+                acc[cw][8] += b1 * I1 + b2 * J1;
+                acc[cw][9] += b1 * b1 * R0 + b2 * b2 * T0;
             }
         }
+    }
+}
+
+// A whole level for the wave's NC candidates: FP32 recurrence at or below the FP64 threshold,
+// FP64 recurrence (two candidates per pass, to bound registers) above it.
+template <int NC, bool DERIV>
+__device__ void eval_level_any(const float4 *Cp, const float4 *tab, const double2 *tab64, const PairInfo *pinfo,
+                               int L, int fp64_above, const BetaConst *bc, const WaveScratch<NC> &ws,
+                               float (&acc)[NC][10], int lane)
+{
+    if (L <= fp64_above || tab64 == nullptr) {
+        eval_level<NC, NC, DERIV, float>(Cp, tab, tab64, pinfo, L, bc, ws, acc, 0, lane);
+    } else {
+        constexpr int H = NC < 2 ? NC : 2;
+#pragma unroll
+        for (int c0 = 0; c0 < NC; c0 += H) eval_level<H, NC, DERIV, double>(Cp, tab, tab64, pinfo, L, bc, ws, acc, c0, lane);
     }
 }
 
@@ -339,10 +452,10 @@ __device__ void prepare_step(WaveState<NC> &st, WaveScratch<NC> &ws, int L, int 
 }
 
 template <int NC>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 3 : 2, 8))) k_march(MarchArgs a)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))) k_march(MarchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int p = blockIdx.x;
+    const int p = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int G = blockDim.x / kWave;
     WaveScratch<NC> &ws = reinterpret_cast<WaveScratch<NC> *>(smem)[wave];
@@ -373,7 +486,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NC <= 
         if (lane < NC) st.frozen[lane] = 0;
         for (int s = 0; s < a.steps; ++s) {
             prepare_step<NC>(st, ws, L, lane);
-            eval_level<NC, true>(Cp, a.tab, a.pinfo, L, st.bc, ws, acc, lane);
+            eval_level_any<NC, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
             wave_reduce<NC, 10>(acc, ws, st, lane);
             if (lane < NC && !st.frozen[lane]) {
                 double e[10];
@@ -413,7 +526,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(NC <= 
     }
     // value at the final points on the last level, then selection
     prepare_step<NC>(st, ws, Lp, lane);
-    eval_level<NC, false>(Cp, a.tab, a.pinfo, Lp, st.bc, ws, acc, lane);
+    eval_level_any<NC, false>(Cp, a.tab, a.tab64, a.pinfo, Lp, a.fp64_above, st.bc, ws, acc, lane);
     wave_reduce<NC, 1>(acc, ws, st, lane);
     if (lane < NC) {
         const int k = wave * NC + lane;
@@ -445,8 +558,8 @@ __global__ void __launch_bounds__(64) k_evaluate(EvalArgs a)
     __shared__ WaveScratch<1> ws;
     __shared__ WaveState<1> st;
     const int p = blockIdx.x, lane = threadIdx.x;
-    const float4 *Cp = a.C + 0;
-    Cp = a.C + a.C_off[p] / 2;
+    const float4 *Cp = a.C + a.C_off[p] / 2;
+    const int L = a.L > 0 ? a.L : a.Lp[p];
     if (lane == 0) {
         const float4 t = a.theta[p];
         st.th[0][0] = t.x;
@@ -454,9 +567,9 @@ __global__ void __launch_bounds__(64) k_evaluate(EvalArgs a)
         st.th[0][2] = t.z;
     }
     __syncthreads();
-    prepare_step<1>(st, ws, a.L, lane);
+    prepare_step<1>(st, ws, L, lane);
     float acc[1][10];
-    eval_level<1, true>(Cp, a.tab, a.pinfo, a.L, st.bc, ws, acc, lane);
+    eval_level_any<1, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
     wave_reduce<1, 10>(acc, ws, st, lane);
     if (lane < 10) {
         const float sgn = (lane == 0 || lane == 2 || lane == 7) ? 2.f : -2.f;

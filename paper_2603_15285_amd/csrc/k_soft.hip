@@ -13,7 +13,6 @@
 
 namespace matcha {
 
-constexpr int kSoftThreads = 256;
 constexpr int kListCap = 1024;
 
 
@@ -25,8 +24,13 @@ struct SoftSmem {
     int *nmax;
     float2 *S;                 // [(B+1)(2B+1)]
     float2 *T;                 // [(B+1) n]
-    float2 *tw;                // [n]
-    float *ring[3];            // [n*n] each
+    float2 *tw;                // [n]          e^{2 pi i t / n}
+    float2 *E;                 // [(B+1) n]    e^{i m a_j}
+    float *ring0;              // 3 x [n*n]    grid values of three consecutive slices
+    float *mx90;               // 3 x [n*n]    3x3 in-plane maximum (centre included)
+    int plane;                 // floats per slice slot (n*n rounded to 16 bytes)
+    __device__ float *ring(int s) const { return ring0 + s * plane; }
+    __device__ float *mx9(int s) const { return mx90 + s * plane; }
 };
 
 __host__ __device__ inline size_t soft_align16(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -37,7 +41,8 @@ __host__ __device__ inline size_t soft_smem_size(int n, int B)
     o += soft_align16(sizeof(float2) * (B + 1) * (2 * B + 1));
     o += soft_align16(sizeof(float2) * (B + 1) * n);
     o += soft_align16(sizeof(float2) * n);
-    o += 3 * soft_align16(sizeof(float) * n * n);
+    o += soft_align16(sizeof(float2) * (B + 1) * n);
+    o += 6 * soft_align16(sizeof(float) * n * n);
     return o;
 }
 
@@ -52,10 +57,12 @@ __device__ inline void soft_bind(SoftSmem &sm, unsigned char *base, int n, int B
     o += soft_align16(sizeof(float2) * (B + 1) * n);
     sm.tw = reinterpret_cast<float2 *>(base + o);
     o += soft_align16(sizeof(float2) * n);
-    for (int r = 0; r < 3; ++r) {
-        sm.ring[r] = reinterpret_cast<float *>(base + o);
-        o += soft_align16(sizeof(float) * n * n);
-    }
+    sm.E = reinterpret_cast<float2 *>(base + o);
+    o += soft_align16(sizeof(float2) * (B + 1) * n);
+    sm.plane = (int)(soft_align16(sizeof(float) * n * n) / sizeof(float));
+    sm.ring0 = reinterpret_cast<float *>(base + o);
+    o += 3 * soft_align16(sizeof(float) * n * n);
+    sm.mx90 = reinterpret_cast<float *>(base + o);
 }
 
 __device__ inline unsigned long long make_key(float v, uint32_t idx)
@@ -64,11 +71,12 @@ __device__ inline unsigned long long make_key(float v, uint32_t idx)
 }
 
 // Bitonic sort of sm.list[0..kListCap) in descending key order (empty slots hold 0).
+template <int NT>
 __device__ void sort_list_desc(SoftSmem &sm)
 {
     for (int k = 2; k <= kListCap; k <<= 1) {
         for (int j = k >> 1; j > 0; j >>= 1) {
-            for (int i = threadIdx.x; i < kListCap; i += kSoftThreads) {
+            for (int i = threadIdx.x; i < kListCap; i += NT) {
                 const int ixj = i ^ j;
                 if (ixj > i) {
                     const unsigned long long a = sm.list[i], b = sm.list[ixj];
@@ -85,12 +93,13 @@ __device__ void sort_list_desc(SoftSmem &sm)
 }
 
 // Keep the Kc largest keys; everything at or below the Kc-th key can never be ranked.
+template <int NT>
 __device__ void compact_list(SoftSmem &sm, int Kc)
 {
     __syncthreads();
-    for (int i = (*sm.count) + threadIdx.x; i < kListCap; i += kSoftThreads) sm.list[i] = 0ull;
+    for (int i = (*sm.count) + threadIdx.x; i < kListCap; i += NT) sm.list[i] = 0ull;
     __syncthreads();
-    sort_list_desc(sm);
+    sort_list_desc<NT>(sm);
     if (threadIdx.x == 0) {
         const int keep = min((*sm.count), Kc);
         (*sm.count) = keep;
@@ -99,37 +108,32 @@ __device__ void compact_list(SoftSmem &sm, int Kc)
     __syncthreads();
 }
 
-// Wigner-d transform of one polar node into the half-plane array S[(m)(2B+1) + n + B].
-__device__ void wigner_slice(const SoftArgs &a, const float4 *Cp, SoftSmem &sm, double b)
+// Wigner-d transform of polar node i into the half-plane array S[m (2B+1) + n + B]:
+// S[pair] = sum_l C^l_pair dg0^l_pair(b_i), S[partner] = sum_l C^l_partner dg1^l_pair(b_i), with
+// the node's d values (weights folded in) read from the table shared by all particles.
+// Entries (0, n < 0) are never written and stay zero.
+template <int NT>
+__device__ void wigner_slice(const SoftArgs &a, const float4 *Cp, SoftSmem &sm, int i)
 {
     const int B = a.B, W = 2 * B + 1;
-    for (int i = threadIdx.x; i < (B + 1) * W; i += kSoftThreads) sm.S[i] = make_float2(0.f, 0.f);
-    __syncthreads();
-    const BetaConst bc = beta_const(b);
     const int npairs = (B + 1) * (B + 1);
-    for (int q = threadIdx.x; q < npairs; q += kSoftThreads) {
+    const float2 *dg = a.dgrid + (int64_t)i * wedge_row(B + 1);
+    for (int q = threadIdx.x; q < npairs; q += NT) {
         const PairInfo pi = a.pinfo[q];
         const int m = pi.m, n = pi.n;
-        float s0, s1, s2;
-        edge_seed(m, n, pi.lbh2, bc, s0, s1, s2);
-        float D = 0.f, Dm = 0.f;
         float2 u0 = make_float2(0.f, 0.f), u1 = u0;
-        float pwt = 0.f;
+        int row = (int)wedge_row(m);
         for (int l = m; l <= B; ++l) {
-            const float4 tb = a.tab[wedge_row(l) + q];
-            const float4 cc = Cp[wedge_row(l) + q];
-            float dn = fmaf(tb.x * bc.cb - tb.y, D, -Dm);
-            if (l == m) dn = s0;
-            Dm = D;
-            D = dn;
-            u0.x = fmaf(cc.x * tb.z, dn, u0.x);
-            u0.y = fmaf(cc.y * tb.z, dn, u0.y);
-            u1.x = fmaf(cc.z * tb.w, dn, u1.x);
-            u1.y = fmaf(cc.w * tb.w, dn, u1.y);
-            pwt = tb.w;
+            const float2 d = dg[row + q];
+            const float4 cc = Cp[row + q];
+            row += (l + 1) * (l + 1);
+            u0.x = fmaf(cc.x, d.x, u0.x);
+            u0.y = fmaf(cc.y, d.x, u0.y);
+            u1.x = fmaf(cc.z, d.y, u1.x);
+            u1.y = fmaf(cc.w, d.y, u1.y);
         }
         sm.S[m * W + n + B] = u0;
-        if (pwt != 0.f) {  // not a diagonal pair: the partner is a distinct entry
+        if (n != m && n != -m) {  // diagonal pairs are their own partners
             const int a2 = n >= 0 ? n : -n, b2 = n >= 0 ? m : -m;
             sm.S[a2 * W + b2 + B] = u1;
         }
@@ -137,100 +141,149 @@ __device__ void wigner_slice(const SoftArgs &a, const float4 *Cp, SoftSmem &sm, 
     __syncthreads();
 }
 
-// grid slice g[j][k] = 2 Re sum_{(m, n) in half plane} S[m, n] e^{i (m a_j + n c_k)}
-__device__ void dft_slice(const SoftArgs &a, SoftSmem &sm, float *out)
+// grid slice g[j][k] = 2 Re sum_{(m, n) in half plane} S[m, n] e^{i (m a_j + n c_k)}, then the
+// 3x3 in-plane maximum of the slice (a and c periodic).
+template <int NT>
+__device__ void dft_slice(const SoftArgs &a, SoftSmem &sm, float *out, float *m9)
 {
     const int B = a.B, W = 2 * B + 1, N = a.n;
-    for (int t = threadIdx.x; t < (B + 1) * N; t += kSoftThreads) {
-        const int m = t / N, k = t % N;
+    // T[m][k] = sum_n S[m, n] e^{i n c_k}; twiddle index (n k) mod N advanced incrementally
+    for (int t = threadIdx.x; t < (B + 1) * N; t += NT) {
+        const int m = t / N, k = t - (t / N) * N;
         float2 acc = make_float2(0.f, 0.f);
-        for (int nn = -B; nn <= B; ++nn) {
-            int r = (nn * k) % N;
-            if (r < 0) r += N;
-            const float2 s = sm.S[m * W + nn + B], e = sm.tw[r];
-            acc.x = fmaf(s.x, e.x, fmaf(-s.y, e.y, acc.x));
-            acc.y = fmaf(s.x, e.y, fmaf(s.y, e.x, acc.y));
+        int r = (N - (B * k) % N) % N;
+        const float2 *Sm = sm.S + m * W;
+        for (int nn = 0; nn < W; ++nn) {
+            const float2 sv = Sm[nn], e = sm.tw[r];
+            acc.x = fmaf(sv.x, e.x, fmaf(-sv.y, e.y, acc.x));
+            acc.y = fmaf(sv.x, e.y, fmaf(sv.y, e.x, acc.y));
+            r += k;
+            if (r >= N) r -= N;
         }
         sm.T[m * N + k] = acc;
     }
     __syncthreads();
-    for (int t = threadIdx.x; t < N * N; t += kSoftThreads) {
-        const int j = t / N, k = t % N;
-        float acc = 0.f;
+    // g[j][k] = 2 sum_m Re(T[m][k] e^{i m a_j}), six rows j per task
+    constexpr int JB = 6;
+    const int NJ = (N + JB - 1) / JB;
+    for (int t = threadIdx.x; t < NJ * N; t += NT) {
+        const int jb = t / N, k = t - (t / N) * N;
+        const int j0 = JB * jb;
+        float g[JB];
+#pragma unroll
+        for (int r = 0; r < JB; ++r) g[r] = 0.f;
         for (int m = 0; m <= B; ++m) {
-            const int r = (m * j) % N;
-            const float2 x = sm.T[m * N + k], e = sm.tw[r];
-            acc = fmaf(x.x, e.x, fmaf(-x.y, e.y, acc));
+            const float2 x = sm.T[m * N + k];
+            const float2 *Em = sm.E + m * N;
+#pragma unroll
+            for (int r = 0; r < JB; ++r) {
+                const float2 e = Em[min(j0 + r, N - 1)];
+                g[r] = fmaf(x.x, e.x, fmaf(-x.y, e.y, g[r]));
+            }
         }
-        out[t] = 2.f * acc;
+#pragma unroll
+        for (int r = 0; r < JB; ++r)
+            if (j0 + r < N) out[(j0 + r) * N + k] = 2.f * g[r];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < N * N; t += NT) {
+        const int j = t / N, k = t - (t / N) * N;
+        const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
+        const int km = k == 0 ? N - 1 : k - 1, kp = k == N - 1 ? 0 : k + 1;
+        const float *r0 = out + jm * N, *r1 = out + j * N, *r2 = out + jp * N;
+        float v = fmaxf(fmaxf(r0[km], r0[k]), r0[kp]);
+        v = fmaxf(v, fmaxf(fmaxf(r1[km], r1[k]), r1[kp]));
+        v = fmaxf(v, fmaxf(fmaxf(r2[km], r2[k]), r2[kp]));
+        m9[t] = v;
     }
     __syncthreads();
 }
 
-// Offer the nodes of slice i (value ring slot ci, neighbours pi / ni, -1 when absent) to the list.
-// want_max: offer local maxima (and count them); otherwise offer the other nodes.
+// Exact test of the node t of slice i against its 26 neighbours: (value, smaller index) wins.
+template <int NT>
+__device__ bool beats_all(const SoftArgs &a, const SoftSmem &sm, int i, int t, int pslot, int cslot, int nslot)
+{
+    const int N = a.n;
+    const int j = t / N, k = t - (t / N) * N;
+    const unsigned long long key = make_key(sm.ring(cslot)[t], (uint32_t)(i * N * N + t));
+    for (int di = -1; di <= 1; ++di) {
+        const int slot = di < 0 ? pslot : (di > 0 ? nslot : cslot);
+        if (slot < 0) continue;
+        const float *pl = sm.ring(slot);
+        for (int dj = -1; dj <= 1; ++dj) {
+            const int jj = (j + dj + N) % N;
+            for (int dk = -1; dk <= 1; ++dk) {
+                if (!di && !dj && !dk) continue;
+                const int kk = (k + dk + N) % N;
+                if (make_key(pl[jj * N + kk], (uint32_t)((i + di) * N * N + jj * N + kk)) > key) return false;
+            }
+        }
+    }
+    return true;
+}
+
+// Offer the nodes of slice i (ring slot cslot; neighbour slots pslot / nslot, -1 when the
+// slice is absent) to the list.  A node can be a local maximum only if its value equals the
+// maximum of the three 3x3 in-plane maxima around it; only those nodes take the exact test.
+// want_max: offer the local maxima (and count them); otherwise offer every other node.
+template <int NT>
 __device__ void offer_slice(const SoftArgs &a, SoftSmem &sm, int i, int pslot, int cslot, int nslot, bool want_max)
 {
     const int N = a.n;
-    const float *cur = sm.ring[cslot];
-    for (int base = 0; base < N * N; base += kSoftThreads) {
+    const float *cur = sm.ring(cslot);
+    for (int base = 0; base < N * N; base += NT) {
         const int t = base + threadIdx.x;
         bool offer = false;
         unsigned long long key = 0ull;
         if (t < N * N) {
-            const int j = t / N, k = t % N;
-            const uint32_t idx = (uint32_t)(i * N * N + t);
             const float v = cur[t];
-            key = make_key(v, idx);
-            bool is_max = true;
-            for (int di = -1; di <= 1 && is_max; ++di) {
-                const int slot = di < 0 ? pslot : (di > 0 ? nslot : cslot);
-                if (slot < 0) continue;
-                const float *pl = sm.ring[slot];
-                const int ii = i + di;
-                for (int dj = -1; dj <= 1; ++dj) {
-                    const int jj = (j + dj + N) % N;
-                    for (int dk = -1; dk <= 1; ++dk) {
-                        if (!di && !dj && !dk) continue;
-                        const int kk = (k + dk + N) % N;
-                        const unsigned long long kn = make_key(pl[jj * N + kk], (uint32_t)(ii * N * N + jj * N + kk));
-                        if (kn > key) is_max = false;
-                    }
-                }
-            }
-            offer = want_max ? is_max : !is_max;
+            float mx = sm.mx9(cslot)[t];
+            if (pslot >= 0) mx = fmaxf(mx, sm.mx9(pslot)[t]);
+            if (nslot >= 0) mx = fmaxf(mx, sm.mx9(nslot)[t]);
+            const bool is_max = (v >= mx) && beats_all<NT>(a, sm, i, t, pslot, cslot, nslot);
             if (want_max && is_max) atomicAdd(sm.nmax, 1);
-            if (offer && key <= (*sm.thresh)) offer = false;
+            offer = want_max ? is_max : !is_max;
+            if (offer) {
+                key = make_key(v, (uint32_t)(i * N * N + t));
+                if (key <= (*sm.thresh)) offer = false;
+            }
         }
         if (offer) {
             const int slot = atomicAdd(sm.count, 1);
             sm.list[slot] = key;
         }
-        __syncthreads();
-        if ((*sm.count) > kListCap - kSoftThreads) compact_list(sm, a.Kc);
+        if (!want_max) {
+            // every node of a chunk may be offered: keep room for a whole chunk
+            __syncthreads();
+            if ((*sm.count) > kListCap - NT) compact_list<NT>(sm, a.Kc);
+        }
     }
+    // local maxima never touch each other in a slice, so one slice adds at most n^2/4 keys
+    __syncthreads();
+    if ((*sm.count) > kListCap - (N * N + 3) / 4 - NT) compact_list<NT>(sm, a.Kc);
 }
 
 // One sweep over the grid; offers maxima (want_max) or non-maxima to the list.
+template <int NT>
 __device__ void soft_sweep(const SoftArgs &a, const float4 *Cp, SoftSmem &sm, bool want_max)
 {
     const int N = a.n;
     for (int i = 0; i <= N; ++i) {
         if (i < N) {
-            const double b = kPi * (2.0 * i + 1.0) / (2.0 * N);
-            wigner_slice(a, Cp, sm, b);
-            dft_slice(a, sm, sm.ring[i % 3]);
+            wigner_slice<NT>(a, Cp, sm, i);
+            dft_slice<NT>(a, sm, sm.ring(i % 3), sm.mx9(i % 3));
         }
         if (i >= 1) {
             const int ic = i - 1;
             const int pslot = ic >= 1 ? (ic - 1) % 3 : -1;
             const int nslot = ic + 1 < N ? (ic + 1) % 3 : -1;
-            offer_slice(a, sm, ic, pslot, ic % 3, nslot, want_max);
+            offer_slice<NT>(a, sm, ic, pslot, ic % 3, nslot, want_max);
         }
     }
 }
 
-__global__ void __launch_bounds__(kSoftThreads) k_soft_search(SoftArgs a)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_soft_search(SoftArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ unsigned long long s_thresh;
@@ -243,23 +296,30 @@ __global__ void __launch_bounds__(kSoftThreads) k_soft_search(SoftArgs a)
     const int p = blockIdx.x;
     const int N = a.n, Kc = a.Kc;
     const float4 *Cp = a.C + a.C_off[p] / 2;
-    for (int t = threadIdx.x; t < N; t += kSoftThreads) {
+    for (int t = threadIdx.x; t < N; t += NT) {
         float s, c;
         sincosf((float)(kTwoPi * t / N), &s, &c);
         sm.tw[t] = make_float2(c, s);
     }
+    for (int t = threadIdx.x; t < (a.B + 1) * N; t += NT) {
+        const int m = t / N, j = t - (t / N) * N;
+        float s, c;
+        sincosf((float)(kTwoPi * ((m * j) % N) / N), &s, &c);
+        sm.E[t] = make_float2(c, s);
+    }
+    for (int t = threadIdx.x; t < (a.B + 1) * (2 * a.B + 1); t += NT) sm.S[t] = make_float2(0.f, 0.f);
     if (threadIdx.x == 0) {
         (*sm.count) = 0;
         (*sm.nmax) = 0;
         (*sm.thresh) = 0ull;
     }
     __syncthreads();
-    soft_sweep(a, Cp, sm, true);
-    compact_list(sm, Kc);
+    soft_sweep<NT>(a, Cp, sm, true);
+    compact_list<NT>(sm, Kc);
     const int nmax = (*sm.nmax);
     const int nm = min(nmax, Kc);
     // ranked maxima -> cand[0 .. nm)
-    for (int t = threadIdx.x; t < nm; t += kSoftThreads) {
+    for (int t = threadIdx.x; t < nm; t += NT) {
         const unsigned long long key = sm.list[t];
         const uint32_t idx = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
         const float v = unordered_bits((uint32_t)(key >> 32));
@@ -275,9 +335,9 @@ __global__ void __launch_bounds__(kSoftThreads) k_soft_search(SoftArgs a)
             (*sm.thresh) = 0ull;
         }
         __syncthreads();
-        soft_sweep(a, Cp, sm, false);
-        compact_list(sm, Kc - nm);
-        for (int t = threadIdx.x; t < Kc - nm; t += kSoftThreads) {
+        soft_sweep<NT>(a, Cp, sm, false);
+        compact_list<NT>(sm, Kc - nm);
+        for (int t = threadIdx.x; t < Kc - nm; t += NT) {
             const unsigned long long key = sm.list[t];
             const uint32_t idx = 0xffffffffu - (uint32_t)(key & 0xffffffffull);
             const float v = unordered_bits((uint32_t)(key >> 32));
@@ -292,9 +352,16 @@ __global__ void __launch_bounds__(kSoftThreads) k_soft_search(SoftArgs a)
 
 size_t soft_smem_bytes(int n, int B) { return soft_smem_size(n, B); }
 
-hipError_t launch_soft(const SoftArgs &a, int P, hipStream_t s)
+hipError_t launch_soft(const SoftArgs &a, int P, int threads, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_soft_search, dim3(P), dim3(kSoftThreads), soft_smem_size(a.n, a.B), s, a);
+    if (threads == 256)
+        hipLaunchKernelGGL(k_soft_search<256>, dim3(P), dim3(256), soft_smem_size(a.n, a.B), s, a);
+    else if (threads == 512)
+        hipLaunchKernelGGL(k_soft_search<512>, dim3(P), dim3(512), soft_smem_size(a.n, a.B), s, a);
+    else if (threads == 1024)
+        hipLaunchKernelGGL(k_soft_search<1024>, dim3(P), dim3(1024), soft_smem_size(a.n, a.B), s, a);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
 }
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <utility>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -18,7 +19,11 @@ struct matcha_ctx {
     int device = 0;
     int tab_L = -1;  // tables cover l <= tab_L
     float4 *tab = nullptr;
+    double2 *tab64 = nullptr;  // (A, AC) of tab in FP64
     PairInfo *pinfo = nullptr;
+    matcha_tuning tune{0, 0};
+    int grid_B = -1, grid_n = -1;  // the SOFFT node table below is for (grid_B, grid_n)
+    float2 *dgrid = nullptr;
 };
 
 namespace {
@@ -45,9 +50,10 @@ double rec_c(int l, int m, int n) { return l == 0 ? 0.0 : (double)m * n / ((doub
 // w = 1/2 for the self-conjugate pair (0, 0) (every other term is doubled by its Hermitian
 // mirror); w~ = 0 for diagonal pairs whose partner is the pair itself; s = (-1)^{m-n} for
 // n >= 0 (d_nm = (-1)^{m-n} d_mn) and 1 for n < 0 (d_{-n,-m} = d_mn).
-void build_tables(int Lmax, std::vector<float4> &tab, std::vector<PairInfo> &pinfo)
+void build_tables(int Lmax, std::vector<float4> &tab, std::vector<double2> &tab64, std::vector<PairInfo> &pinfo)
 {
     tab.assign((size_t)wedge_row(Lmax + 1), make_float4(0.f, 0.f, 0.f, 0.f));
+    tab64.assign((size_t)wedge_row(Lmax + 1), make_double2(0.0, 0.0));
     pinfo.assign((size_t)(Lmax + 1) * (Lmax + 1), PairInfo{0, 0, 0.0});
     std::vector<double> P((size_t)Lmax + 2);
     for (int m = 0; m <= Lmax; ++m)
@@ -65,14 +71,17 @@ void build_tables(int Lmax, std::vector<float4> &tab, std::vector<PairInfo> &pin
             for (int l = m + 1; l <= Lmax; ++l) P[l + 1] = rec_b(l, m, n) * P[l - 1];
             for (int l = m; l <= Lmax; ++l) {
                 float4 e;
+                double2 e64 = make_double2(0.0, 0.0);
                 if (l == m) {
                     e.x = 0.f;
                     e.y = 0.f;
                 } else {
                     const double ab = rec_a(l - 1, m, n) * P[l - 1] / P[l];
-                    e.x = (float)ab;
-                    e.y = (float)(ab * rec_c(l - 1, m, n));
+                    e64 = make_double2(ab, ab * rec_c(l - 1, m, n));
+                    e.x = (float)e64.x;
+                    e.y = (float)e64.y;
                 }
+                tab64[(size_t)wedge_row(l) + q] = e64;
                 e.z = (float)(wt * P[l]);
                 e.w = (float)(wtt * sg * P[l]);
                 tab[(size_t)wedge_row(l) + q] = e;
@@ -84,19 +93,28 @@ matcha_status ensure_tables(matcha_ctx *ctx, int L)
 {
     if (L <= ctx->tab_L) return MATCHA_OK;
     std::vector<float4> tab;
+    std::vector<double2> tab64;
     std::vector<PairInfo> pinfo;
-    build_tables(L, tab, pinfo);
+    build_tables(L, tab, tab64, pinfo);
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     float4 *dt = nullptr;
+    double2 *dt64 = nullptr;
     PairInfo *dp = nullptr;
     if (hipMalloc(&dt, tab.size() * sizeof(float4)) != hipSuccess) return MATCHA_ERR_HIP;
-    if (hipMalloc(&dp, pinfo.size() * sizeof(PairInfo)) != hipSuccess) {
+    if (hipMalloc(&dt64, tab64.size() * sizeof(double2)) != hipSuccess) {
         (void)hipFree(dt);
         return MATCHA_ERR_HIP;
     }
+    if (hipMalloc(&dp, pinfo.size() * sizeof(PairInfo)) != hipSuccess) {
+        (void)hipFree(dt);
+        (void)hipFree(dt64);
+        return MATCHA_ERR_HIP;
+    }
     if (hipMemcpy(dt, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(dt64, tab64.data(), tab64.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(dp, pinfo.data(), pinfo.size() * sizeof(PairInfo), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(dt);
+        (void)hipFree(dt64);
         (void)hipFree(dp);
         return MATCHA_ERR_HIP;
     }
@@ -104,11 +122,66 @@ matcha_status ensure_tables(matcha_ctx *ctx, int L)
     if (ctx->tab) {
         (void)hipDeviceSynchronize();
         (void)hipFree(ctx->tab);
+        (void)hipFree(ctx->tab64);
         (void)hipFree(ctx->pinfo);
     }
     ctx->tab = dt;
+    ctx->tab64 = dt64;
     ctx->pinfo = dp;
     ctx->tab_L = L;
+    return MATCHA_OK;
+}
+
+// d^l_mn(b_i) at the SOFFT polar nodes b_i = pi (2i+1) / (2n) for every wedge pair and l <= B,
+// in FP64 by the three-term recurrence from the edge value
+//   d^m_mn(b) = (-1)^{m-n} sqrt(binom(2m, m+n)) cos^{m+n}(b/2) sin^{m-n}(b/2),
+// stored per node in the wedge layout as (w d, w~ s d) -- the weights of build_tables.
+void build_grid_table(int B, int n, std::vector<float2> &g)
+{
+    const int64_t rows = wedge_row(B + 1);
+    g.assign((size_t)(n * rows), make_float2(0.f, 0.f));
+    for (int i = 0; i < n; ++i) {
+        const double b = M_PI * (2.0 * i + 1.0) / (2.0 * n);
+        const double cb = std::cos(b), ch = std::cos(0.5 * b), sh = std::sin(0.5 * b);
+        for (int m = 0; m <= B; ++m)
+            for (int nn = -m; nn <= m; ++nn) {
+                const int q = m * m + m + nn;
+                const double wt = (m == 0) ? 0.5 : 1.0;
+                const double wtt = (nn == m || nn == -m) ? 0.0 : 1.0;
+                const double sg = (nn >= 0 && ((m - nn) & 1)) ? -1.0 : 1.0;
+                const double lb = 0.5 * (std::lgamma(2.0 * m + 1.0) - std::lgamma(m + nn + 1.0) - std::lgamma(m - nn + 1.0));
+                double d = std::exp(lb) * std::pow(ch, m + nn) * std::pow(sh, m - nn);
+                if ((m - nn) & 1) d = -d;
+                double dm = 0.0;
+                for (int l = m; l <= B; ++l) {
+                    g[(size_t)(i * rows + wedge_row(l) + q)] = make_float2((float)(wt * d), (float)(wtt * sg * d));
+                    const double dn = rec_a(l, m, nn) * (cb - rec_c(l, m, nn)) * d - rec_b(l, m, nn) * dm;
+                    dm = d;
+                    d = dn;
+                }
+            }
+    }
+}
+
+matcha_status ensure_grid(matcha_ctx *ctx, int B, int n)
+{
+    if (ctx->dgrid && ctx->grid_B == B && ctx->grid_n == n) return MATCHA_OK;
+    std::vector<float2> g;
+    build_grid_table(B, n, g);
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    float2 *d = nullptr;
+    if (hipMalloc(&d, g.size() * sizeof(float2)) != hipSuccess) return MATCHA_ERR_HIP;
+    if (hipMemcpy(d, g.data(), g.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        return MATCHA_ERR_HIP;
+    }
+    if (ctx->dgrid) {
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->dgrid);
+    }
+    ctx->dgrid = d;
+    ctx->grid_B = B;
+    ctx->grid_n = n;
     return MATCHA_OK;
 }
 
@@ -141,7 +214,13 @@ matcha_status check_batch(const matcha_batch *b, int *minL, int *maxL, int *maxR
 
 matcha_status launched(hipError_t e) { return e == hipSuccess ? MATCHA_OK : MATCHA_ERR_HIP; }
 
-int march_nc(int Kc) { return Kc <= 32 ? 4 : 8; }
+int march_nc(const matcha_ctx *ctx, int Kc)
+{
+    int nc = ctx->tune.march_nc;
+    if (nc == 0) nc = Kc <= 32 ? 4 : 8;
+    while ((Kc + nc - 1) / nc > 8) nc *= 2;
+    return nc;
+}
 
 }  // namespace
 
@@ -167,7 +246,13 @@ matcha_status matcha_destroy(matcha_ctx *ctx)
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
         (void)hipFree(ctx->tab);
+        (void)hipFree(ctx->tab64);
         (void)hipFree(ctx->pinfo);
+    }
+    if (ctx->dgrid) {
+        (void)hipSetDevice(ctx->device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ctx->dgrid);
     }
     delete ctx;
     return MATCHA_OK;
@@ -176,7 +261,9 @@ matcha_status matcha_destroy(matcha_ctx *ctx)
 matcha_status matcha_prepare(matcha_ctx *ctx, int32_t L_max, int32_t B, int32_t n_grid)
 {
     if (!ctx || L_max < 0 || L_max > MATCHA_MAX_L || B < 0 || B > L_max || n_grid < 0) return MATCHA_ERR_INVALID_ARG;
-    return ensure_tables(ctx, L_max);
+    matcha_status st = ensure_tables(ctx, L_max);
+    if (st != MATCHA_OK || B < 1 || n_grid < 4) return st;
+    return ensure_grid(ctx, B, n_grid);
 }
 
 const char *matcha_status_string(matcha_status s)
@@ -189,6 +276,24 @@ const char *matcha_status_string(matcha_status s)
     case MATCHA_ERR_WORKSPACE: return "workspace too small";
     }
     return "unknown status";
+}
+
+matcha_status matcha_set_tuning(matcha_ctx *ctx, const matcha_tuning *t)
+{
+    if (!ctx || !t) return MATCHA_ERR_INVALID_ARG;
+    const int nc = t->march_nc;
+    if (nc != 0 && nc != 1 && nc != 2 && nc != 4 && nc != 8) return MATCHA_ERR_INVALID_ARG;
+    const int st = t->soft_threads;
+    if (st != 0 && st != 256 && st != 512 && st != 1024) return MATCHA_ERR_INVALID_ARG;
+    ctx->tune = *t;
+    return MATCHA_OK;
+}
+
+matcha_status matcha_get_tuning(const matcha_ctx *ctx, matcha_tuning *t)
+{
+    if (!ctx || !t) return MATCHA_ERR_INVALID_ARG;
+    *t = ctx->tune;
+    return MATCHA_OK;
 }
 
 int64_t matcha_c_elems(int32_t L)
@@ -205,9 +310,16 @@ int64_t matcha_f_elems(int32_t L, int32_t R)
 
 size_t matcha_workspace_size(const matcha_batch *batch, int32_t Kc)
 {
-    (void)batch;
     (void)Kc;
-    return 0;
+    if (!batch || batch->n_particles <= 0 || !batch->L_host || !batch->R_host) return 0;
+    // matcha_grad_template: one complex float32 template-gradient term per particle, laid out like f
+    size_t n = 0;
+    for (int p = 0; p < batch->n_particles; ++p) {
+        const int64_t e = matcha_f_elems(batch->L_host[p], batch->R_host[p]);
+        if (e < 0) return 0;
+        n += (size_t)e;
+    }
+    return n * 2 * sizeof(float);
 }
 
 matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
@@ -219,10 +331,41 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
     if (st != MATCHA_OK) return st;
     if (batch->n_particles == 0) return MATCHA_OK;
     if (!f || !h || !w || !C || !batch->f_offset || !aligned16(C)) return MATCHA_ERR_INVALID_ARG;
-    if (prec != MATCHA_FP32) return MATCHA_ERR_UNSUPPORTED;
-    if (assemble_smem_bytes(hi, rmax) > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
+    if (prec != MATCHA_FP32 && prec != MATCHA_BF16_FP32ACC) return MATCHA_ERR_UNSUPPORTED;
+    const size_t smem = prec == MATCHA_FP32 ? assemble_smem_bytes(hi, rmax) : assemble_bf16_smem_bytes(hi, rmax);
+    if (smem > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    // split 0..hi into up to 4 chunks of about equal work, sum_l (l+1)(2l+1)
+    int n_chunks = 0, chunk_lo[9] = {0};
+    {
+        double total = 0.0;
+        for (int l = 0; l <= hi; ++l) total += (l + 1.0) * (2.0 * l + 1.0);
+        const int want = hi >= 8 ? 4 : 1;
+        double acc = 0.0;
+        for (int l = 0; l <= hi; ++l) {
+            acc += (l + 1.0) * (2.0 * l + 1.0);
+            if (acc >= total * (n_chunks + 1) / want && n_chunks + 1 < want && l < hi) chunk_lo[++n_chunks] = l + 1;
+        }
+        chunk_lo[++n_chunks] = hi + 1;
+    }
+    if (prec == MATCHA_BF16_FP32ACC) {
+        AsmBArgs b;
+        std::memset(&b, 0, sizeof b);
+        b.f = static_cast<const __bf16 *>(f);
+        b.f_off = batch->f_offset;
+        b.h = static_cast<const __bf16 *>(h);
+        b.w = w;
+        b.Lp = batch->L_dev;
+        b.Rp = batch->R_dev;
+        b.Lh = batch->L_h;
+        b.C = reinterpret_cast<float4 *>(C);
+        b.C_off = batch->C_offset;
+        b.n_chunks = n_chunks;
+        for (int c = 0; c <= n_chunks; ++c) b.chunk_lo[c] = chunk_lo[c];
+        return launched(launch_assemble_bf16(b, batch->n_particles, hi, rmax, static_cast<hipStream_t>(stream)));
+    }
     AsmArgs a;
+    std::memset(&a, 0, sizeof a);
     a.f = static_cast<const float2 *>(f);
     a.f_off = batch->f_offset;
     a.h = static_cast<const float2 *>(h);
@@ -232,6 +375,8 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
     a.Lh = batch->L_h;
     a.C = reinterpret_cast<float4 *>(C);
     a.C_off = batch->C_offset;
+    a.n_chunks = n_chunks;
+    for (int c = 0; c <= n_chunks; ++c) a.chunk_lo[c] = chunk_lo[c];
     return launched(launch_assemble_f32(a, batch->n_particles, hi, rmax, static_cast<hipStream_t>(stream)));
 }
 
@@ -249,18 +394,21 @@ matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, con
     if (soft_smem_bytes(n, B) > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
     st = ensure_tables(ctx, std::max(hi, B));
     if (st != MATCHA_OK) return st;
+    st = ensure_grid(ctx, B, n);
+    if (st != MATCHA_OK) return st;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     SoftArgs a;
     a.C = reinterpret_cast<const float4 *>(C);
     a.C_off = batch->C_offset;
-    a.tab = ctx->tab;
+    a.dgrid = ctx->dgrid;
     a.pinfo = ctx->pinfo;
     a.B = B;
     a.n = n;
     a.Kc = Kc;
     a.cand = reinterpret_cast<float4 *>(cand);
     a.status = status;
-    return launched(launch_soft(a, batch->n_particles, static_cast<hipStream_t>(stream)));
+    const int nt = ctx->tune.soft_threads ? ctx->tune.soft_threads : 512;
+    return launched(launch_soft(a, batch->n_particles, nt, static_cast<hipStream_t>(stream)));
 }
 
 matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
@@ -290,6 +438,8 @@ matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, co
     a.C_off = batch->C_offset;
     a.Lp = batch->L_dev;
     a.tab = ctx->tab;
+    a.tab64 = ctx->tab64;
+    a.fp64_above = cfg->fp64_above > 0 ? cfg->fp64_above : MATCHA_MAX_L;
     a.pinfo = ctx->pinfo;
     a.n_levels = cfg->n_levels;
     for (int j = 0; j < cfg->n_levels; ++j) a.levels[j] = cfg->levels[j];
@@ -304,12 +454,13 @@ matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, co
     a.best = reinterpret_cast<float4 *>(best);
     a.best_idx = best_idx;
     a.status = status;
-    const int nc = march_nc(Kc);
+    a.order = batch->order;
+    const int nc = march_nc(ctx, Kc);
     return launched(launch_march_any(a, batch->n_particles, nc, static_cast<hipStream_t>(stream)));
 }
 
 matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const float *C, int32_t L_eval,
-                              const float *theta, float *out, void *stream)
+                              int32_t fp64_above, const float *theta, float *out, void *stream)
 {
     int lo, hi, rmax;
     if (!ctx) return MATCHA_ERR_INVALID_ARG;
@@ -317,7 +468,7 @@ matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const 
     if (st != MATCHA_OK) return st;
     if (batch->n_particles == 0) return MATCHA_OK;
     if (!C || !theta || !out || !aligned16(C) || !aligned16(theta)) return MATCHA_ERR_INVALID_ARG;
-    if (L_eval < 0 || L_eval > lo) return MATCHA_ERR_INVALID_ARG;
+    if (L_eval < 0 || L_eval > lo) return MATCHA_ERR_INVALID_ARG;  /* 0: each particle's own L_p */
     st = ensure_tables(ctx, std::max(hi, L_eval));
     if (st != MATCHA_OK) return st;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
@@ -325,7 +476,10 @@ matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const 
     a.C = reinterpret_cast<const float4 *>(C);
     a.C_off = batch->C_offset;
     a.tab = ctx->tab;
+    a.tab64 = ctx->tab64;
+    a.fp64_above = fp64_above > 0 ? fp64_above : MATCHA_MAX_L;
     a.pinfo = ctx->pinfo;
+    a.Lp = batch->L_dev;
     a.L = L_eval;
     a.theta = reinterpret_cast<const float4 *>(theta);
     a.out = out;
@@ -336,19 +490,195 @@ matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, c
                                    const float *w, const float *best, const float *g, float *grad_h, float *grad_f,
                                    void *ws, size_t ws_bytes, void *stream)
 {
-    (void)ctx;
-    (void)batch;
-    (void)f;
-    (void)h;
-    (void)w;
-    (void)best;
-    (void)g;
-    (void)grad_h;
-    (void)grad_f;
-    (void)ws;
-    (void)ws_bytes;
-    (void)stream;
-    return MATCHA_ERR_UNSUPPORTED;
+    int lo, hi, rmax;
+    if (!ctx) return MATCHA_ERR_INVALID_ARG;
+    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
+    if (st != MATCHA_OK) return st;
+    if (batch->n_particles == 0) return MATCHA_OK;
+    if (!f || !h || !w || !best || !g || !batch->f_offset || !aligned16(best)) return MATCHA_ERR_INVALID_ARG;
+    if (!grad_h && !grad_f) return MATCHA_OK;
+    if (grad_h && (!ws || ws_bytes < matcha_workspace_size(batch, 0))) return MATCHA_ERR_WORKSPACE;
+    if (grad_smem_bytes(hi) > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
+    st = ensure_tables(ctx, hi);
+    if (st != MATCHA_OK) return st;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    GradArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.f = reinterpret_cast<const float2 *>(f);
+    a.f_off = batch->f_offset;
+    a.h = reinterpret_cast<const float2 *>(h);
+    a.w = w;
+    a.Lp = batch->L_dev;
+    a.Rp = batch->R_dev;
+    a.Lh = batch->L_h;
+    a.Rh = batch->R_h;
+    a.L_max = hi;
+    a.P = batch->n_particles;
+    a.best = reinterpret_cast<const float4 *>(best);
+    a.g = g;
+    a.grad_f = reinterpret_cast<float2 *>(grad_f);
+    a.grad_h = reinterpret_cast<float2 *>(grad_h);
+    a.ws = grad_h ? static_cast<float2 *>(ws) : nullptr;
+    a.pinfo = ctx->pinfo;
+    a.tab = ctx->tab;
+    return launched(launch_grad(a, static_cast<hipStream_t>(stream)));
+}
+
+matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg *cfg, int32_t *order_host)
+{
+    int lo, hi, rmax;
+    if (!cfg || !order_host || !cfg->levels || cfg->n_levels < 1) return MATCHA_ERR_INVALID_ARG;
+    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
+    if (st != MATCHA_OK) return st;
+    const int P = batch->n_particles;
+    std::vector<std::pair<double, int>> cost((size_t)P);
+    for (int p = 0; p < P; ++p) {
+        const int Lp = batch->L_host[p];
+        double c = 0.0;
+        for (int j = 0; j < cfg->n_levels; ++j)
+            if (cfg->levels[j] < Lp) c += (double)wedge_row(cfg->levels[j] + 1);
+        c += (double)wedge_row(Lp + 1);
+        cost[(size_t)p] = {-c, p};
+    }
+    std::stable_sort(cost.begin(), cost.end());
+    for (int p = 0; p < P; ++p) order_host[p] = cost[(size_t)p].second;
+    return MATCHA_OK;
+}
+
+struct matcha_graph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
+                                        const float *w, float *C, matcha_precision prec, const matcha_soft_cfg *soft,
+                                        const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
+                                        uint32_t *status, matcha_graph **out)
+{
+    int lo, hi, rmax;
+    if (!ctx || !soft || !march || !out) return MATCHA_ERR_INVALID_ARG;
+    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
+    if (st != MATCHA_OK) return st;
+    // build every table now: nothing may allocate while the stream is being captured
+    st = ensure_tables(ctx, std::max(hi, soft->B));
+    if (st != MATCHA_OK) return st;
+    if (soft->B >= 1 && soft->n_grid >= 4) {
+        st = ensure_grid(ctx, soft->B, soft->n_grid);
+        if (st != MATCHA_OK) return st;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MATCHA_ERR_HIP;
+    matcha_graph *g = new (std::nothrow) matcha_graph();
+    if (!g) {
+        (void)hipStreamDestroy(cs);
+        return MATCHA_ERR_HIP;
+    }
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        delete g;
+        (void)hipStreamDestroy(cs);
+        return MATCHA_ERR_HIP;
+    }
+    st = matcha_coeff_assemble(ctx, batch, f, h, w, C, prec, cs);
+    if (st == MATCHA_OK) st = matcha_soft_search(ctx, batch, C, soft, cand, status, cs);
+    if (st == MATCHA_OK) st = matcha_march_newton(ctx, batch, C, march, soft->Kc, cand, best, best_idx, status, cs);
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (st != MATCHA_OK || ec != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        delete g;
+        return st != MATCHA_OK ? st : MATCHA_ERR_HIP;
+    }
+    if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        delete g;
+        return MATCHA_ERR_HIP;
+    }
+    g->graph = graph;
+    *out = g;
+    return MATCHA_OK;
+}
+
+matcha_status matcha_graph_launch(matcha_graph *g, void *stream)
+{
+    if (!g || !g->exec) return MATCHA_ERR_INVALID_ARG;
+    return launched(hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream)));
+}
+
+matcha_status matcha_graph_destroy(matcha_graph *g)
+{
+    if (!g) return MATCHA_ERR_INVALID_ARG;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return MATCHA_OK;
+}
+
+matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *soft,
+                              const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
+                              uint32_t *status, int32_t reps, matcha_tuning *best_tuning)
+{
+    if (!ctx || !soft || !march || !best_tuning || reps < 1) return MATCHA_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return MATCHA_ERR_HIP;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        (void)hipStreamDestroy(s);
+        return MATCHA_ERR_HIP;
+    }
+    const matcha_tuning saved = ctx->tune;
+    matcha_status st = MATCHA_OK;
+    auto time_it = [&](auto &&run, float *ms) -> matcha_status {
+        matcha_status r = run();  // warm-up
+        if (r != MATCHA_OK) return r;
+        if (hipEventRecord(e0, s) != hipSuccess) return MATCHA_ERR_HIP;
+        for (int i = 0; i < reps; ++i)
+            if ((r = run()) != MATCHA_OK) return r;
+        if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return MATCHA_ERR_HIP;
+        return hipEventElapsedTime(ms, e0, e1) == hipSuccess ? MATCHA_OK : MATCHA_ERR_HIP;
+    };
+    matcha_tuning best_t = saved;
+    // SOFFT workgroup size
+    float best_ms = 1e30f;
+    for (int nt : {256, 512}) {
+        ctx->tune.soft_threads = nt;
+        float ms = 0.f;
+        st = time_it([&] { return matcha_soft_search(ctx, batch, C, soft, cand, status, s); }, &ms);
+        if (st != MATCHA_OK) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_t.soft_threads = nt;
+        }
+    }
+    // march candidates per wave (each trial re-runs the search so that it starts from fresh candidates)
+    ctx->tune.soft_threads = best_t.soft_threads;
+    best_ms = 1e30f;
+    for (int nc : {2, 4, 8}) {
+        if (st != MATCHA_OK) break;
+        if ((soft->Kc + nc - 1) / nc > 8) continue;
+        ctx->tune.march_nc = nc;
+        float ms = 0.f;
+        st = time_it(
+            [&] {
+                matcha_status r = matcha_soft_search(ctx, batch, C, soft, cand, status, s);
+                return r == MATCHA_OK ? matcha_march_newton(ctx, batch, C, march, soft->Kc, cand, best, best_idx, status, s)
+                                      : r;
+            },
+            &ms);
+        if (st == MATCHA_OK && ms < best_ms) {
+            best_ms = ms;
+            best_t.march_nc = nc;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamSynchronize(s);
+    (void)hipStreamDestroy(s);
+    ctx->tune = st == MATCHA_OK ? best_t : saved;
+    *best_tuning = ctx->tune;
+    return st;
 }
 
 }  // extern "C"

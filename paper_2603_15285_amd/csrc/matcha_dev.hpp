@@ -35,9 +35,11 @@ __device__ inline int isqrt_dev(int q)
 // at 1e-15 so that the edge seeds never meet 0 * inf at the chart poles.
 struct BetaConst {
     float cb, sb;     // cos b, sin b
+    double cbd, sbd;  // cos b, sin b in FP64 (for the FP64 recurrence)
     float ct, tn;     // cot(b/2), tan(b/2)
     float qk, qp;     // -csc^2(b/2)/4, -sec^2(b/2)/4
     double lc2, ls2;  // log2 cos(b/2), log2 sin(b/2)
+    double ch, sh;    // cos(b/2), sin(b/2), clamped
 };
 
 __device__ inline BetaConst beta_const(double b)
@@ -46,14 +48,18 @@ __device__ inline BetaConst beta_const(double b)
     double c = cos(0.5 * b), s = sin(0.5 * b);
     c = fmax(fabs(c), 1e-15);
     s = fmax(fabs(s), 1e-15);
-    k.cb = (float)cos(b);
-    k.sb = (float)sin(b);
+    k.cbd = cos(b);
+    k.sbd = sin(b);
+    k.cb = (float)k.cbd;
+    k.sb = (float)k.sbd;
     k.ct = (float)(c / s);
     k.tn = (float)(s / c);
     k.qk = (float)(-0.25 / (s * s));
     k.qp = (float)(-0.25 / (c * c));
     k.lc2 = log2(c);
     k.ls2 = log2(s);
+    k.ch = c;
+    k.sh = s;
     return k;
 }
 
@@ -75,6 +81,21 @@ __device__ inline void edge_seed(int m, int n, double lbh2, const BetaConst &k, 
     d0 = e;
     d1 = e * h1;
     d2 = e * fmaf(h1, h1, h2);
+}
+
+// The same edge values in FP64 (for the FP64 recurrence above the threshold degree).
+__device__ inline void edge_seed_d(int m, int n, double lbh2, const BetaConst &k, double &d0, double &d1, double &d2)
+{
+    const int p = m + n, kk = m - n;
+    const double x = lbh2 + (double)p * k.lc2 + (double)kk * k.ls2;
+    double e = exp2(x);
+    if (kk & 1) e = -e;
+    const double c = k.ch, s = k.sh;
+    const double h1 = 0.5 * ((double)kk * (c / s) - (double)p * (s / c));
+    const double h2 = -0.25 * ((double)kk / (s * s) + (double)p / (c * c));
+    d0 = e;
+    d1 = e * h1;
+    d2 = e * (h1 * h1 + h2);
 }
 
 __device__ inline float bcast(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }

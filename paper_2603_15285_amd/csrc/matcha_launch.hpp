@@ -14,12 +14,28 @@ struct AsmArgs {
     int Lh;
     float4 *C;
     const int64_t *C_off;
+    int n_chunks;             // degrees are split into chunks [chunk_lo[c], chunk_lo[c+1])
+    int chunk_lo[9];
+};
+
+struct AsmBArgs {
+    const __bf16 *f;          // complex BF16 pairs (re, im)
+    const int64_t *f_off;     // complex offsets
+    const __bf16 *h;
+    const float *w;
+    const int32_t *Lp;
+    const int32_t *Rp;
+    int Lh;
+    float4 *C;
+    const int64_t *C_off;
+    int n_chunks;
+    int chunk_lo[9];
 };
 
 struct SoftArgs {
     const float4 *C;
     const int64_t *C_off;
-    const float4 *tab;
+    const float2 *dgrid;      // [n][wedge_row(B+1)]: weighted d^l(b_i) of each wedge pair and its partner
     const PairInfo *pinfo;
     int B, n, Kc;
     float4 *cand;
@@ -31,6 +47,8 @@ struct MarchArgs {
     const int64_t *C_off;     // complex offsets (even)
     const int32_t *Lp;
     const float4 *tab;        // per (l, q): A = abar_{l-1}, AC = abar_{l-1} c_{l-1}, PW = w P_l, PWT = w~ s P_l
+    const double2 *tab64;     // per (l, q): (A, AC) in FP64 for the FP64 recurrence
+    int fp64_above;           // levels above this degree run the recurrence in FP64
     const PairInfo *pinfo;
     int n_levels;
     int levels[kMaxLevels];
@@ -43,26 +61,53 @@ struct MarchArgs {
     float4 *best;
     int32_t *best_idx;
     uint32_t *status;
+    const int32_t *order;     // nullable processing order (workgroup b takes particle order[b])
 };
 
 struct EvalArgs {
     const float4 *C;
     const int64_t *C_off;
     const float4 *tab;
+    const double2 *tab64;
+    int fp64_above;
     const PairInfo *pinfo;
-    int L;
+    const int32_t *Lp;
+    int L;                    // > 0: this band for every particle; 0: each particle's L_p
     const float4 *theta;
     float *out;
+};
+
+struct GradArgs {
+    const float2 *f;
+    const int64_t *f_off;
+    const float2 *h;
+    const float *w;
+    const int32_t *Lp;
+    const int32_t *Rp;
+    int Lh, Rh, L_max, P;
+    const float4 *best;
+    const float *g;
+    float2 *grad_f;           // may be null
+    float2 *ws;               // per-particle grad_h terms, laid out like f (null if grad_h is null)
+    float2 *grad_h;           // may be null
+    const PairInfo *pinfo;
+    const float4 *tab;
 };
 
 size_t assemble_smem_bytes(int Lmax, int Rmax);
 hipError_t launch_assemble_f32(const AsmArgs &a, int P, int Lmax, int Rmax, hipStream_t s);
 
+size_t assemble_bf16_smem_bytes(int Lmax, int Rmax);
+hipError_t launch_assemble_bf16(const AsmBArgs &a, int P, int Lmax, int Rmax, hipStream_t s);
+
 size_t soft_smem_bytes(int n, int B);
-hipError_t launch_soft(const SoftArgs &a, int P, hipStream_t s);
+hipError_t launch_soft(const SoftArgs &a, int P, int threads, hipStream_t s);
 
 size_t march_smem_any(int Kc, int nc);
 hipError_t launch_march_any(const MarchArgs &a, int P, int nc, hipStream_t s);
 hipError_t launch_evaluate(const EvalArgs &a, int P, hipStream_t s);
+
+size_t grad_smem_bytes(int Lmax);
+hipError_t launch_grad(const GradArgs &a, hipStream_t s);
 
 }  // namespace matcha

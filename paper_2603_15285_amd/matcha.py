@@ -22,9 +22,11 @@ FP32, BF16_FP32ACC = 0, 1
 ST_NONFINITE, ST_INDEFINITE, ST_SINGULAR, ST_NEAR_POLE, ST_FEW_MAXIMA, ST_EARLY_STOP = 1, 2, 4, 8, 16, 32
 MAX_L, MAX_KC, MAX_LEVELS = 64, 64, 16
 
-EXPORTED = ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_status_string", "matcha_c_elems",
-            "matcha_f_elems", "matcha_workspace_size", "matcha_coeff_assemble", "matcha_soft_search",
-            "matcha_march_newton", "matcha_evaluate", "matcha_grad_template"]
+EXPORTED = ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_status_string", "matcha_set_tuning",
+            "matcha_get_tuning", "matcha_c_elems", "matcha_f_elems", "matcha_workspace_size", "matcha_lpt_order",
+            "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton", "matcha_evaluate",
+            "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch", "matcha_graph_destroy",
+            "matcha_autotune"]
 
 
 class MatchaError(RuntimeError):
@@ -35,7 +37,11 @@ class _Batch(ct.Structure):
     _fields_ = [("n_particles", ct.c_int32), ("L_max", ct.c_int32),
                 ("L_host", ct.POINTER(ct.c_int32)), ("R_host", ct.POINTER(ct.c_int32)),
                 ("L_dev", ct.c_void_p), ("R_dev", ct.c_void_p), ("f_offset", ct.c_void_p), ("C_offset", ct.c_void_p),
-                ("L_h", ct.c_int32), ("R_h", ct.c_int32)]
+                ("L_h", ct.c_int32), ("R_h", ct.c_int32), ("order", ct.c_void_p)]
+
+
+class _Tuning(ct.Structure):
+    _fields_ = [("march_nc", ct.c_int32), ("soft_threads", ct.c_int32)]
 
 
 class _SoftCfg(ct.Structure):
@@ -45,7 +51,8 @@ class _SoftCfg(ct.Structure):
 class _MarchCfg(ct.Structure):
     _fields_ = [("levels", ct.POINTER(ct.c_int32)), ("n_levels", ct.c_int32), ("steps", ct.c_int32),
                 ("max_step", ct.c_double), ("early_stop", ct.c_int32),
-                ("tol_grad", ct.c_double), ("tol_step", ct.c_double), ("tol_rel", ct.c_double)]
+                ("tol_grad", ct.c_double), ("tol_step", ct.c_double), ("tol_rel", ct.c_double),
+                ("fp64_above", ct.c_int32)]
 
 
 _lib = None
@@ -65,6 +72,8 @@ def lib():
         L.matcha_prepare.argtypes = [vp, i32, i32, i32]
         L.matcha_status_string.argtypes = [ct.c_int]
         L.matcha_status_string.restype = ct.c_char_p
+        L.matcha_set_tuning.argtypes = [vp, ct.POINTER(_Tuning)]
+        L.matcha_get_tuning.argtypes = [vp, ct.POINTER(_Tuning)]
         L.matcha_c_elems.argtypes = [i32]
         L.matcha_c_elems.restype = i64
         L.matcha_f_elems.argtypes = [i32, i32]
@@ -74,10 +83,19 @@ def lib():
         L.matcha_coeff_assemble.argtypes = [vp, bp, vp, vp, vp, vp, ct.c_int, vp]
         L.matcha_soft_search.argtypes = [vp, bp, vp, ct.POINTER(_SoftCfg), vp, vp, vp]
         L.matcha_march_newton.argtypes = [vp, bp, vp, ct.POINTER(_MarchCfg), i32, vp, vp, vp, vp, vp]
-        L.matcha_evaluate.argtypes = [vp, bp, vp, i32, vp, vp, vp]
+        L.matcha_evaluate.argtypes = [vp, bp, vp, i32, i32, vp, vp, vp]
         L.matcha_grad_template.argtypes = [vp, bp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
-        for name in ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_coeff_assemble",
-                     "matcha_soft_search", "matcha_march_newton", "matcha_evaluate", "matcha_grad_template"]:
+        L.matcha_lpt_order.argtypes = [bp, ct.POINTER(_MarchCfg), ct.POINTER(ct.c_int32)]
+        L.matcha_align_graph_create.argtypes = [vp, bp, vp, vp, vp, vp, ct.c_int, ct.POINTER(_SoftCfg),
+                                                ct.POINTER(_MarchCfg), vp, vp, vp, vp, ct.POINTER(vp)]
+        L.matcha_graph_launch.argtypes = [vp, vp]
+        L.matcha_graph_destroy.argtypes = [vp]
+        L.matcha_autotune.argtypes = [vp, bp, vp, ct.POINTER(_SoftCfg), ct.POINTER(_MarchCfg), vp, vp, vp, vp, i32,
+                                      ct.POINTER(_Tuning)]
+        for name in ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_set_tuning", "matcha_get_tuning",
+                     "matcha_lpt_order", "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton",
+                     "matcha_evaluate", "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch",
+                     "matcha_graph_destroy", "matcha_autotune"]:
             getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -124,6 +142,15 @@ class Context:
     def prepare(self, L_max: int, B: int = 0, n_grid: int = 0):
         _check(lib().matcha_prepare(self.handle, L_max, B, n_grid), "matcha_prepare")
 
+    def set_tuning(self, march_nc: int = 0, soft_threads: int = 0):
+        t = _Tuning(int(march_nc), int(soft_threads))
+        _check(lib().matcha_set_tuning(self.handle, ct.byref(t)), "matcha_set_tuning")
+
+    def get_tuning(self) -> dict:
+        t = _Tuning()
+        _check(lib().matcha_get_tuning(self.handle, ct.byref(t)), "matcha_get_tuning")
+        return {"march_nc": int(t.march_nc), "soft_threads": int(t.soft_threads)}
+
     def close(self):
         if self.handle:
             lib().matcha_destroy(self.handle)
@@ -152,6 +179,7 @@ class Batch:
     C_off_dev: torch.Tensor
     c_total: int
     f_total: int
+    order_dev: torch.Tensor | None = None
 
     @staticmethod
     def make(L: Sequence[int], R: Sequence[int], L_h: int, R_h: int, device="cuda", f_offset=None) -> "Batch":
@@ -183,7 +211,27 @@ class Batch:
         b.C_offset = self.C_off_dev.data_ptr()
         b.L_h = self.L_h
         b.R_h = self.R_h
+        b.order = self.order_dev.data_ptr() if self.order_dev is not None else None
         return b
+
+    def set_lpt_order(self, levels: Sequence[int], steps: int):
+        """Process particles longest-first in the march (uneven L_p)."""
+        cfg = _march_cfg(levels, steps)
+        order = np.zeros(self.n, dtype=np.int32)
+        bs = self.c_struct()
+        _check(lib().matcha_lpt_order(ct.byref(bs), ct.byref(cfg), order.ctypes.data_as(ct.POINTER(ct.c_int32))),
+               "matcha_lpt_order")
+        self.order_dev = torch.from_numpy(order).to(self.L_dev.device)
+        return order
+
+
+def _march_cfg(levels, steps, max_step=0.0, early_stop=False, tol_grad=1e-6, tol_step=1e-7, tol_rel=1e-7,
+               fp64_above=0):
+    lv = np.ascontiguousarray(levels, dtype=np.int32)
+    cfg = _MarchCfg(lv.ctypes.data_as(ct.POINTER(ct.c_int32)), len(lv), int(steps), float(max_step),
+                    int(early_stop), float(tol_grad), float(tol_step), float(tol_rel), int(fp64_above))
+    cfg._keep = lv  # the levels array must outlive the struct
+    return cfg
 
 
 def coeff_assemble(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch.Tensor,
@@ -216,15 +264,14 @@ def soft_search(ctx: Context, batch: Batch, C: torch.Tensor, B: int, n_grid: int
 def march_newton(ctx: Context, batch: Batch, C: torch.Tensor, levels: Sequence[int], steps: int,
                  cand: torch.Tensor, status: torch.Tensor, best: torch.Tensor | None = None,
                  best_idx: torch.Tensor | None = None, max_step: float = 0.0, early_stop: bool = False,
-                 tol_grad: float = 1e-6, tol_step: float = 1e-7, tol_rel: float = 1e-7, stream=None):
+                 tol_grad: float = 1e-6, tol_step: float = 1e-7, tol_rel: float = 1e-7, fp64_above: int = 0,
+                 stream=None):
     Kc = int(cand.shape[1])
     if best is None:
         best = torch.empty((batch.n, 4), dtype=torch.float32, device=C.device)
     if best_idx is None:
         best_idx = torch.empty(batch.n, dtype=torch.int32, device=C.device)
-    lv = np.ascontiguousarray(levels, dtype=np.int32)
-    cfg = _MarchCfg(lv.ctypes.data_as(ct.POINTER(ct.c_int32)), len(lv), int(steps), float(max_step),
-                    int(early_stop), float(tol_grad), float(tol_step), float(tol_rel))
+    cfg = _march_cfg(levels, steps, max_step, early_stop, tol_grad, tol_step, tol_rel, fp64_above)
     bs = batch.c_struct()
     _check(lib().matcha_march_newton(ctx.handle, ct.byref(bs), _ptr(C), ct.byref(cfg), Kc, _ptr(cand), _ptr(best),
                                      _ptr(best_idx), _ptr(status), ct.c_void_p(_stream(stream))),
@@ -232,28 +279,134 @@ def march_newton(ctx: Context, batch: Batch, C: torch.Tensor, levels: Sequence[i
     return best, best_idx, status
 
 
-def evaluate(ctx: Context, batch: Batch, C: torch.Tensor, L_eval: int, theta: torch.Tensor, stream=None):
-    """Objective, gradient and Hessian (10 values) at one rotation per particle."""
+def evaluate(ctx: Context, batch: Batch, C: torch.Tensor, L_eval: int, theta: torch.Tensor, fp64_above: int = 0,
+             stream=None):
+    """Objective, gradient and Hessian (10 values) at one rotation per particle (L_eval = 0: each L_p)."""
     _need(theta, torch.float32, "theta")
     out = torch.empty((batch.n, 10), dtype=torch.float32, device=C.device)
     bs = batch.c_struct()
-    _check(lib().matcha_evaluate(ctx.handle, ct.byref(bs), _ptr(C), int(L_eval), _ptr(theta), _ptr(out),
+    _check(lib().matcha_evaluate(ctx.handle, ct.byref(bs), _ptr(C), int(L_eval), int(fp64_above), _ptr(theta), _ptr(out),
                                  ct.c_void_p(_stream(stream))), "matcha_evaluate")
     return out
 
 
+def workspace_bytes(batch: Batch, Kc: int = 0) -> int:
+    bs = batch.c_struct()
+    return int(lib().matcha_workspace_size(ct.byref(bs), int(Kc)))
+
+
+def grad_template(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch.Tensor,
+                  best: torch.Tensor, g: torch.Tensor, want_h: bool = True, want_f: bool = True, stream=None):
+    """Adjoint of sum_p g_p C_{L_p}(R_p*) at fixed rotations: (grad_h, grad_f), each None if not wanted.
+    Gradients are d/dRe + i d/dIm of the full complex arrays, as float32 views of complex pairs."""
+    _need(best, torch.float32, "best")
+    _need(g, torch.float32, "g")
+    gh = torch.empty_like(h) if want_h else None
+    gf = torch.empty_like(f) if want_f else None
+    ws = None
+    nbytes = 0
+    if want_h:
+        nbytes = workspace_bytes(batch)
+        ws = torch.empty(max(nbytes // 4, 1), dtype=torch.float32, device=f.device)
+    bs = batch.c_struct()
+    _check(lib().matcha_grad_template(ctx.handle, ct.byref(bs), _ptr(f), _ptr(h), _ptr(w), _ptr(best), _ptr(g),
+                                      _ptr(gh), _ptr(gf), _ptr(ws), nbytes, ct.c_void_p(_stream(stream))),
+           "matcha_grad_template")
+    return gh, gf
+
+
+class Objective(torch.autograd.Function):
+    """F_p = C_{L_p}(R_p*) for fixed rotations best[p]; backward through the hand-written adjoint.
+
+    forward(ctx_, batch, f, h, w, best) -> F [P]; f and h are float32 views of complex coefficients."""
+
+    @staticmethod
+    def forward(fctx, mctx: Context, batch: Batch, f, h, w, best):
+        C = coeff_assemble(mctx, batch, f.detach(), h.detach(), w)
+        out = evaluate(mctx, batch, C, 0, best.detach().contiguous())
+        fctx.save_for_backward(f.detach(), h.detach(), w, best.detach().contiguous())
+        fctx.mctx, fctx.batch = mctx, batch
+        return out[:, 0].clone()
+
+    @staticmethod
+    def backward(fctx, gF):
+        f, h, w, best = fctx.saved_tensors
+        gh, gf = grad_template(fctx.mctx, fctx.batch, f, h, w, best, gF.contiguous().float(),
+                               want_h=fctx.needs_input_grad[3], want_f=fctx.needs_input_grad[2])
+        return None, None, gf, gh, None, None
+
+
 def align(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch.Tensor, B: int, n_grid: int,
-          Kc: int, levels: Sequence[int], steps: int, max_step: float = 0.0, bufs: dict | None = None, stream=None):
+          Kc: int, levels: Sequence[int], steps: int, max_step: float = 0.0, fp64_above: int = 0,
+          bufs: dict | None = None, stream=None):
     """The whole path: assembly, SOFFT search, march and selection.  Returns (best, best_idx, status)."""
     b = {} if bufs is None else bufs
     C = coeff_assemble(ctx, batch, f, h, w, C=b.get("C"), stream=stream)
     cand, status = soft_search(ctx, batch, C, B, n_grid, Kc, cand=b.get("cand"), status=b.get("status"),
                                stream=stream)
     best, best_idx, status = march_newton(ctx, batch, C, levels, steps, cand, status, best=b.get("best"),
-                                          best_idx=b.get("best_idx"), max_step=max_step, stream=stream)
+                                          best_idx=b.get("best_idx"), max_step=max_step, fp64_above=fp64_above,
+                                          stream=stream)
     if bufs is not None:
         bufs.update(C=C, cand=cand, status=status, best=best, best_idx=best_idx)
     return best, best_idx, status
+
+
+class AlignGraph:
+    """The whole path (assembly, SOFFT search, march) for fixed buffers, captured once into a HIP
+    graph and replayed with one launch."""
+
+    def __init__(self, ctx: Context, batch: Batch, f, h, w, B: int, n_grid: int, Kc: int, levels, steps: int,
+                 prec: int = FP32, fp64_above: int = 0):
+        dev = f.device
+        self.bufs = dict(C=torch.empty(2 * batch.c_total, dtype=torch.float32, device=dev),
+                         cand=torch.empty((batch.n, Kc, 4), dtype=torch.float32, device=dev),
+                         status=torch.empty(batch.n, dtype=torch.int32, device=dev),
+                         best=torch.empty((batch.n, 4), dtype=torch.float32, device=dev),
+                         best_idx=torch.empty(batch.n, dtype=torch.int32, device=dev))
+        self._keep = (ctx, batch, f, h, w)
+        self._bs = batch.c_struct()
+        self._soft = _SoftCfg(B, n_grid, Kc)
+        self._march = _march_cfg(levels, steps, fp64_above=fp64_above)
+        g = ct.c_void_p()
+        b = self.bufs
+        _check(lib().matcha_align_graph_create(ctx.handle, ct.byref(self._bs), _ptr(f), _ptr(h), _ptr(w), _ptr(b["C"]),
+                                               prec, ct.byref(self._soft), ct.byref(self._march), _ptr(b["cand"]),
+                                               _ptr(b["best"]), _ptr(b["best_idx"]), _ptr(b["status"]), ct.byref(g)),
+               "matcha_align_graph_create")
+        self.handle = g
+
+    def launch(self, stream=None):
+        _check(lib().matcha_graph_launch(self.handle, ct.c_void_p(_stream(stream))), "matcha_graph_launch")
+        return self.bufs["best"], self.bufs["best_idx"], self.bufs["status"]
+
+    def close(self):
+        if self.handle:
+            lib().matcha_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune(ctx: Context, batch: Batch, C: torch.Tensor, B: int, n_grid: int, Kc: int, levels, steps: int,
+             reps: int = 2, fp64_above: int = 0) -> dict:
+    """Times the supported launch shapes on this batch and keeps the fastest in the context."""
+    dev = C.device
+    cand = torch.empty((batch.n, Kc, 4), dtype=torch.float32, device=dev)
+    status = torch.empty(batch.n, dtype=torch.int32, device=dev)
+    best = torch.empty((batch.n, 4), dtype=torch.float32, device=dev)
+    best_idx = torch.empty(batch.n, dtype=torch.int32, device=dev)
+    soft = _SoftCfg(B, n_grid, Kc)
+    march = _march_cfg(levels, steps, fp64_above=fp64_above)
+    t = _Tuning()
+    bs = batch.c_struct()
+    _check(lib().matcha_autotune(ctx.handle, ct.byref(bs), _ptr(C), ct.byref(soft), ct.byref(march), _ptr(cand),
+                                 _ptr(best), _ptr(best_idx), _ptr(status), int(reps), ct.byref(t)), "matcha_autotune")
+    return {"march_nc": int(t.march_nc), "soft_threads": int(t.soft_threads)}
 
 
 # ------------------------------------------------------------ layout helpers

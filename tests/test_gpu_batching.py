@@ -1,0 +1,97 @@
+"""Batched execution: HIP-graph replay, launch-shape tuning and longest-first ordering must not
+change any result (every kernel is deterministic, so results are compared bit for bit)."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2603_15285_amd import synth as S  # noqa: E402
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2603_15285_amd import matcha
+    matcha.lib()
+    return matcha
+
+
+@pytest.fixture(scope="module")
+def ctx(M):
+    c = M.Context(0)
+    yield c
+    c.close()
+
+
+def upload(M, b):
+    batch = M.Batch.make(b.L, b.R, b.L_h, b.R_h, f_offset=b.f_offset)
+    f = torch.from_numpy(b.f_flat.astype(np.complex64).view(np.float32).copy()).cuda()
+    h = torch.from_numpy(b.h.astype(np.complex64).view(np.float32).reshape(-1).copy()).cuda()
+    w = torch.from_numpy(b.w.astype(np.float32)).cuda()
+    return batch, f, h, w
+
+
+def eager(M, ctx, batch, f, h, w, wl):
+    best, bi, st = M.align(ctx, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps)
+    torch.cuda.synchronize()
+    return best.clone(), bi.clone(), st.clone()
+
+
+def test_graph_replays_match_eager(M, ctx):
+    wl = S.WORKLOADS["L32_R32_B12_K16"]
+    b1 = S.make_workload("L32_R32_B12_K16", n_particles=64)
+    b2 = S.make_workload("L32_R32_B12_K16", n_particles=64, seed_offset=1)
+    batch, f, h, w = upload(M, b1)
+    _, f2, _, _ = upload(M, b2)
+    ref1 = eager(M, ctx, batch, f, h, w, wl)
+    ref2 = eager(M, ctx, batch, f2, h, w, wl)
+    g = M.AlignGraph(ctx, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps)
+    f_orig = f.clone()
+    for rep in range(3):
+        if rep == 1:
+            f.copy_(f2)  # the graph reads its buffers at replay time
+        else:
+            f.copy_(f_orig)
+        eager(M, ctx, batch, f2, h, w, wl)  # unrelated eager work between replays
+        best, bi, st = g.launch()
+        torch.cuda.synchronize()
+        ref = ref2 if rep == 1 else ref1
+        assert torch.equal(best, ref[0]) and torch.equal(bi, ref[1]) and torch.equal(st, ref[2]), rep
+    g.close()
+
+
+def test_autotune_keeps_results(M):
+    c = M.Context(0)
+    wl = S.WORKLOADS["L32_R32_B12_K16"]
+    b = S.make_workload("L32_R32_B12_K16", n_particles=128)
+    batch, f, h, w = upload(M, b)
+    ref = eager(M, c, batch, f, h, w, wl)
+    C = M.coeff_assemble(c, batch, f, h, w)
+    t = M.autotune(c, batch, C, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
+    assert t["march_nc"] in (2, 4, 8) and t["soft_threads"] in (256, 512)
+    assert c.get_tuning() == t
+    got = eager(M, c, batch, f, h, w, wl)
+    for x, y in zip(got, ref):
+        assert torch.equal(x, y)
+    for nc in (2, 8):
+        c.set_tuning(nc, 256)
+        got = eager(M, c, batch, f, h, w, wl)
+        for x, y in zip(got, ref):
+            assert torch.equal(x, y)
+    c.close()
+
+
+def test_longest_first_order_keeps_results(M, ctx):
+    wl = S.WORKLOADS["uneven_L24to48"]
+    b = S.make_workload("uneven_L24to48", n_particles=48)
+    batch, f, h, w = upload(M, b)
+    ref = eager(M, ctx, batch, f, h, w, wl)
+    order = batch.set_lpt_order(wl.levels, wl.steps)
+    assert sorted(order.tolist()) == list(range(48))
+    Ls = b.L[order]
+    assert np.all(np.diff(Ls) <= 0)  # longer bands (more work) first
+    got = eager(M, ctx, batch, f, h, w, wl)
+    for x, y in zip(got, ref):
+        assert torch.equal(x, y)

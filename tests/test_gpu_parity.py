@@ -252,3 +252,80 @@ def test_empty_batch_and_invalid_arguments(M, ctx):
     best, bi, st = M.march_newton(ctx, batch, C, [4, 8], 0, cand, status)  # zero steps: select only
     torch.cuda.synchronize()
     assert 0 <= int(bi[0]) < 4
+
+
+# ---------------------------------------------------------------- precision modes
+def to_bf16(M, x_complex):
+    t = torch.from_numpy(np.ascontiguousarray(x_complex).astype(np.complex64).view(np.float32).reshape(-1).copy())
+    return t.to(torch.bfloat16).cuda()
+
+
+def test_assembly_bf16_matches_rounded_oracle(M, ctx):
+    """BF16 inputs on the matrix cores: against the oracle on the same BF16-rounded inputs; the
+    kernel rounds w_r h once more to BF16, so each product may differ by 2^-8 relative."""
+    b = S.make_batch(32, 32, 3, seed=21, snr=0.1, L_per=[32, 17, 5], R_per=[32, 9, 3])
+    batch, _, _, w = upload(M, b)
+    parts = [b.f(p).reshape(-1) for p in range(3)]
+    f16 = to_bf16(M, np.concatenate(parts))
+    h16 = to_bf16(M, b.h)
+    C = M.coeff_assemble(ctx, batch, f16, h16, w, prec=M.BF16_FP32ACC).cpu().numpy().view(np.complex64)
+    fr = f16.float().cpu().numpy().view(np.complex64)
+    hr = h16.float().cpu().numpy().view(np.complex64).reshape(b.h.shape).astype(np.complex128)
+    for p in range(3):
+        Lp, Rp = int(b.L[p]), int(b.R[p])
+        o = int(batch.f_offset[p])
+        fp = fr[o: o + Rp * (Lp + 1) ** 2].reshape(Rp, -1).astype(np.complex128)
+        ref = O.coeff_assemble(Lp, Rp, fp, Lp, hr, b.L_h, b.w)
+        bound = O.coeff_assemble(Lp, Rp, np.abs(fp), Lp, np.abs(hr), b.L_h, b.w).real  # sum_r w |f| |h|
+        Cw = C[batch.C_offset[p]: batch.C_offset[p] + M.c_elems(Lp)].reshape(-1, 2)
+        l, m, n, pm, pn = M.wedge_index(Lp)
+        i0, i1 = M.canonical_at(l, m, n), M.canonical_at(l, pm, pn)
+        assert np.all(np.abs(Cw[:, 0] - ref[i0]) <= 2 ** -7 * bound[i0] + 1e-6 * np.abs(ref).max())
+        assert np.all(np.abs(Cw[:, 1] - ref[i1]) <= 2 ** -7 * bound[i1] + 1e-6 * np.abs(ref).max())
+
+
+def test_batched_bf16_path_within_005_degree_of_fp64_oracle(M, ctx):
+    wl = S.WORKLOADS["L32_R32_B12_K16"]
+    b = S.make_workload("L32_R32_B12_K16", n_particles=8)
+    batch, _, _, w = upload(M, b)
+    f16 = to_bf16(M, b.f_flat)
+    h16 = to_bf16(M, b.h)
+    C = M.coeff_assemble(ctx, batch, f16, h16, w, prec=M.BF16_FP32ACC)
+    cand, status = M.soft_search(ctx, batch, C, wl.B, wl.n_grid, wl.Kc)
+    best, _, _ = M.march_newton(ctx, batch, C, wl.levels, wl.steps, cand, status)
+    best = best.cpu().numpy().astype(np.float64)
+    ob, obi, ost, ocand = O.align_batch(b, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps)
+    for p in range(8):
+        top = np.sort(ocand[p, :, 3])[::-1]
+        if top[0] - top[1] <= 1e-5 * scale(b, p, 32):
+            continue
+        assert rot_err(best[p, :3], ob[p, :3]) <= 0.05
+
+
+def test_fp64_recurrence_above_40(M, ctx):
+    """Levels above degree 40 with the FP64 recurrence: objective parity and the march."""
+    b = S.make_batch(48, 24, 2, seed=1048, snr=0.1)
+    batch, f, h, w = upload(M, b)
+    C = M.coeff_assemble(ctx, batch, f, h, w)
+    rng = np.random.default_rng(48)
+    for th in [S.haar_euler(rng, 1)[0], np.array([1.0, 0.05, 2.0])]:
+        theta = torch.tensor(np.tile(np.r_[th, 0.0], (2, 1)), dtype=torch.float32).cuda()
+        out = M.evaluate(ctx, batch, C, 48, theta, fp64_above=40).cpu().numpy().astype(np.float64)
+        th32 = theta[0, :3].cpu().numpy().astype(np.float64)
+        for p in range(2):
+            ref = O.evaluate(48, oracle_C(b, p), th32)
+            Sc = scale(b, p, 48)
+            assert abs(out[p, 0] - ref[0]) <= 1e-5 * Sc
+            assert np.abs(out[p, 1:4] - ref[1:4]).max() <= 1e-5 * Sc * 49
+            assert np.abs(out[p, 4:] - ref[4:]).max() <= 1e-5 * Sc * 49 ** 2
+    wl = S.WORKLOADS["uneven_L24to48"]
+    bu = S.make_batch(48, 48, 3, seed=93, snr=(0.05, 0.2), L_per=[33, 44, 48], R_per=[33, 44, 48])
+    batch, f, h, w = upload(M, bu)
+    best, _, _ = M.align(ctx, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, fp64_above=40)
+    best = best.cpu().numpy().astype(np.float64)
+    ob, obi, ost, ocand = O.align_batch(bu, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps)
+    for p in range(3):
+        top = np.sort(ocand[p, :, 3])[::-1]
+        if top[0] - top[1] <= 1e-5 * scale(bu, p, int(bu.L[p])):
+            continue
+        assert rot_err(best[p, :3], ob[p, :3]) <= 1e-3

@@ -128,7 +128,7 @@ typedef struct {
 
 /* Launch shapes.  Zero fields mean "library default".  march_nc: candidates per wavefront
  * of the march kernel (1, 2, 4 or 8; a workgroup holds ceil(Kc / march_nc) <= 8 waves).
- * soft_threads: threads per SOFFT workgroup (256, 512 or 1024). */
+ * soft_threads: threads per SOFFT workgroup (256 or 512). */
 typedef struct {
     int32_t march_nc;
     int32_t soft_threads;

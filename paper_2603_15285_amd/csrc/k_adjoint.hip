@@ -26,7 +26,6 @@ __global__ void __launch_bounds__(kAdjThreads) k_grad_particle(GradArgs a)
     const int p = blockIdx.x;
     const int L = a.Lp[p], R = a.Rp[p];
     const int Lmax = a.L_max;
-    const int W = 2 * L + 1;
     float *dm = reinterpret_cast<float *>(smem_raw);                    // [(2Lmax+1)^2]
     float2 *ea = reinterpret_cast<float2 *>(dm + (2 * Lmax + 1) * (2 * Lmax + 1));  // [Lmax+1] e^{i k a}
     float2 *eg = ea + (Lmax + 1);                                        // [Lmax+1] e^{i k c}

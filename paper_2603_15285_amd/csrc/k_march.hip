@@ -122,7 +122,7 @@ template <>
 struct Coef<double> {
     __device__ static void get(const float4, const double2 *t64, int row, uint32_t lb, double &A, double &AC)
     {
-        const double2 c = ld_row(t64, row, 2 * lb);
+        const double2 c = ld_row(t64, row, lb);  // one 16-byte (A, AC) per pair, like tab
         A = c.x;
         AC = c.y;
     }

@@ -284,7 +284,7 @@ matcha_status matcha_set_tuning(matcha_ctx *ctx, const matcha_tuning *t)
     const int nc = t->march_nc;
     if (nc != 0 && nc != 1 && nc != 2 && nc != 4 && nc != 8) return MATCHA_ERR_INVALID_ARG;
     const int st = t->soft_threads;
-    if (st != 0 && st != 256 && st != 512 && st != 1024) return MATCHA_ERR_INVALID_ARG;
+    if (st != 0 && st != 256 && st != 512) return MATCHA_ERR_INVALID_ARG;
     ctx->tune = *t;
     return MATCHA_OK;
 }
@@ -391,7 +391,8 @@ matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, con
     if (!C || !cand || !status || !aligned16(C) || !aligned16(cand)) return MATCHA_ERR_INVALID_ARG;
     const int B = cfg->B, n = cfg->n_grid, Kc = cfg->Kc;
     if (B < 1 || B > lo || B > 32 || n < 4 || n > 96 || Kc < 1 || Kc > MATCHA_MAX_KC) return MATCHA_ERR_INVALID_ARG;
-    if (soft_smem_bytes(n, B) > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
+    const int nt = ctx->tune.soft_threads ? ctx->tune.soft_threads : 256;
+    if (soft_smem_bytes(n, B, nt) > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
     st = ensure_tables(ctx, std::max(hi, B));
     if (st != MATCHA_OK) return st;
     st = ensure_grid(ctx, B, n);
@@ -407,7 +408,6 @@ matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, con
     a.Kc = Kc;
     a.cand = reinterpret_cast<float4 *>(cand);
     a.status = status;
-    const int nt = ctx->tune.soft_threads ? ctx->tune.soft_threads : 512;
     return launched(launch_soft(a, batch->n_particles, nt, static_cast<hipStream_t>(stream)));
 }
 
@@ -646,6 +646,10 @@ matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const 
         ctx->tune.soft_threads = nt;
         float ms = 0.f;
         st = time_it([&] { return matcha_soft_search(ctx, batch, C, soft, cand, status, s); }, &ms);
+        if (st == MATCHA_ERR_UNSUPPORTED) {  // this shape does not fit the workgroup's LDS
+            st = MATCHA_OK;
+            continue;
+        }
         if (st != MATCHA_OK) break;
         if (ms < best_ms) {
             best_ms = ms;

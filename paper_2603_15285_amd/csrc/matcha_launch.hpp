@@ -100,7 +100,7 @@ hipError_t launch_assemble_f32(const AsmArgs &a, int P, int Lmax, int Rmax, hipS
 size_t assemble_bf16_smem_bytes(int Lmax, int Rmax);
 hipError_t launch_assemble_bf16(const AsmBArgs &a, int P, int Lmax, int Rmax, hipStream_t s);
 
-size_t soft_smem_bytes(int n, int B);
+size_t soft_smem_bytes(int n, int B, int threads);
 hipError_t launch_soft(const SoftArgs &a, int P, int threads, hipStream_t s);
 
 size_t march_smem_any(int Kc, int nc);

@@ -329,3 +329,31 @@ def test_fp64_recurrence_above_40(M, ctx):
         if top[0] - top[1] <= 1e-5 * scale(bu, p, int(bu.L[p])):
             continue
         assert rot_err(best[p, :3], ob[p, :3]) <= 1e-3
+
+
+def test_uneven_full_size_sampled(M, ctx):
+    """8192 particles with L_p in 24..48 (shells = L_p), longest-first order, FP64 recurrence
+    above degree 40, in one launch per step; the oracle recomputes sampled particles."""
+    wl = S.WORKLOADS["uneven_L24to48"]
+    b = S.make_workload("uneven_L24to48")
+    batch, f, h, w = upload(M, b)
+    batch.set_lpt_order(wl.levels, wl.steps)
+    best, _, status = M.align(ctx, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, fp64_above=40)
+    best = best.cpu().numpy().astype(np.float64)
+    sample = [int(np.argmax(b.L)), int(np.argmin(b.L)), 4321]
+    ob, obi, ost, ocand = O.align_batch(b, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps, particles=sample)
+    n_cmp = 0
+    for t, p in enumerate(sample):
+        top = np.sort(ocand[t, :, 3])[::-1]
+        if top[0] - top[1] <= 1e-5 * scale(b, p, int(b.L[p])):
+            continue
+        assert rot_err(best[p, :3], ob[t, :3]) <= 1e-3, (p, int(b.L[p]))
+        n_cmp += 1
+    assert n_cmp >= 1
+
+
+def test_large_band_L64_shapes(M, ctx):
+    """L = 64, 64 shells, SOFFT at B = 16 on a 64^3 grid, 32 candidates, 16 -> 64 x 2 steps."""
+    wl = S.WORKLOADS["L64_R64_B16_K32"]
+    b = S.make_workload("L64_R64_B16_K32", n_particles=2)
+    compare_align(M, ctx, b, wl, [0, 1])

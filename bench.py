@@ -5,6 +5,7 @@ march and selection -- over one batch of synthetic particles already resident in
 Prints one JSON line (see the fields below).
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -42,6 +43,74 @@ def march_flops_per_particle(levels, L, steps, Kc):
     return Kc * f
 
 
+# HBM traffic of k_march, from two rocprofv3 counter passes (FETCH_SIZE, WRITE_SIZE) over
+# `bench.py --pmc-probe`, scaled by the same counters on a copy of known size.  Only used while
+# the kernel's sources are the ones the counters were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_L32_R32_B12_K16_hbm_traffic.txt")
+MARCH_SOURCES = ["paper_2603_15285_amd/csrc/k_march.hip", "paper_2603_15285_amd/csrc/matcha_dev.hpp",
+                 "paper_2603_15285_amd/csrc/matcha_launch.hpp"]
+
+
+def march_source_digest():
+    h = hashlib.sha256()
+    for rel in MARCH_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_march_traffic(workload):
+    """Bytes per k_march launch, or None when no summary matches this workload and source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    fields = {}
+    with open(TRAFFIC_FILE) as fh:
+        for line in fh:
+            if ":" in line and not line.startswith(" "):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+    if fields.get("workload") != workload or fields.get("kernel_source_sha256") != march_source_digest():
+        return None
+    try:
+        return float(fields["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def pmc_probe(args):
+    """One device copy of known size (the counters' scale reference), then one pass of the batched
+    path on the bench workload with the default launch shapes; prints no JSON line."""
+    import torch
+
+    from paper_2603_15285_amd import matcha as M
+    from paper_2603_15285_amd import synth as S
+
+    torch.cuda.set_device(0)
+    nbytes = 1 << 30
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    src.fill_(1.0)  # writes nbytes
+    dst = torch.empty_like(src)
+    dst.copy_(src)  # reads nbytes, writes nbytes
+    torch.cuda.synchronize()
+    del src, dst
+    print(f"reference: fill then copy of {nbytes} bytes", flush=True)
+    wl = S.WORKLOADS[args.workload]
+    b = S.make_workload(args.workload, n_particles=args.particles)
+    ctx = M.Context(0)
+    ctx.prepare(int(b.L.max()), wl.B, wl.n_grid)
+    batch = M.Batch.make(b.L, b.R, b.L_h, b.R_h, f_offset=b.f_offset)
+    f = torch.from_numpy(b.f_flat.astype(np.complex64).view(np.float32)).cuda()
+    h = torch.from_numpy(b.h.astype(np.complex64).view(np.float32).reshape(-1)).cuda()
+    w = torch.from_numpy(b.w.astype(np.float32)).cuda()
+    if int(b.L.max()) != int(b.L.min()):
+        batch.set_lpt_order(wl.levels, wl.steps)
+    fp64_above = 40 if int(b.L.max()) > 40 else 0
+    best, _, _ = M.align(ctx, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, fp64_above=fp64_above)
+    torch.cuda.synchronize()
+    print(f"probe pass done: {b.n_particles} particles, march source {march_source_digest()}", flush=True)
+    ctx.close()
+
+
 def cpu_baseline(b, wl, budget_s=15.0):
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -69,11 +138,16 @@ def main():
     ap.add_argument("--plain", type=int, default=32, help="particles timed on the one-particle path")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="run the counter probe (reference copy + one pass) instead of the benchmark")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); particles shard across GPUs "
               "with no exchange in the forward path, so run one process per GPU.", file=sys.stderr)
         sys.exit(2)
+    if args.pmc_probe:
+        pmc_probe(args)
+        return
 
     import torch
 
@@ -185,6 +259,7 @@ def main():
     log(f"batched bf16: {bf16_value:.0f} particles/s")
 
     flops = sum(march_flops_per_particle(wl.levels, int(Lp), wl.steps, wl.Kc) for Lp in b.L)
+    traffic = measured_march_traffic(wl.name) if args.particles is None else None
     achieved = flops / (ms_march / 1e3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
@@ -195,7 +270,8 @@ def main():
                    "newton_steps_per_level": wl.steps, "snr": list(wl.snr) if isinstance(wl.snr, tuple) else wl.snr},
         "roofline": {"kernel": "k_march (frequency march: value, gradient, Hessian, Newton, selection)",
                      "bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": None, "ms_per_launch": ms_march},
+                     "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": traffic, "traffic_unit": "bytes/launch",
+                     "ms_per_launch": ms_march},
         "plain": {"value": plain_value, "unit": "particles/s", "particles": n_plain},
         "batched_over_plain": value / plain_value,
         "batched_bf16": {"value": bf16_value, "unit": "particles/s", "over_plain": bf16_value / plain_value,

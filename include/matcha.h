@@ -170,19 +170,24 @@ matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg
 matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
                                     const float *w, float *C, matcha_precision prec, void *stream);
 
-/* SOFFT search at band B (Sec. 2.3; Alg. 1 lines 1-2): evaluates C_B on the
+/* SOFFT search at band B (Sec. 2.3; the search step of Alg. 1): evaluates C_B on the
  * n_grid^3 grid (Wigner-d transform over l, then a 2-D inverse DFT over (a, c)),
  * finds the nodes that beat all 26 neighbours (a, c periodic; b neighbours outside
  * the grid absent; equal values: the smaller linear index i n^2 + j n + k wins),
  * ranks them by (value desc, index asc) and writes the first Kc to cand
  * [P][Kc] float4 (a_j, b_i, c_k, value).  With fewer than Kc maxima the list is
  * filled with the best remaining nodes and MATCHA_ST_FEW_MAXIMA is set.
- * status [P] is overwritten.  Requires 1 <= B <= min_p L_p, 4 <= n_grid <= 256,
- * 1 <= Kc <= MATCHA_MAX_KC. */
+ * status [P] is overwritten.  Requires 1 <= B <= min_p L_p, B <= 32, 4 <= n_grid <= 96,
+ * 1 <= Kc <= MATCHA_MAX_KC (MATCHA_ERR_UNSUPPORTED if the shape does not fit a workgroup's LDS).
+ * The grid passes through a workspace owned by the context (n_grid^3 floats per particle,
+ * at most 2 GiB; larger batches run in chunks of particles), allocated on first need and
+ * grown synchronously; calls on one context must not overlap in time (use one stream per
+ * context).  matcha_align_graph_create gives each graph a workspace of its own. */
 matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
                                  const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream);
 
-/* Frequency-marched Newton refinement and selection (Alg. 1 lines 3-8, Sec. 2.2):
+/* Frequency-marched Newton refinement and selection (the march and selection steps of
+ * Alg. 1, Sec. 2.2):
  * for every candidate, M_iter Newton steps theta <- theta - H^{-1} grad C_L on
  * each level of the particle's schedule, the 3x3 system inverted explicitly in
  * FP64; then C_{L_p} at each final point, and the candidate with the largest value

@@ -353,7 +353,7 @@ unsigned mo_newton_step(const double *e, double max_step, double *th, double *st
 /* ------------------------------------------------------------ march + select
  * Alg. 1: from the retained candidates, M_iter Newton steps on C_{L_j} at every
  * cutoff of the schedule (the first cutoff is the SOFFT band L0, i.e. the
- * optional refinement of line 3), then the candidate with the largest C_{L_J} at
+ * optional refinement at the search band), then the candidate with the largest C_{L_J} at
  * its final point.  The per-particle schedule is the global one with every
  * cutoff >= Lp dropped and Lp appended (cutoffs above L_max are skipped, Sec. 4.1).
  * Early stopping (Sec. 2.4) is optional: at a level, stop stepping once

@@ -379,14 +379,14 @@ __device__ void wave_reduce(float (&acc)[NC][10], WaveScratch<NC> &ws, WaveState
             x += __shfl_xor(x, 16);
             if (lane < 16) ws.red[c * NV + v][lane] = x;
         }
-    __syncthreads();
+    wave_sync();
     for (int v = lane; v < NC * NV; v += kWave) {
         const float4 *row = reinterpret_cast<const float4 *>(ws.red[v]);
         const float4 x0 = row[0], x1 = row[1], x2 = row[2], x3 = row[3];
         st.tot[v / NV][v % NV] = ((x0.x + x0.y) + (x0.z + x0.w)) + ((x1.x + x1.y) + (x1.z + x1.w)) +
                                  (((x2.x + x2.y) + (x2.z + x2.w)) + ((x3.x + x3.y) + (x3.z + x3.w)));
     }
-    __syncthreads();
+    wave_sync();
 }
 
 __device__ inline double wrap2pi(double x)
@@ -448,7 +448,7 @@ __device__ void prepare_step(WaveState<NC> &st, WaveScratch<NC> &ws, int L, int 
     if (lane < NC) st.bc[lane] = beta_const(st.th[lane][1]);
 #pragma unroll
     for (int c = 0; c < NC; ++c) fill_phases(st.th[c][0], st.th[c][2], L, ws.ph.ea[c], ws.ph.eg[c], lane);
-    __syncthreads();
+    wave_sync();
 }
 
 template <int NC>
@@ -521,7 +521,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))
                     }
                 }
             }
-            __syncthreads();
+            wave_sync();
         }
     }
     // value at the final points on the last level, then selection

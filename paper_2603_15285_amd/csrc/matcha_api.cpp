@@ -22,8 +22,11 @@ struct matcha_ctx {
     double2 *tab64 = nullptr;  // (A, AC) of tab in FP64
     PairInfo *pinfo = nullptr;
     matcha_tuning tune{0, 0};
-    int grid_B = -1, grid_n = -1;  // the SOFFT node table below is for (grid_B, grid_n)
+    int grid_B = -1, grid_n = -1;  // the SOFFT node tables below are for (grid_B, grid_n)
     float2 *dgrid = nullptr;
+    float2 *etab = nullptr;         // [(B+1) n] e^{i m a_j}, then [n] e^{2 pi i t / n}
+    float *soft_ws = nullptr;       // SOFFT grid workspace of the eager calls
+    size_t soft_ws_bytes = 0;
 };
 
 namespace {
@@ -163,25 +166,79 @@ void build_grid_table(int B, int n, std::vector<float2> &g)
     }
 }
 
+// Phase factors of the SOFFT grid's DFT: e^{i m a_j} with a_j = 2 pi j / n for m <= B, then the
+// twiddles e^{2 pi i t / n}; each angle is reduced exactly as (m j mod n) / n.
+void build_phase_table(int B, int n, std::vector<float2> &e)
+{
+    e.assign((size_t)((B + 1) * n + n), make_float2(0.f, 0.f));
+    for (int m = 0; m <= B; ++m)
+        for (int j = 0; j < n; ++j) {
+            const double x = 2.0 * M_PI * (double)((m * j) % n) / n;
+            e[(size_t)(m * n + j)] = make_float2((float)std::cos(x), (float)std::sin(x));
+        }
+    for (int t = 0; t < n; ++t) {
+        const double x = 2.0 * M_PI * t / n;
+        e[(size_t)((B + 1) * n + t)] = make_float2((float)std::cos(x), (float)std::sin(x));
+    }
+}
+
 matcha_status ensure_grid(matcha_ctx *ctx, int B, int n)
 {
     if (ctx->dgrid && ctx->grid_B == B && ctx->grid_n == n) return MATCHA_OK;
-    std::vector<float2> g;
+    std::vector<float2> g, e;
     build_grid_table(B, n, g);
+    build_phase_table(B, n, e);
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    float2 *d = nullptr;
+    float2 *d = nullptr, *de = nullptr;
     if (hipMalloc(&d, g.size() * sizeof(float2)) != hipSuccess) return MATCHA_ERR_HIP;
-    if (hipMemcpy(d, g.data(), g.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMalloc(&de, e.size() * sizeof(float2)) != hipSuccess) {
         (void)hipFree(d);
+        return MATCHA_ERR_HIP;
+    }
+    if (hipMemcpy(d, g.data(), g.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(de, e.data(), e.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(d);
+        (void)hipFree(de);
         return MATCHA_ERR_HIP;
     }
     if (ctx->dgrid) {
         (void)hipDeviceSynchronize();
         (void)hipFree(ctx->dgrid);
+        (void)hipFree(ctx->etab);
     }
     ctx->dgrid = d;
+    ctx->etab = de;
     ctx->grid_B = B;
     ctx->grid_n = n;
+    return MATCHA_OK;
+}
+
+// The SOFFT grid of a particle (n^3 floats) lives in a workspace between the two kernels;
+// batches whose grids exceed kSoftWsCap run in chunks of particles.
+constexpr size_t kSoftWsCap = (size_t)2 << 30;
+
+size_t soft_ws_need(int P, int n)
+{
+    const size_t per = (size_t)n * n * n * sizeof(float);
+    const size_t pc = std::max<size_t>(1, std::min<size_t>((size_t)P, kSoftWsCap / per));
+    return pc * per;
+}
+
+matcha_status ensure_soft_ws(matcha_ctx *ctx, size_t bytes)
+{
+    if (ctx->soft_ws_bytes >= bytes) return MATCHA_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    if (ctx->soft_ws) {
+        (void)hipDeviceSynchronize();  // earlier searches may still read it
+        (void)hipFree(ctx->soft_ws);
+        ctx->soft_ws = nullptr;
+        ctx->soft_ws_bytes = 0;
+    }
+    if (hipMalloc(&ctx->soft_ws, bytes) != hipSuccess) {
+        ctx->soft_ws = nullptr;
+        return MATCHA_ERR_HIP;
+    }
+    ctx->soft_ws_bytes = bytes;
     return MATCHA_OK;
 }
 
@@ -249,10 +306,12 @@ matcha_status matcha_destroy(matcha_ctx *ctx)
         (void)hipFree(ctx->tab64);
         (void)hipFree(ctx->pinfo);
     }
-    if (ctx->dgrid) {
+    if (ctx->dgrid || ctx->soft_ws) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->dgrid);
+        if (ctx->dgrid) (void)hipFree(ctx->dgrid);
+        if (ctx->etab) (void)hipFree(ctx->etab);
+        if (ctx->soft_ws) (void)hipFree(ctx->soft_ws);
     }
     delete ctx;
     return MATCHA_OK;
@@ -332,6 +391,8 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
     if (batch->n_particles == 0) return MATCHA_OK;
     if (!f || !h || !w || !C || !batch->f_offset || !aligned16(C)) return MATCHA_ERR_INVALID_ARG;
     if (prec != MATCHA_FP32 && prec != MATCHA_BF16_FP32ACC) return MATCHA_ERR_UNSUPPORTED;
+    // the kernels index within one particle's f and within h with 32-bit offsets
+    if ((int64_t)batch->R_h * (batch->L_h + 1) * (batch->L_h + 1) >= INT32_MAX) return MATCHA_ERR_UNSUPPORTED;
     const size_t smem = prec == MATCHA_FP32 ? assemble_smem_bytes(hi, rmax) : assemble_bf16_smem_bytes(hi, rmax);
     if (smem > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
@@ -380,8 +441,13 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
     return launched(launch_assemble_f32(a, batch->n_particles, hi, rmax, static_cast<hipStream_t>(stream)));
 }
 
-matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
-                                 const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Checks of a SOFFT search; on success *nt is the select kernel's workgroup size.
+matcha_status soft_check(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *cfg,
+                         const float *cand, const uint32_t *status, int *nt)
 {
     int lo, hi, rmax;
     if (!ctx || !cfg) return MATCHA_ERR_INVALID_ARG;
@@ -391,24 +457,58 @@ matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, con
     if (!C || !cand || !status || !aligned16(C) || !aligned16(cand)) return MATCHA_ERR_INVALID_ARG;
     const int B = cfg->B, n = cfg->n_grid, Kc = cfg->Kc;
     if (B < 1 || B > lo || B > 32 || n < 4 || n > 96 || Kc < 1 || Kc > MATCHA_MAX_KC) return MATCHA_ERR_INVALID_ARG;
-    const int nt = ctx->tune.soft_threads ? ctx->tune.soft_threads : 256;
-    if (soft_smem_bytes(n, B, nt) > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
+    *nt = ctx->tune.soft_threads ? ctx->tune.soft_threads : 256;
+    if (soft_grid_smem_bytes(n, B) > 160 * 1024 || soft_select_smem_bytes(n, *nt) > 160 * 1024)
+        return MATCHA_ERR_UNSUPPORTED;
     st = ensure_tables(ctx, std::max(hi, B));
     if (st != MATCHA_OK) return st;
-    st = ensure_grid(ctx, B, n);
-    if (st != MATCHA_OK) return st;
+    return ensure_grid(ctx, B, n);
+}
+
+// The search proper over a grid workspace ws of ws_bytes (at least one particle's grid).
+matcha_status soft_search_ws(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *cfg,
+                             float *cand, uint32_t *status, int nt, float *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int P = batch->n_particles, n = cfg->n_grid;
+    const size_t per = (size_t)n * n * n * sizeof(float);
+    if (!ws || ws_bytes < per) return MATCHA_ERR_INVALID_ARG;
+    const int pc = (int)std::min<size_t>((size_t)P, ws_bytes / per);
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     SoftArgs a;
     a.C = reinterpret_cast<const float4 *>(C);
     a.C_off = batch->C_offset;
     a.dgrid = ctx->dgrid;
+    a.etab = ctx->etab;
     a.pinfo = ctx->pinfo;
-    a.B = B;
+    a.B = cfg->B;
     a.n = n;
-    a.Kc = Kc;
+    a.Kc = cfg->Kc;
+    a.grid = ws;
     a.cand = reinterpret_cast<float4 *>(cand);
     a.status = status;
-    return launched(launch_soft(a, batch->n_particles, nt, static_cast<hipStream_t>(stream)));
+    for (int p0 = 0; p0 < P; p0 += pc) {
+        const int cnt = std::min(pc, P - p0);
+        a.p0 = p0;
+        if (launch_soft_grid(a, cnt, s) != hipSuccess) return MATCHA_ERR_HIP;
+        if (launch_soft_select(a, cnt, nt, s) != hipSuccess) return MATCHA_ERR_HIP;
+    }
+    return MATCHA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
+                                 const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream)
+{
+    int nt = 0;
+    matcha_status st = soft_check(ctx, batch, C, cfg, cand, status, &nt);
+    if (st != MATCHA_OK || batch->n_particles == 0) return st;
+    st = ensure_soft_ws(ctx, soft_ws_need(batch->n_particles, cfg->n_grid));
+    if (st != MATCHA_OK) return st;
+    return soft_search_ws(ctx, batch, C, cfg, cand, status, nt, ctx->soft_ws, ctx->soft_ws_bytes,
+                          static_cast<hipStream_t>(stream));
 }
 
 matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
@@ -548,6 +648,8 @@ matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg
 struct matcha_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    float *soft_ws = nullptr;  // the graph's own SOFFT grid workspace (the context's may be regrown)
+    int device = 0;
 };
 
 matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
@@ -562,38 +664,43 @@ matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *bat
     // build every table now: nothing may allocate while the stream is being captured
     st = ensure_tables(ctx, std::max(hi, soft->B));
     if (st != MATCHA_OK) return st;
-    if (soft->B >= 1 && soft->n_grid >= 4) {
-        st = ensure_grid(ctx, soft->B, soft->n_grid);
-        if (st != MATCHA_OK) return st;
-    }
+    int nt = 0;
+    st = soft_check(ctx, batch, C, soft, cand, status, &nt);
+    if (st != MATCHA_OK) return st;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    hipStream_t cs = nullptr;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return MATCHA_ERR_HIP;
     matcha_graph *g = new (std::nothrow) matcha_graph();
-    if (!g) {
-        (void)hipStreamDestroy(cs);
+    if (!g) return MATCHA_ERR_HIP;
+    g->device = ctx->device;
+    const int P = batch->n_particles;
+    const size_t ws_bytes = P > 0 ? soft_ws_need(P, soft->n_grid) : 0;
+    if (P > 0 && hipMalloc(&g->soft_ws, ws_bytes) != hipSuccess) {
+        delete g;
         return MATCHA_ERR_HIP;
     }
-    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    auto fail = [&](matcha_status e) {
+        if (g->soft_ws) (void)hipFree(g->soft_ws);
         delete g;
+        return e;
+    };
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(MATCHA_ERR_HIP);
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipStreamDestroy(cs);
-        return MATCHA_ERR_HIP;
+        return fail(MATCHA_ERR_HIP);
     }
     st = matcha_coeff_assemble(ctx, batch, f, h, w, C, prec, cs);
-    if (st == MATCHA_OK) st = matcha_soft_search(ctx, batch, C, soft, cand, status, cs);
+    if (st == MATCHA_OK && P > 0) st = soft_search_ws(ctx, batch, C, soft, cand, status, nt, g->soft_ws, ws_bytes, cs);
     if (st == MATCHA_OK) st = matcha_march_newton(ctx, batch, C, march, soft->Kc, cand, best, best_idx, status, cs);
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &graph);
     (void)hipStreamDestroy(cs);
     if (st != MATCHA_OK || ec != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
-        delete g;
-        return st != MATCHA_OK ? st : MATCHA_ERR_HIP;
+        return fail(st != MATCHA_OK ? st : MATCHA_ERR_HIP);
     }
     if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGraphDestroy(graph);
-        delete g;
-        return MATCHA_ERR_HIP;
+        return fail(MATCHA_ERR_HIP);
     }
     g->graph = graph;
     *out = g;
@@ -611,6 +718,11 @@ matcha_status matcha_graph_destroy(matcha_graph *g)
     if (!g) return MATCHA_ERR_INVALID_ARG;
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->soft_ws) {
+        (void)hipSetDevice(g->device);
+        (void)hipDeviceSynchronize();  // replays may still read it
+        (void)hipFree(g->soft_ws);
+    }
     delete g;
     return MATCHA_OK;
 }

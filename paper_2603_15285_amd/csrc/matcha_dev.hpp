@@ -98,6 +98,16 @@ __device__ inline void edge_seed_d(int m, int n, double lbh2, const BetaConst &k
     d2 = e * (h1 * h1 + h2);
 }
 
+// Orders the LDS accesses of one wave's lanes.  A wave's LDS operations complete in issue
+// order, so only the compiler must be kept from moving accesses across this point; waves of
+// the same workgroup do not wait for each other.
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ inline float bcast(float x) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(x))); }
 
 __device__ inline float2 cmul(float2 a, float2 b) { return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }

@@ -36,8 +36,12 @@ struct SoftArgs {
     const float4 *C;
     const int64_t *C_off;
     const float2 *dgrid;      // [n][wedge_row(B+1)]: weighted d^l(b_i) of each wedge pair and its partner
+    const float2 *etab;       // [(B+1) n] e^{i m a_j}, then [n] e^{2 pi i t / n}
     const PairInfo *pinfo;
     int B, n, Kc;
+    int gslices;              // polar nodes per workgroup of the grid kernel (set by its launcher)
+    int p0;                   // first particle of this launch
+    float *grid;              // [launch particles][n][n][n] workspace: C_B on the grid
     float4 *cand;
     uint32_t *status;
 };
@@ -100,8 +104,10 @@ hipError_t launch_assemble_f32(const AsmArgs &a, int P, int Lmax, int Rmax, hipS
 size_t assemble_bf16_smem_bytes(int Lmax, int Rmax);
 hipError_t launch_assemble_bf16(const AsmBArgs &a, int P, int Lmax, int Rmax, hipStream_t s);
 
-size_t soft_smem_bytes(int n, int B, int threads);
-hipError_t launch_soft(const SoftArgs &a, int P, int threads, hipStream_t s);
+size_t soft_grid_smem_bytes(int n, int B);
+size_t soft_select_smem_bytes(int n, int threads);
+hipError_t launch_soft_grid(const SoftArgs &a, int P, hipStream_t s);
+hipError_t launch_soft_select(const SoftArgs &a, int P, int threads, hipStream_t s);
 
 size_t march_smem_any(int Kc, int nc);
 hipError_t launch_march_any(const MarchArgs &a, int P, int nc, hipStream_t s);

@@ -47,15 +47,21 @@ def march_flops_per_particle(levels, L, steps, Kc):
 # `bench.py --pmc-probe`, scaled by the same counters on a copy of known size.  Only used while
 # the kernel's sources are the ones the counters were taken on.
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_march_L32_R32_B12_K16_hbm_traffic.txt")
-MARCH_SOURCES = ["paper_2603_15285_amd/csrc/k_march.hip", "paper_2603_15285_amd/csrc/matcha_dev.hpp",
-                 "paper_2603_15285_amd/csrc/matcha_launch.hpp"]
+MARCH_SOURCES = ["paper_2603_15285_amd/csrc/k_march.hip", "paper_2603_15285_amd/csrc/matcha_dev.hpp"]
+LAUNCH_HEADER = "paper_2603_15285_amd/csrc/matcha_launch.hpp"
 
 
 def march_source_digest():
+    """SHA-256 over the march kernel's source, the device header and the MarchArgs block of the
+    launch header (the other kernels' argument blocks do not reach the march)."""
     h = hashlib.sha256()
     for rel in MARCH_SOURCES:
         with open(os.path.join(ROOT, rel), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(ROOT, LAUNCH_HEADER)) as fh:
+        text = fh.read()
+    i = text.index("struct MarchArgs {")
+    h.update(text[i:text.index("};", i) + 2].encode())
     return h.hexdigest()
 
 

@@ -24,8 +24,8 @@ template <int NC>
 struct __align__(16) WaveScratch {
     union {
         struct {
-            float2 ea[NC][kMaxL + 1];  // e^{i k a_c}
-            float2 eg[NC][kMaxL + 1];  // e^{i k c_c}
+            float2 ea[NC][kMaxL + 1];      // e^{i k a_c}, k = 0 .. L
+            float2 eg[NC][2 * kMaxL + 1];  // e^{i k c_c} at kMaxL + k, k = -L .. L
         } ph;
         float red[10 * NC][16];
     };
@@ -41,15 +41,19 @@ struct WaveState {
     float fprev[NC];
 };
 
-__device__ inline void fill_phases(double a, double c, int L, float2 *ea, float2 *eg, int lane)
+// Inlined into its callers so that ea / eg are addressed as LDS, never through generic pointers.
+__device__ __forceinline__ void fill_phases(double a, double c, int L, float2 *ea, float2 *eg, int lane)
 {
     for (int k = lane; k <= L; k += kWave) {
-        double ta = fmod((double)k * a, kTwoPi), tc = fmod((double)k * c, kTwoPi);
+        // k a reduced to [-pi, pi] in FP64 (exact enough for |k a| < 1e6), then sin / cos in FP32
+        const double xa = (double)k * a, xc = (double)k * c;
+        const double ta = fma(-kTwoPi, rint(xa * (1.0 / kTwoPi)), xa), tc = fma(-kTwoPi, rint(xc * (1.0 / kTwoPi)), xc);
         float sa, ca, sc, cc;
         sincosf((float)ta, &sa, &ca);
         sincosf((float)tc, &sc, &cc);
         ea[k] = make_float2(ca, sa);
-        eg[k] = make_float2(cc, sc);
+        eg[kMaxL + k] = make_float2(cc, sc);
+        eg[kMaxL - k] = make_float2(cc, -sc);
     }
 }
 
@@ -155,8 +159,8 @@ __device__ inline double bcastT<double>(double x)
 
 // Sum over all wedge pairs of one level for the NC candidates c0 .. c0+NC-1 of a wave that owns
 // NCW.  acc[c0+c][0..9] receive the (positive-sign, undoubled) sums described at the top of the
-// file; with DERIV == false only acc[.][0] (the value) is formed.  T is the arithmetic of the
-// recurrence and the l-sums.
+// file, the b-b sum (7) from D''/2, i.e. halved; with DERIV == false only acc[.][0] (the value)
+// is formed.  T is the arithmetic of the recurrence and the l-sums.
 template <int NC, int NCW, bool DERIV, typename T>
 __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restrict__ tab,
                            const double2 *__restrict__ tab64, const PairInfo *__restrict__ pinfo, int L,
@@ -184,7 +188,7 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         const int m = pi.m, n = pi.n;
         // lane 0 holds the tile's smallest m, the last valid lane its largest
         const int mlo = __builtin_amdgcn_readfirstlane(m);
-        const int mhi = __shfl(m, min(npairs - 1 - q0, kWave - 1));
+        const int mhi = __builtin_amdgcn_readfirstlane(__shfl(m, min(npairs - 1 - q0, kWave - 1)));
 
         // edge values of every lane's pair, computed once per tile without divergence
         T sd0[NC], sd1[NC], sd2[NC];
@@ -305,18 +309,14 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         }
         if (!valid) continue;
         // phases and the m, n weights of the a / c derivatives
-        const int an = n >= 0 ? n : -n;
+        const int an = n >= 0 ? n : -n, b2i = n >= 0 ? m : -m;
         const float a1 = (float)m, b1 = (float)n;
-        const float a2 = n >= 0 ? (float)n : (float)(-n), b2 = n >= 0 ? (float)m : (float)(-m);
+        const float a2 = (float)an, b2 = (float)b2i;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const int cw = c0 + c;
             const float2 am = ws.ph.ea[cw][m], aN = ws.ph.ea[cw][an];
-            float2 gm = ws.ph.eg[cw][m], gN = ws.ph.eg[cw][an];
-            if (n < 0) {
-                gN = cconj(gN);
-                gm = cconj(gm);
-            }
+            const float2 gN = ws.ph.eg[cw][kMaxL + n], gm = ws.ph.eg[cw][kMaxL + b2i];
             const float2 p1 = cmul(am, gN);  // e^{i(m a + n c)}
             const float2 p2 = cmul(aN, gm);  // e^{i(a2 a + b2 c)}
             float u[NU];
@@ -332,8 +332,8 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
                 const float I1 = p1.x * u[5] + p1.y * u[4];
                 const float T1 = p2.x * u[6] - p2.y * u[7];
                 const float J1 = p2.x * u[7] + p2.y * u[6];
-                const float R2 = 2.f * (p1.x * u[8] - p1.y * u[9]);
-                const float T2 = 2.f * (p2.x * u[10] - p2.y * u[11]);
+                const float R2 = p1.x * u[8] - p1.y * u[9];  // half of the D'' terms (D''/2 is carried)
+                const float T2 = p2.x * u[10] - p2.y * u[11];
                 acc[cw][1] += a1 * I0 + a2 * J0;
                 acc[cw][2] += R1 + T1;
                 acc[cw][3] += b1 * I0 + b2 * J0;
@@ -442,8 +442,10 @@ __device__ uint32_t newton_step(const double *e, double max_step, double *th, do
     return st;
 }
 
+// Inlined into the kernels: the wave state and scratch are then addressed as LDS (a generic
+// pointer formed as base - offset can leave the shared aperture when the base sits at LDS 0).
 template <int NC>
-__device__ void prepare_step(WaveState<NC> &st, WaveScratch<NC> &ws, int L, int lane)
+__device__ __forceinline__ void prepare_step(WaveState<NC> &st, WaveScratch<NC> &ws, int L, int lane)
 {
     if (lane < NC) st.bc[lane] = beta_const(st.th[lane][1]);
 #pragma unroll
@@ -498,7 +500,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))
                 e[4] = -2.0 * tv[4];
                 e[5] = -2.0 * tv[5];
                 e[6] = -2.0 * tv[6];
-                e[7] = 2.0 * tv[7];
+                e[7] = 4.0 * tv[7];  // the b-b sum is accumulated from D''/2
                 e[8] = -2.0 * tv[8];
                 e[9] = -2.0 * tv[9];
                 bool stop = false;
@@ -572,7 +574,8 @@ __global__ void __launch_bounds__(64) k_evaluate(EvalArgs a)
     eval_level_any<1, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
     wave_reduce<1, 10>(acc, ws, st, lane);
     if (lane < 10) {
-        const float sgn = (lane == 0 || lane == 2 || lane == 7) ? 2.f : -2.f;
+        // signs and factors of the 10 sums; the b-b sum is accumulated from D''/2
+        const float sgn = lane == 7 ? 4.f : ((lane == 0 || lane == 2) ? 2.f : -2.f);
         a.out[(int64_t)p * 10 + lane] = sgn * st.tot[0][lane];
     }
 }

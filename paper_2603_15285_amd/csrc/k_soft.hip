@@ -10,42 +10,77 @@
 // the nodes come from a table shared by all particles), then the 2-D inverse DFT over (a, c):
 // first T[m][k] = sum_n S[m, n] e^{i n c_k}, then g[j][k] = 2 Re sum_m T[m][k] e^{i m a_j}.
 //
-// k_soft_select takes one particle per workgroup and streams its grid slice by slice through an
-// LDS ring of three slices (the next one is prefetched into registers meanwhile); the middle
-// slice is tested for local maxima against its 26 neighbours.  Maxima enter an LDS list of
-// 64-bit keys (ordered value, inverted linear index) that is sorted and cut to the Kc best now
-// and then, so the final ranking is exact whatever order the nodes arrive in.  Once Kc maxima
-// are known, the Kc-th best key is a threshold: a node below it is dropped after one compare,
-// which is the fate of almost every node of the later slices.
+// k_soft_maxima takes a particle and 8 consecutive polar nodes per workgroup and streams their
+// slices (with one neighbour slice on each side) through an LDS ring of three; every node is
+// tested for a local maximum against its 26 neighbours (six axis neighbours first, then the
+// exact test), and each maximum's 64-bit key (ordered value, inverted linear index) is appended
+// to the particle's list in the workspace.
+//
+// k_soft_rank takes one particle per workgroup, sorts its list and writes the Kc best keys, so
+// the ranking is exact whatever order the maxima arrived in.  A particle whose list overflowed,
+// or that has fewer than Kc maxima, takes the streaming path instead: its grid goes slice by
+// slice through an LDS ring, the maxima enter an LDS key list that is sorted and cut to the Kc
+// best now and then, and once Kc maxima are known the Kc-th best key is a threshold below which
+// a node is dropped after one compare; a second sweep ranks the best non-maxima when there are
+// fewer than Kc maxima.
 #include "matcha_launch.hpp"
+
+#include <algorithm>
 
 namespace matcha {
 
 // ---------------------------------------------------------------- grid synthesis
-constexpr int kGridThreads = 256;
+//
+// Per polar node the 2-D inverse DFT is two real products on the matrix cores
+// (v_mfma_f32_16x16x4_f32: lane i supplies A[i%16][i/16] and B[i/16][i%16] of a 16 x 4 x 16 step
+// and holds D rows 4(i/16) .. +3 of column i%16):
+//   stage 1  T = S B1:  A = S with (Re, Im) interleaved along K = 2(n+B) + c, B1r / B1i the
+//            twiddles of e^{i n c_k} in the matching real form, giving Re T and Im T;
+//   stage 2  g = A2 T':  A2[j][2m + c] = 2 cos(m a_j) / -2 sin(m a_j), T'[2m + c][k] = Re / Im T.
+// S and T' live in the wave's own LDS; B1 and A2 are host-built tables read through the caches.
+constexpr int kGridSPW = 3;  // polar nodes per wave
 
-__host__ __device__ inline size_t soft_grid_smem(int n, int B, int G)
+struct GridGeom {
+    int MT;   // 16-row tiles of m (B+1 rows)
+    int KP;   // stage-1 K, 2(2B+1) padded to a multiple of 4
+    int NP;   // k (and j) padded to a multiple of 16
+    int K2R;  // rows of T' held: 32 MT (two per m)
+    int KS2;  // stage-2 K steps: ceil(2(B+1) / 4)
+};
+
+__host__ __device__ inline GridGeom grid_geom(int n, int B)
 {
-    const size_t SW = (size_t)(B + 1) * (2 * B + 1), TW = (size_t)(B + 1) * n;
-    return sizeof(float2) * (G * SW + G * TW + TW + n);
+    GridGeom g;
+    g.MT = (B + 16) / 16;
+    g.KP = 4 * ((2 * (2 * B + 1) + 3) / 4);
+    g.NP = 16 * ((n + 15) / 16);
+    g.K2R = 32 * g.MT;
+    g.KS2 = (2 * (B + 1) + 3) / 4;
+    return g;
 }
 
-// Polar nodes per workgroup: four when their LDS fits 64 KB (two or more workgroups per CU),
-// else fewer.
-inline int soft_grid_slices(int n, int B)
+__host__ __device__ inline int grid_wave_floats(const GridGeom &g) { return 16 * g.MT * g.KP + g.K2R * g.NP; }
+
+__host__ __device__ inline size_t soft_grid_smem(int n, int B, int waves)
 {
-    for (int G : {4, 2})
-        if (soft_grid_smem(n, B, G) <= 64 * 1024) return G;
+    return sizeof(float) * (size_t)waves * grid_wave_floats(grid_geom(n, B));
+}
+
+// Waves per workgroup: four when their LDS fits 64 KB, else fewer.
+inline int soft_grid_waves(int n, int B)
+{
+    for (int w : {4, 2})
+        if (soft_grid_smem(n, B, w) <= 64 * 1024) return w;
     return 1;
 }
 
-// S_i for the pairs of one task: S[pair] = sum_l C^l_pair dg0^l_pair(b_i), S[partner] = sum_l
-// C^l_partner dg1^l_pair(b_i).  Entries (0, n < 0) are never written and stay zero.  Four
-// degrees per trip keep eight independent loads in flight.
+// S_i for one wedge pair into the interleaved rows of Sf (row stride KP):
+// S[pair] = sum_l C^l_pair dg0^l_pair(b_i), S[partner] = sum_l C^l_partner dg1^l_pair(b_i).
+// Entries (0, n < 0) are never written and stay zero.  Four degrees per trip keep eight
+// independent loads in flight.
 __device__ inline void wigner_pair(const float4 *__restrict__ Cp, const float2 *__restrict__ dg, const PairInfo &pi,
-                                   int q, int B, float2 *S)
+                                   int q, int B, int KP, float *Sf)
 {
-    const int W = 2 * B + 1;
     const int m = pi.m, n = pi.n;
     float2 u0 = make_float2(0.f, 0.f), u1 = u0;
     int row = (int)wedge_row(m) + q;
@@ -81,107 +116,106 @@ __device__ inline void wigner_pair(const float4 *__restrict__ Cp, const float2 *
         u1.x = fmaf(cc.z, d.y, u1.x);
         u1.y = fmaf(cc.w, d.y, u1.y);
     }
-    S[m * W + n + B] = u0;
+    Sf[m * KP + 2 * (n + B)] = u0.x;
+    Sf[m * KP + 2 * (n + B) + 1] = u0.y;
     if (n != m && n != -m) {  // diagonal pairs are their own partners
         const int a2 = n >= 0 ? n : -n, b2 = n >= 0 ? m : -m;
-        S[a2 * W + b2 + B] = u1;
+        Sf[a2 * KP + 2 * (b2 + B)] = u1.x;
+        Sf[a2 * KP + 2 * (b2 + B) + 1] = u1.y;
     }
 }
 
-__global__ void __launch_bounds__(kGridThreads) k_soft_grid(SoftArgs a)
-{
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int B = a.B, N = a.n, W = 2 * B + 1;
-    const int SW = (B + 1) * W, TW = (B + 1) * N;
-    const int G = a.gslices;
-    const int NG = (N + G - 1) / G;
-    const int pl = blockIdx.x / NG, i0 = (blockIdx.x - pl * NG) * G;
-    const int ni = min(G, N - i0);
-    const int p = a.p0 + pl;
-    float2 *S = reinterpret_cast<float2 *>(smem_raw);  // [G][SW]
-    float2 *T = S + G * SW;                             // [G][TW]
-    float2 *E = T + G * TW;                             // [TW] e^{i m a_j}, then [N] twiddles
-    const float2 *tw = E + TW;
-    const float4 *Cp = a.C + a.C_off[p] / 2;
-    for (int t = threadIdx.x; t < TW + N; t += kGridThreads) E[t] = a.etab[t];
-    for (int t = threadIdx.x; t < G * SW; t += kGridThreads) S[t] = make_float2(0.f, 0.f);
-    __syncthreads();
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+constexpr int kGridChunk = 8;  // K steps whose operands are loaded before their MFMAs
 
-    // Wigner-d transforms of the block's nodes
+__global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
+{
+    extern __shared__ __align__(16) float smem_f[];
+    const int B = a.B, N = a.n;
+    const GridGeom g = grid_geom(N, B);
+    const int WB = a.gslices;  // waves per workgroup
+    const int SB = WB * kGridSPW;
+    const int NG = (N + SB - 1) / SB;
+    const int pl = blockIdx.x / NG, ib = (blockIdx.x - pl * NG) * SB;
+    const int p = a.p0 + pl;
+    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+    const int col = lane % 16, kq = lane / 16;
+    float *Sf = smem_f + wave * grid_wave_floats(g);  // [16 MT][KP]
+    float *Tf = Sf + 16 * g.MT * g.KP;                // [K2R][NP]
+    const float *B1r = a.dft, *B1i = B1r + g.KP * g.NP, *A2 = B1i + g.KP * g.NP;
+    const int A2W = 4 * g.KS2;
+    const float4 *Cp = a.C + a.C_off[p] / 2;
+    if (ib == 0 && threadIdx.x == 0) a.mcount[pl] = 0u;  // the maxima kernel that follows appends from 0
     const int npairs = (B + 1) * (B + 1);
     const int64_t drow = wedge_row(B + 1);
-    for (int t = threadIdx.x; t < ni * npairs; t += kGridThreads) {
-        const int gi = t / npairs, q = t - gi * npairs;
-        wigner_pair(Cp, a.dgrid + (int64_t)(i0 + gi) * drow, a.pinfo[q], q, B, S + gi * SW);
-    }
-    __syncthreads();
-
-    // first DFT stage, three k per task; the twiddle index (n k) mod N advances incrementally
-    {
-        constexpr int KB = 3;
-        const int NKB = (N + KB - 1) / KB, per = (B + 1) * NKB;
-        for (int t = threadIdx.x; t < ni * per; t += kGridThreads) {
-            const int gi = t / per, tt = t - gi * per;
-            const int m = tt / NKB, kb = tt - m * NKB;
-            int k[KB], r[KB];
-            float2 acc[KB];
+    const int KS1 = g.KP / 4, NT = g.NP / 16;
+    for (int si = 0; si < kGridSPW; ++si) {
+        const int i = ib + wave * kGridSPW + si;  // the wave's polar node
+        if (i >= N) break;
+        for (int t = lane; t < 16 * g.MT * g.KP; t += kWave) Sf[t] = 0.f;
+        wave_sync();
+        for (int q = lane; q < npairs; q += kWave) wigner_pair(Cp, a.dgrid + i * drow, a.pinfo[q], q, B, g.KP, Sf);
+        wave_sync();
+        // stage 1: Re T and Im T, rows m, columns k
+        for (int tn = 0; tn < NT; ++tn)
+            for (int tm = 0; tm < g.MT; ++tm) {
+                f32x4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+                for (int s0 = 0; s0 < KS1; s0 += kGridChunk) {
+                    float av[kGridChunk], br[kGridChunk], bi[kGridChunk];
 #pragma unroll
-            for (int u = 0; u < KB; ++u) {
-                k[u] = min(KB * kb + u, N - 1);
-                r[u] = (N - (B * k[u]) % N) % N;
-                acc[u] = make_float2(0.f, 0.f);
-            }
-            const float2 *Sm = S + gi * SW + m * W;
-            for (int nn = 0; nn < W; ++nn) {
-                const float2 sv = Sm[nn];
+                    for (int s = 0; s < kGridChunk; ++s) {
+                        if (s0 + s < KS1) {
+                            const int kk = 4 * (s0 + s) + kq;
+                            av[s] = Sf[(16 * tm + col) * g.KP + kk];
+                            br[s] = B1r[kk * g.NP + 16 * tn + col];
+                            bi[s] = B1i[kk * g.NP + 16 * tn + col];
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int u = 0; u < KB; ++u) {
-                    const float2 e = tw[r[u]];
-                    acc[u].x = fmaf(sv.x, e.x, fmaf(-sv.y, e.y, acc[u].x));
-                    acc[u].y = fmaf(sv.x, e.y, fmaf(sv.y, e.x, acc[u].y));
-                    r[u] += k[u];
-                    if (r[u] >= N) r[u] -= N;
+                    for (int s = 0; s < kGridChunk; ++s) {
+                        if (s0 + s < KS1) {
+                            cr = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], br[s], cr, 0, 0, 0);
+                            ci = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bi[s], ci, 0, 0, 0);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int m = 16 * tm + 4 * kq + v;
+                    Tf[(2 * m) * g.NP + 16 * tn + col] = cr[v];
+                    Tf[(2 * m + 1) * g.NP + 16 * tn + col] = ci[v];
                 }
             }
-            float2 *Tm = T + gi * TW + m * N;
+        wave_sync();
+        // stage 2: g[j][k] = sum_K A2[j][K] T'[K][k], straight to the workspace
+        float *out = a.grid + ((int64_t)pl * N + i) * N * N;
+        for (int tj = 0; tj < NT; ++tj)
+            for (int tk = 0; tk < NT; ++tk) {
+                f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+                for (int s0 = 0; s0 < g.KS2; s0 += kGridChunk) {
+                    float av[kGridChunk], bv[kGridChunk];
 #pragma unroll
-            for (int u = 0; u < KB; ++u)
-                if (KB * kb + u < N) Tm[KB * kb + u] = acc[u];
-        }
-    }
-    __syncthreads();
-
-    // second stage, a 6 (j) x 2 (k) block per task, straight to the workspace
-    {
-        constexpr int JB = 6, KB = 2;
-        const int NJ = (N + JB - 1) / JB, NK = (N + KB - 1) / KB, per = NJ * NK;
-        for (int t = threadIdx.x; t < ni * per; t += kGridThreads) {
-            const int gi = t / per, tt = t - gi * per;
-            const int jb = tt / NK, kb = tt - jb * NK;
-            const int j0 = JB * jb, k0 = KB * kb, k1 = min(k0 + 1, N - 1);
-            const float2 *Tg = T + gi * TW;
-            float g[JB][KB];
+                    for (int s = 0; s < kGridChunk; ++s) {
+                        if (s0 + s < g.KS2) {
+                            const int kk = 4 * (s0 + s) + kq;
+                            av[s] = A2[(16 * tj + col) * A2W + kk];
+                            bv[s] = Tf[kk * g.NP + 16 * tk + col];
+                        }
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int r = 0; r < JB; ++r) g[r][0] = g[r][1] = 0.f;
-            for (int m = 0; m <= B; ++m) {
-                const float2 x0 = Tg[m * N + k0], x1 = Tg[m * N + k1];
-                const float2 *Em = E + m * N;
+                    for (int s = 0; s < kGridChunk; ++s)
+                        if (s0 + s < g.KS2) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bv[s], acc, 0, 0, 0);
+                }
+                const int k = 16 * tk + col;
 #pragma unroll
-                for (int r = 0; r < JB; ++r) {
-                    const float2 e = Em[min(j0 + r, N - 1)];
-                    g[r][0] = fmaf(x0.x, e.x, fmaf(-x0.y, e.y, g[r][0]));
-                    g[r][1] = fmaf(x1.x, e.x, fmaf(-x1.y, e.y, g[r][1]));
+                for (int v = 0; v < 4; ++v) {
+                    const int j = 16 * tj + 4 * kq + v;
+                    if (j < N && k < N) out[j * N + k] = acc[v];
                 }
             }
-            float *out = a.grid + ((int64_t)pl * N + i0 + gi) * N * N;
-#pragma unroll
-            for (int r = 0; r < JB; ++r) {
-                if (j0 + r < N) {
-                    out[(j0 + r) * N + k0] = 2.f * g[r][0];
-                    if (k0 + 1 < N) out[(j0 + r) * N + k0 + 1] = 2.f * g[r][1];
-                }
-            }
-        }
+        wave_sync();  // the next node overwrites S and T'
     }
 }
 
@@ -267,7 +301,8 @@ __device__ void compact_list(SoftSmem &sm, int Kc)
 // larger key (ordered value bits, then the smaller linear index).  The wrapped row and column
 // offsets are formed once; the index is consulted only on equal value bits.
 template <int NT>
-__device__ bool beats_all(const SoftArgs &a, const SoftSmem &sm, int i, int t, int pslot, int cslot, int nslot)
+__device__ __forceinline__ bool beats_all(const SoftArgs &a, const SoftSmem &sm, int i, int t, int pslot, int cslot,
+                                          int nslot)
 {
     const int N = a.n;
     const int j = t / N, k = t - (t / N) * N;
@@ -427,8 +462,145 @@ __device__ inline float4 key_to_cand(unsigned long long key, int N)
     return make_float4((float)(kTwoPi * j / N), (float)(kPi * (2.0 * i + 1.0) / (2.0 * N)), (float)(kTwoPi * k / N), v);
 }
 
+// ---------------------------------------------------------------- parallel maxima
+constexpr int kMaxThreads = 256;
+constexpr int kMaxSlices = 8;  // polar nodes tested per workgroup
+
+__host__ __device__ inline size_t soft_maxima_smem(int n) { return 3 * soft_align16(sizeof(float) * n * n); }
+
+// Appends the key of node t of slice ic to the particle's list if it beats its 26 neighbours.
+__device__ __forceinline__ void maxima_exact(const SoftArgs &a, const SoftSmem &sm, int pl, int ic, int t, int pslot, int cslot,
+                                    int nslot, float v)
+{
+    if (!beats_all<kMaxThreads>(a, sm, ic, t, pslot, cslot, nslot)) return;
+    const uint32_t slot = atomicAdd(a.mcount + pl, 1u);
+    if (slot < (uint32_t)a.mcap) a.mlist[(int64_t)pl * a.mcap + slot] = make_key(v, (uint32_t)(ic * a.n * a.n + t));
+}
+
+// Four nodes (j, k0 .. k0+3) of slice ic (n a multiple of 4): a node is a candidate when its
+// value is at least the largest of its six axis neighbours (absent slices count as -inf);
+// candidates take the exact test.
+__device__ __forceinline__ void maxima_quad(const SoftArgs &a, const SoftSmem &sm, int pl, int ic, int j, int k0, int pslot,
+                                   int cslot, int nslot)
+{
+    const int N = a.n;
+    const float *cur = sm.ring(cslot);
+    const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
+    const float4 c = *reinterpret_cast<const float4 *>(cur + j * N + k0);
+    const float4 up = *reinterpret_cast<const float4 *>(cur + jm * N + k0);
+    const float4 dn = *reinterpret_cast<const float4 *>(cur + jp * N + k0);
+    const float left = cur[j * N + (k0 == 0 ? N - 1 : k0 - 1)];
+    const float right = cur[j * N + (k0 + 4 == N ? 0 : k0 + 4)];
+    const float ninf = -__builtin_huge_valf();
+    float4 pv = make_float4(ninf, ninf, ninf, ninf), nv = pv;
+    if (pslot >= 0) pv = *reinterpret_cast<const float4 *>(sm.ring(pslot) + j * N + k0);
+    if (nslot >= 0) nv = *reinterpret_cast<const float4 *>(sm.ring(nslot) + j * N + k0);
+    const float vv[4] = {c.x, c.y, c.z, c.w}, uu[4] = {up.x, up.y, up.z, up.w}, dd[4] = {dn.x, dn.y, dn.z, dn.w};
+    const float ll[4] = {left, c.x, c.y, c.z}, rr[4] = {c.y, c.z, c.w, right};
+    const float pp[4] = {pv.x, pv.y, pv.z, pv.w}, qq[4] = {nv.x, nv.y, nv.z, nv.w};
+    unsigned cand = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const float mx = fmaxf(fmaxf(fmaxf(uu[q], dd[q]), fmaxf(ll[q], rr[q])), fmaxf(pp[q], qq[q]));
+        cand |= (vv[q] >= mx ? 1u : 0u) << q;
+    }
+    while (cand) {  // rare: candidates take the exact test
+        const int q = __builtin_ctz(cand);
+        cand &= cand - 1;
+        const float v = q == 0 ? c.x : (q == 1 ? c.y : (q == 2 ? c.z : c.w));
+        maxima_exact(a, sm, pl, ic, j * N + k0 + q, pslot, cslot, nslot, v);
+    }
+}
+
+__global__ void __launch_bounds__(kMaxThreads) k_soft_maxima(SoftArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int N = a.n, NN = N * N;
+    const int NG = (N + kMaxSlices - 1) / kMaxSlices;
+    const int pl = blockIdx.x / NG, i0 = (blockIdx.x - pl * NG) * kMaxSlices;
+    const int i1 = min(i0 + kMaxSlices, N);  // tests slices i0 .. i1-1
+    const bool quads = (N & 3) == 0;         // rows split into float4 quads (slices 16-byte aligned)
+    SoftSmem sm;
+    sm.ring0 = reinterpret_cast<float *>(smem_raw);
+    sm.plane = (int)(soft_align16(sizeof(float) * NN) / sizeof(float));
+    const float *grid = a.grid + (int64_t)pl * N * NN;
+    constexpr int PER = (kSelMaxN * kSelMaxN / 4 + kMaxThreads - 1) / kMaxThreads;
+    const int NQ = NN / 4, QR = N / 4;  // quads per slice and per row
+    // slice s lives in ring slot s mod 3; each slice's loads are all in flight before the stores
+    for (int s = max(i0 - 1, 0); s <= min(i0 + 1, N - 1); ++s) {
+        const float *src = grid + (int64_t)s * NN;
+        float *dst = sm.ring(s % 3);
+        if (quads) {
+            float4 v[PER];
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int t = threadIdx.x + u * kMaxThreads;
+                v[u] = t < NQ ? reinterpret_cast<const float4 *>(src)[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+#pragma unroll
+            for (int u = 0; u < PER; ++u) {
+                const int t = threadIdx.x + u * kMaxThreads;
+                if (t < NQ) reinterpret_cast<float4 *>(dst)[t] = v[u];
+            }
+        } else {
+            for (int t = threadIdx.x; t < NN; t += kMaxThreads) dst[t] = src[t];
+        }
+    }
+    __syncthreads();
+    for (int ic = i0; ic < i1; ++ic) {
+        // slice ic+2 is needed when slice ic+1 is tested here; it is read as float4 quads, or as
+        // single values when n is not a multiple of 4
+        const bool pre = ic + 1 < i1 && ic + 2 < N;
+        const float *src = grid + (int64_t)(ic + 2) * NN;
+        float4 nxt[PER];
+        const bool preq = pre && quads;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int t = threadIdx.x + u * kMaxThreads;
+            nxt[u] = (preq && t < NQ) ? reinterpret_cast<const float4 *>(src)[t] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        const int pslot = ic >= 1 ? (ic - 1) % 3 : -1;
+        const int cslot = ic % 3;
+        const int nslot = ic + 1 < N ? (ic + 1) % 3 : -1;
+        if (quads) {
+            for (int qd = threadIdx.x; qd < NQ; qd += kMaxThreads) {
+                const int j = qd / QR, k0 = 4 * (qd - (qd / QR) * QR);
+                maxima_quad(a, sm, pl, ic, j, k0, pslot, cslot, nslot);
+            }
+        } else {
+            const float *cur = sm.ring(cslot);
+            for (int t = threadIdx.x; t < NN; t += kMaxThreads) {
+                const float v = cur[t];
+                const int j = t / N, k = t - (t / N) * N;
+                const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
+                const int km = k == 0 ? N - 1 : k - 1, kp = k == N - 1 ? 0 : k + 1;
+                float mx = fmaxf(fmaxf(cur[jm * N + k], cur[jp * N + k]), fmaxf(cur[j * N + km], cur[j * N + kp]));
+                if (pslot >= 0) mx = fmaxf(mx, sm.ring(pslot)[t]);
+                if (nslot >= 0) mx = fmaxf(mx, sm.ring(nslot)[t]);
+                if (v >= mx) maxima_exact(a, sm, pl, ic, t, pslot, cslot, nslot, v);
+            }
+        }
+        __syncthreads();
+        if (pre) {
+            float *dst = sm.ring((ic + 2) % 3);
+            if (quads) {
+#pragma unroll
+                for (int u = 0; u < PER; ++u) {
+                    const int t = threadIdx.x + u * kMaxThreads;
+                    if (t < NQ) reinterpret_cast<float4 *>(dst)[t] = nxt[u];
+                }
+            } else {
+                for (int t = threadIdx.x; t < NN; t += kMaxThreads) dst[t] = src[t];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Ranking of one particle's maxima (fast path), or the streaming search when its list
+// overflowed or holds fewer than Kc keys.  The list capacity a.mcap equals list_cap<NT>().
 template <int NT>
-__global__ void __launch_bounds__(NT) k_soft_select(SoftArgs a)
+__global__ void __launch_bounds__(NT) k_soft_rank(SoftArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     __shared__ unsigned long long s_thresh;
@@ -443,6 +615,18 @@ __global__ void __launch_bounds__(NT) k_soft_select(SoftArgs a)
     sm.nmax = &s_nmax;
     sm.overflow = &s_overflow;
     const int pl = blockIdx.x, p = a.p0 + pl;
+    const uint32_t cnt = a.mcount[pl];
+    if (cnt >= (uint32_t)Kc && cnt <= (uint32_t)a.mcap) {
+        int sz = 2;
+        while (sz < (int)cnt) sz <<= 1;
+        const unsigned long long *src = a.mlist + (int64_t)pl * a.mcap;
+        for (int t = threadIdx.x; t < sz; t += NT) sm.list[t] = t < (int)cnt ? src[t] : 0ull;
+        __syncthreads();
+        sort_list_desc<NT>(sm, sz);
+        for (int t = threadIdx.x; t < Kc; t += NT) a.cand[(int64_t)p * Kc + t] = key_to_cand(sm.list[t], N);
+        if (threadIdx.x == 0) a.status[p] = 0u;
+        return;
+    }
     const float *grid = a.grid + (int64_t)pl * N * N * N;
     if (threadIdx.x == 0) {
         (*sm.count) = 0;
@@ -459,7 +643,7 @@ __global__ void __launch_bounds__(NT) k_soft_select(SoftArgs a)
     for (int t = threadIdx.x; t < nm; t += NT) a.cand[(int64_t)p * Kc + t] = key_to_cand(sm.list[t], N);
     __syncthreads();
     if (nmax < Kc) {
-        // rare: fill with the best nodes that are not local maxima (second sweep)
+        // fill with the best nodes that are not local maxima (second sweep)
         if (threadIdx.x == 0) {
             (*sm.count) = 0;
             (*sm.thresh) = 0ull;
@@ -473,26 +657,68 @@ __global__ void __launch_bounds__(NT) k_soft_select(SoftArgs a)
 }
 
 size_t soft_grid_smem_bytes(int n, int B) { return soft_grid_smem(n, B, 1); }
-size_t soft_select_smem_bytes(int n, int threads) { return soft_select_smem(n, 2 * threads); }
+
+size_t soft_select_smem_bytes(int n, int threads)
+{
+    return std::max(soft_select_smem(n, 2 * threads), soft_maxima_smem(n));
+}
 
 hipError_t launch_soft_grid(const SoftArgs &a0, int P, hipStream_t s)
 {
     SoftArgs a = a0;
-    a.gslices = soft_grid_slices(a.n, a.B);
-    const int NG = (a.n + a.gslices - 1) / a.gslices;
-    hipLaunchKernelGGL(k_soft_grid, dim3(P * NG), dim3(kGridThreads), soft_grid_smem(a.n, a.B, a.gslices), s, a);
+    a.gslices = soft_grid_waves(a.n, a.B);
+    const int SB = a.gslices * kGridSPW;
+    const int NG = (a.n + SB - 1) / SB;
+    hipLaunchKernelGGL(k_soft_grid, dim3(P * NG), dim3(kWave * a.gslices), soft_grid_smem(a.n, a.B, a.gslices), s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_soft_select(const SoftArgs &a, int P, int threads, hipStream_t s)
+size_t soft_dft_floats(int n, int B)
 {
-    if (a.n > kSelMaxN) return hipErrorInvalidValue;
+    const GridGeom g = grid_geom(n, B);
+    return (size_t)2 * g.KP * g.NP + (size_t)g.NP * 4 * g.KS2;
+}
+
+// The DFT tables of k_soft_grid for (B, n), in FP64 with each angle reduced exactly as
+// (integer mod n) / n, rounded once: B1r, B1i [KP][NP], then A2 [NP][4 KS2]; padding is zero.
+void build_soft_dft(int B, int n, float *t)
+{
+    const GridGeom g = grid_geom(n, B);
+    const size_t nf = soft_dft_floats(n, B);
+    for (size_t x = 0; x < nf; ++x) t[x] = 0.f;
+    float *B1r = t, *B1i = t + (size_t)g.KP * g.NP, *A2 = B1i + (size_t)g.KP * g.NP;
+    const int W = 2 * B + 1;
+    for (int np = 0; np < W; ++np)
+        for (int k = 0; k < n; ++k) {
+            const int nn = np - B;
+            const int r = (((nn * k) % n) + n) % n;
+            const double th = 2.0 * kPi * r / n;
+            const double c = cos(th), sn = sin(th);
+            B1r[(2 * np) * g.NP + k] = (float)c;
+            B1i[(2 * np) * g.NP + k] = (float)sn;
+            B1r[(2 * np + 1) * g.NP + k] = (float)(-sn);
+            B1i[(2 * np + 1) * g.NP + k] = (float)c;
+        }
+    const int A2W = 4 * g.KS2;
+    for (int j = 0; j < n; ++j)
+        for (int m = 0; m <= B; ++m) {
+            const double ph = 2.0 * kPi * ((m * j) % n) / n;
+            A2[j * A2W + 2 * m] = (float)(2.0 * cos(ph));
+            A2[j * A2W + 2 * m + 1] = (float)(-2.0 * sin(ph));
+        }
+}
+
+hipError_t launch_soft_select(const SoftArgs &a0, int P, int threads, hipStream_t s)
+{
+    if (a0.n > kSelMaxN || (threads != 256 && threads != 512)) return hipErrorInvalidValue;
+    SoftArgs a = a0;
+    a.mcap = 2 * threads;  // == list_cap<threads>()
+    const int NG = (a.n + kMaxSlices - 1) / kMaxSlices;
+    hipLaunchKernelGGL(k_soft_maxima, dim3(P * NG), dim3(kMaxThreads), soft_maxima_smem(a.n), s, a);
     if (threads == 256)
-        hipLaunchKernelGGL(k_soft_select<256>, dim3(P), dim3(256), soft_select_smem(a.n, list_cap<256>()), s, a);
-    else if (threads == 512)
-        hipLaunchKernelGGL(k_soft_select<512>, dim3(P), dim3(512), soft_select_smem(a.n, list_cap<512>()), s, a);
+        hipLaunchKernelGGL(k_soft_rank<256>, dim3(P), dim3(256), soft_select_smem(a.n, list_cap<256>()), s, a);
     else
-        return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_soft_rank<512>, dim3(P), dim3(512), soft_select_smem(a.n, list_cap<512>()), s, a);
     return hipGetLastError();
 }
 

@@ -24,7 +24,7 @@ struct matcha_ctx {
     matcha_tuning tune{0, 0};
     int grid_B = -1, grid_n = -1;  // the SOFFT node tables below are for (grid_B, grid_n)
     float2 *dgrid = nullptr;
-    float2 *etab = nullptr;         // [(B+1) n] e^{i m a_j}, then [n] e^{2 pi i t / n}
+    float *dft = nullptr;           // DFT tables of the SOFFT grid kernel (build_soft_dft)
     float *soft_ws = nullptr;       // SOFFT grid workspace of the eager calls
     size_t soft_ws_bytes = 0;
 };
@@ -166,37 +166,23 @@ void build_grid_table(int B, int n, std::vector<float2> &g)
     }
 }
 
-// Phase factors of the SOFFT grid's DFT: e^{i m a_j} with a_j = 2 pi j / n for m <= B, then the
-// twiddles e^{2 pi i t / n}; each angle is reduced exactly as (m j mod n) / n.
-void build_phase_table(int B, int n, std::vector<float2> &e)
-{
-    e.assign((size_t)((B + 1) * n + n), make_float2(0.f, 0.f));
-    for (int m = 0; m <= B; ++m)
-        for (int j = 0; j < n; ++j) {
-            const double x = 2.0 * M_PI * (double)((m * j) % n) / n;
-            e[(size_t)(m * n + j)] = make_float2((float)std::cos(x), (float)std::sin(x));
-        }
-    for (int t = 0; t < n; ++t) {
-        const double x = 2.0 * M_PI * t / n;
-        e[(size_t)((B + 1) * n + t)] = make_float2((float)std::cos(x), (float)std::sin(x));
-    }
-}
-
 matcha_status ensure_grid(matcha_ctx *ctx, int B, int n)
 {
     if (ctx->dgrid && ctx->grid_B == B && ctx->grid_n == n) return MATCHA_OK;
-    std::vector<float2> g, e;
+    std::vector<float2> g;
     build_grid_table(B, n, g);
-    build_phase_table(B, n, e);
+    std::vector<float> e(soft_dft_floats(n, B));
+    build_soft_dft(B, n, e.data());
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    float2 *d = nullptr, *de = nullptr;
+    float2 *d = nullptr;
+    float *de = nullptr;
     if (hipMalloc(&d, g.size() * sizeof(float2)) != hipSuccess) return MATCHA_ERR_HIP;
-    if (hipMalloc(&de, e.size() * sizeof(float2)) != hipSuccess) {
+    if (hipMalloc(&de, e.size() * sizeof(float)) != hipSuccess) {
         (void)hipFree(d);
         return MATCHA_ERR_HIP;
     }
     if (hipMemcpy(d, g.data(), g.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(de, e.data(), e.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(de, e.data(), e.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(d);
         (void)hipFree(de);
         return MATCHA_ERR_HIP;
@@ -204,24 +190,40 @@ matcha_status ensure_grid(matcha_ctx *ctx, int B, int n)
     if (ctx->dgrid) {
         (void)hipDeviceSynchronize();
         (void)hipFree(ctx->dgrid);
-        (void)hipFree(ctx->etab);
+        (void)hipFree(ctx->dft);
     }
     ctx->dgrid = d;
-    ctx->etab = de;
+    ctx->dft = de;
     ctx->grid_B = B;
     ctx->grid_n = n;
     return MATCHA_OK;
 }
 
-// The SOFFT grid of a particle (n^3 floats) lives in a workspace between the two kernels;
-// batches whose grids exceed kSoftWsCap run in chunks of particles.
+// The SOFFT grid of a particle (n^3 floats) lives in a workspace between the kernels, with the
+// particle's list of maxima keys and their count; batches whose workspace would exceed
+// kSoftWsCap run in chunks of particles.  Layout of a chunk of pc particles: the grids, then
+// pc lists of kSoftListMax keys, then pc counts.
 constexpr size_t kSoftWsCap = (size_t)2 << 30;
+constexpr size_t kSoftListMax = 1024;  // keys per particle: the larger select workgroup's list
+
+size_t soft_grid_bytes(int n) { return (size_t)n * n * n * sizeof(float); }
+size_t soft_particle_bytes(int n)
+{
+    return soft_grid_bytes(n) + kSoftListMax * sizeof(unsigned long long) + sizeof(uint32_t);
+}
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Bytes for a chunk of pc particles (each region 256-byte aligned).
+size_t soft_chunk_bytes(size_t pc, int n)
+{
+    return align256(pc * soft_grid_bytes(n)) + align256(pc * kSoftListMax * sizeof(unsigned long long)) +
+           align256(pc * sizeof(uint32_t));
+}
 
 size_t soft_ws_need(int P, int n)
 {
-    const size_t per = (size_t)n * n * n * sizeof(float);
-    const size_t pc = std::max<size_t>(1, std::min<size_t>((size_t)P, kSoftWsCap / per));
-    return pc * per;
+    const size_t pc = std::max<size_t>(1, std::min<size_t>((size_t)P, kSoftWsCap / soft_particle_bytes(n)));
+    return soft_chunk_bytes(pc, n);
 }
 
 matcha_status ensure_soft_ws(matcha_ctx *ctx, size_t bytes)
@@ -310,7 +312,7 @@ matcha_status matcha_destroy(matcha_ctx *ctx)
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
         if (ctx->dgrid) (void)hipFree(ctx->dgrid);
-        if (ctx->etab) (void)hipFree(ctx->etab);
+        if (ctx->dft) (void)hipFree(ctx->dft);
         if (ctx->soft_ws) (void)hipFree(ctx->soft_ws);
     }
     delete ctx;
@@ -470,20 +472,26 @@ matcha_status soft_search_ws(matcha_ctx *ctx, const matcha_batch *batch, const f
                              float *cand, uint32_t *status, int nt, float *ws, size_t ws_bytes, hipStream_t s)
 {
     const int P = batch->n_particles, n = cfg->n_grid;
-    const size_t per = (size_t)n * n * n * sizeof(float);
-    if (!ws || ws_bytes < per) return MATCHA_ERR_INVALID_ARG;
-    const int pc = (int)std::min<size_t>((size_t)P, ws_bytes / per);
+    if (!ws || ws_bytes < soft_chunk_bytes(1, n)) return MATCHA_ERR_INVALID_ARG;
+    size_t pcs = std::min<size_t>((size_t)P, ws_bytes / soft_particle_bytes(n));
+    while (pcs > 1 && soft_chunk_bytes(pcs, n) > ws_bytes) --pcs;
+    const int pc = (int)std::max<size_t>(pcs, 1);
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    char *base = reinterpret_cast<char *>(ws);
     SoftArgs a;
+    std::memset(&a, 0, sizeof a);
     a.C = reinterpret_cast<const float4 *>(C);
     a.C_off = batch->C_offset;
     a.dgrid = ctx->dgrid;
-    a.etab = ctx->etab;
+    a.dft = ctx->dft;
     a.pinfo = ctx->pinfo;
     a.B = cfg->B;
     a.n = n;
     a.Kc = cfg->Kc;
-    a.grid = ws;
+    a.grid = reinterpret_cast<float *>(base);
+    a.mlist = reinterpret_cast<unsigned long long *>(base + align256((size_t)pc * soft_grid_bytes(n)));
+    a.mcount = reinterpret_cast<uint32_t *>(base + align256((size_t)pc * soft_grid_bytes(n)) +
+                                            align256((size_t)pc * kSoftListMax * sizeof(unsigned long long)));
     a.cand = reinterpret_cast<float4 *>(cand);
     a.status = status;
     for (int p0 = 0; p0 < P; p0 += pc) {

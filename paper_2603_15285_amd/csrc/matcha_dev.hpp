@@ -42,14 +42,15 @@ struct BetaConst {
     double ch, sh;    // cos(b/2), sin(b/2), clamped
 };
 
-__device__ inline BetaConst beta_const(double b)
+__device__ __forceinline__ BetaConst beta_const(double b)
 {
     BetaConst k;
-    double c = cos(0.5 * b), s = sin(0.5 * b);
+    double s, c;
+    sincos(0.5 * b, &s, &c);
+    k.cbd = (c - s) * (c + s);  // cos b and sin b by the double-angle identities
+    k.sbd = 2.0 * s * c;
     c = fmax(fabs(c), 1e-15);
     s = fmax(fabs(s), 1e-15);
-    k.cbd = cos(b);
-    k.sbd = sin(b);
     k.cb = (float)k.cbd;
     k.sb = (float)k.sbd;
     k.ct = (float)(c / s);

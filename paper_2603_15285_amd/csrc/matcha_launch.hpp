@@ -36,12 +36,15 @@ struct SoftArgs {
     const float4 *C;
     const int64_t *C_off;
     const float2 *dgrid;      // [n][wedge_row(B+1)]: weighted d^l(b_i) of each wedge pair and its partner
-    const float2 *etab;       // [(B+1) n] e^{i m a_j}, then [n] e^{2 pi i t / n}
+    const float *dft;         // DFT tables of the grid kernel (build_soft_dft)
     const PairInfo *pinfo;
     int B, n, Kc;
-    int gslices;              // polar nodes per workgroup of the grid kernel (set by its launcher)
+    int gslices;              // waves per workgroup of the grid kernel (set by its launcher)
     int p0;                   // first particle of this launch
     float *grid;              // [launch particles][n][n][n] workspace: C_B on the grid
+    unsigned long long *mlist;  // [launch particles][mcap] keys of the local maxima (workspace)
+    uint32_t *mcount;         // [launch particles] maxima found (may exceed mcap)
+    int mcap;                 // keys kept per particle (set by the select launcher)
     float4 *cand;
     uint32_t *status;
 };
@@ -105,6 +108,8 @@ size_t assemble_bf16_smem_bytes(int Lmax, int Rmax);
 hipError_t launch_assemble_bf16(const AsmBArgs &a, int P, int Lmax, int Rmax, hipStream_t s);
 
 size_t soft_grid_smem_bytes(int n, int B);
+size_t soft_dft_floats(int n, int B);
+void build_soft_dft(int B, int n, float *t);
 size_t soft_select_smem_bytes(int n, int threads);
 hipError_t launch_soft_grid(const SoftArgs &a, int P, hipStream_t s);
 hipError_t launch_soft_select(const SoftArgs &a, int P, int threads, hipStream_t s);

@@ -154,6 +154,77 @@ def test_soft_search_few_maxima(M, ctx):
         assert status[p] & M.ST_FEW_MAXIMA
 
 
+@pytest.mark.parametrize("L,B,n", [(16, 16, 64), (24, 24, 48)])
+def test_soft_search_many_maxima(M, L, B, n):
+    """Noise-dominated grids with 763 (B=16, n=64) and 1440 (B=24, n=48) local maxima (oracle
+    counts).  The 256-thread select keeps 512 keys per particle, the 512-thread one 1024: the first
+    case takes the fast ranking at 512 threads and the streaming search at 256, the second the
+    streaming search at both.  Every variant matches the oracle, and the two agree bit for bit."""
+    b = S.make_batch(L, 2, 2, seed=77, snr=0.01)
+    c = M.Context(0)
+    batch, f, h, w = upload(M, b)
+    C = M.coeff_assemble(c, batch, f, h, w)
+    out = {}
+    for nt in (256, 512):
+        c.set_tuning(0, nt)
+        cand, status = M.soft_search(c, batch, C, B, n, 16)
+        out[nt] = (cand.cpu().numpy(), status.cpu().numpy())
+    c.close()
+    assert np.array_equal(out[256][0], out[512][0]) and np.array_equal(out[256][1], out[512][1])
+    for p in range(2):
+        check_soft(b, p, out[256][0][p], int(out[256][1][p]), B, n, 16)
+
+
+def test_soft_search_max_shape(M):
+    """The largest search the library takes (B = 32 on a 96^3 grid, Kc = 64), checked without the
+    oracle (too slow at this size): each candidate's value is C_B at its node as the recurrence of
+    matcha_evaluate computes it, no node among its 26 neighbours is larger, the list is ranked,
+    and both select workgroup sizes give the same bits."""
+    B, n, Kc = 32, 96, 64
+    b = S.make_batch(32, 4, 2, seed=90, snr=0.05)
+    c = M.Context(0)
+    batch, f, h, w = upload(M, b)
+    C = M.coeff_assemble(c, batch, f, h, w)
+    out = {}
+    for nt in (256, 512):
+        c.set_tuning(0, nt)
+        cand, status = M.soft_search(c, batch, C, B, n, Kc)
+        out[nt] = (cand.cpu().numpy(), status.cpu().numpy())
+    assert np.array_equal(out[256][0], out[512][0]) and np.array_equal(out[256][1], out[512][1])
+    cand, status = out[256]
+    Cn = C.cpu().numpy()
+    ce = M.c_elems(32)
+    for p in range(2):
+        tol = 2e-5 * scale(b, p, B)
+        assert not (status[p] & M.ST_FEW_MAXIMA)
+        assert np.all(np.diff(cand[p, :, 3]) <= 0)
+        j = np.rint(cand[p, :, 0] * n / (2 * math.pi)).astype(np.int64) % n
+        i = np.rint(cand[p, :, 1] * 2 * n / math.pi - 1).astype(np.int64) // 2
+        k = np.rint(cand[p, :, 2] * n / (2 * math.pi)).astype(np.int64) % n
+        nodes = [(i, j, k)]
+        for di in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                for dk in (-1, 0, 1):
+                    if di or dj or dk:
+                        nodes.append((i + di, (j + dj) % n, (k + dk) % n))
+        ii = np.concatenate([x[0] for x in nodes])
+        jj = np.concatenate([x[1] for x in nodes])
+        kk = np.concatenate([x[2] for x in nodes])
+        ok = (ii >= 0) & (ii < n)
+        ii, jj, kk = np.clip(ii, 0, n - 1), jj, kk
+        theta = np.stack([2 * np.pi * jj / n, np.pi * (2 * ii + 1) / (2 * n), 2 * np.pi * kk / n,
+                          np.zeros_like(jj, dtype=np.float64)], -1).astype(np.float32)
+        Q = theta.shape[0]
+        qb = M.Batch.make(np.full(Q, 32), np.full(Q, 4), b.L_h, b.R_h)
+        Cq = torch.from_numpy(np.tile(Cn[p * ce * 2:(p + 1) * ce * 2], Q)).cuda()
+        F = M.evaluate(c, qb, Cq, B, torch.from_numpy(theta).cuda())[:, 0].cpu().numpy().astype(np.float64)
+        v = cand[p, :, 3].astype(np.float64)
+        assert np.all(np.abs(F[:Kc] - v) <= tol)
+        nb = F[Kc:].reshape(26, Kc)
+        assert np.all((nb <= v[None, :] + tol) | ~ok[Kc:].reshape(26, Kc))
+    c.close()
+
+
 # ---------------------------------------------------------------- march
 def test_march_from_oracle_candidates(M, ctx):
     wl = S.WORKLOADS["L32_R32_B12_K16"]

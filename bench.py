@@ -117,6 +117,33 @@ def pmc_probe(args):
     ctx.close()
 
 
+HBM_PEAK_GBPS = 8000.0
+MFMA_FP32_PEAK_TFLOPS = 157.3
+
+
+def wedge_rows(L):
+    """float4 entries of one particle's wedge-layout C up to band L: sum_{l<=L} (l+1)^2."""
+    return (L + 1) * (L + 2) * (2 * L + 3) // 6
+
+
+def assemble_work(L, R):
+    """(HBM bytes, useful MFMA flops) of the assembly for one particle: f read (R (L+1)^2 complex64),
+    C written (16 bytes per wedge entry); 8 real flops per complex multiply-add over the half plane
+    sum_l (l+1)(2l+1) R."""
+    byts = R * (L + 1) ** 2 * 8 + wedge_rows(L) * 16
+    flops = 8 * R * sum((l + 1) * (2 * l + 1) for l in range(L + 1))
+    return byts, flops
+
+
+def soft_work(B, n):
+    """(HBM bytes, useful DFT flops) of the SOFFT search for one particle: the n^3 grid written
+    and read back (4 bytes each way), C read up to band B; the two real DFT products per polar node,
+    8 (B+1)(2B+1) n for the first stage and 4 (B+1) n^2 for the second."""
+    byts = 2 * 4 * n ** 3 + wedge_rows(B) * 16
+    flops = n * (8 * (B + 1) * (2 * B + 1) * n + 4 * (B + 1) * n * n)
+    return byts, flops
+
+
 def cpu_baseline(b, wl, budget_s=15.0):
     import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -201,19 +228,23 @@ def main():
     ms_step = ms_total / args.steps
     value = P / (ms_step / 1e3)
 
-    # the march alone, timed with events on the stream its kernel runs on
-    cand0 = bufs["cand"].clone()
-    mev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    # each stage alone, timed with events on the stream its kernels run on
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
     for k in range(args.steps):
+        ev[k][0].record(stream)
+        M.coeff_assemble(ctx, batch, f, h, w, C=bufs["C"])
+        ev[k][1].record(stream)
         M.soft_search(ctx, batch, bufs["C"], wl.B, wl.n_grid, wl.Kc, cand=bufs["cand"], status=bufs["status"])
-        mev[k][0].record(stream)
+        ev[k][2].record(stream)
         M.march_newton(ctx, batch, bufs["C"], wl.levels, wl.steps, bufs["cand"], bufs["status"], best=bufs["best"],
                        best_idx=bufs["best_idx"], fp64_above=fp64_above)
-        mev[k][1].record(stream)
+        ev[k][3].record(stream)
     torch.cuda.synchronize()
-    ms_march = float(np.mean([a.elapsed_time(z) for a, z in mev]))
-    del cand0
-    log(f"batched: {ms_step:.3f} ms/step, march {ms_march:.3f} ms, {value:.0f} particles/s")
+    ms_asm = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    ms_soft = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    ms_march = float(np.mean([e[2].elapsed_time(e[3]) for e in ev]))
+    log(f"batched: {ms_step:.3f} ms/step (assembly {ms_asm:.3f}, search {ms_soft:.3f}, march {ms_march:.3f} ms), "
+        f"{value:.0f} particles/s")
 
     best = bufs["best"].cpu().numpy().astype(np.float64)
     err = S.geodesic_deg(b.R_true(), S.euler_zyz_to_matrix(best[:, 0], best[:, 1], best[:, 2]))
@@ -266,6 +297,22 @@ def main():
 
     flops = sum(march_flops_per_particle(wl.levels, int(Lp), wl.steps, wl.Kc) for Lp in b.L)
     traffic = measured_march_traffic(wl.name) if args.particles is None else None
+    a_b, a_f = np.sum([assemble_work(int(Lp), int(Rp)) for Lp, Rp in zip(b.L, b.R)], axis=0)
+    s_b, s_f = soft_work(wl.B, wl.n_grid)
+    s_b, s_f = s_b * P, s_f * P
+    stages = {
+        "assemble": {"kernel": "k_assemble_f32", "ms": ms_asm,
+                     "hbm_GBps": a_b / (ms_asm / 1e3) / 1e9, "hbm_frac": a_b / (ms_asm / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                     "mfma_TFLOPs": a_f / (ms_asm / 1e3) / 1e12,
+                     "mfma_frac": a_f / (ms_asm / 1e3) / 1e12 / MFMA_FP32_PEAK_TFLOPS},
+        "soft_search": {"kernels": "k_soft_grid + k_soft_maxima + k_soft_rank", "ms": ms_soft,
+                        "hbm_GBps": s_b / (ms_soft / 1e3) / 1e9,
+                        "hbm_frac": s_b / (ms_soft / 1e3) / 1e9 / HBM_PEAK_GBPS,
+                        "mfma_TFLOPs": s_f / (ms_soft / 1e3) / 1e12,
+                        "mfma_frac": s_f / (ms_soft / 1e3) / 1e12 / MFMA_FP32_PEAK_TFLOPS},
+        "march": {"kernel": "k_march", "ms": ms_march, "valu_TFLOPs": flops / (ms_march / 1e3) / 1e12,
+                  "valu_frac": flops / (ms_march / 1e3) / 1e12 / VALU_FP32_PEAK_TFLOPS},
+    }
     achieved = flops / (ms_march / 1e3) / 1e12
     out = {
         "metric": METRIC, "value": value, "unit": "particles/s", "n_gpus": 1, "steps": args.steps,
@@ -284,6 +331,7 @@ def main():
                          "rot_diff_vs_fp32_deg": {"median": float(np.median(d16)), "p99": float(np.percentile(d16, 99)),
                                                   "n_over_0.05": int(np.sum(d16 > 0.05))},
                          "rot_err_vs_truth_deg": {"median": float(np.median(err16)), "p90": float(np.percentile(err16, 90))}},
+        "stages": stages,
         "tuning": tuning,
         "rot_err_vs_truth_deg": {"median": float(np.median(err)), "p90": float(np.percentile(err, 90)),
                                  "max": float(err.max())},

@@ -180,7 +180,7 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
  * status [P] is overwritten.  Requires 1 <= B <= min_p L_p, B <= 32, 4 <= n_grid <= 96,
  * 1 <= Kc <= MATCHA_MAX_KC (MATCHA_ERR_UNSUPPORTED if the shape does not fit a workgroup's LDS).
  * The grid passes through a workspace owned by the context (n_grid^3 floats per particle,
- * at most 2 GiB; larger batches run in chunks of particles), allocated on first need and
+ * at most 4 GiB; larger batches run in chunks of particles), allocated on first need and
  * grown synchronously; calls on one context must not overlap in time (use one stream per
  * context).  matcha_align_graph_create gives each graph a workspace of its own. */
 matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, const float *C,

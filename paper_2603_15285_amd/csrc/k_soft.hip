@@ -2,19 +2,20 @@
 //
 // Two kernels per batch of particles, with the grid in an HBM workspace between them.
 //
-// k_soft_grid synthesises C_B on the n^3 grid (a_j = 2 pi j / n, b_i = pi (2i+1) / (2n),
-// c_k = 2 pi k / n).  A workgroup takes a few polar nodes of one particle; per node it
-// forms the Wigner-d transform over l of the coefficients,
+// k_soft_wigner forms, for every polar node b_i = pi (2i+1) / (2n) of a particle, the Wigner-d
+// transform over l of the coefficients,
 //   S_i[m, n] = sum_{l <= B} C^l_mn d^l_mn(b_i)   on the half plane {m > 0} U {m = 0, n >= 0},
-// (the wedge recurrence of the march, one step serving a pair and its partner; the d values at
-// the nodes come from a table shared by all particles), then the 2-D inverse DFT over (a, c):
-// first T[m][k] = sum_n S[m, n] e^{i n c_k}, then g[j][k] = 2 Re sum_m T[m][k] e^{i m a_j}.
+// one workgroup per particle with its coefficients staged in LDS, one step of the sum serving a
+// pair and its partner; the d values at the nodes come from a table shared by all particles.
 //
-// k_soft_maxima takes a particle and 8 consecutive polar nodes per workgroup and streams their
-// slices (with one neighbour slice on each side) through an LDS ring of three; every node is
-// tested for a local maximum against its 26 neighbours (six axis neighbours first, then the
-// exact test), and each maximum's 64-bit key (ordered value, inverted linear index) is appended
-// to the particle's list in the workspace.
+// k_soft_grid synthesises C_B on the n^3 grid (a_j = 2 pi j / n, c_k = 2 pi k / n) with the 2-D
+// inverse DFT over (a, c), each wave taking a few polar nodes of one particle: first
+// T[m][k] = sum_n S[m, n] e^{i n c_k}, then g[j][k] = 2 Re sum_m T[m][k] e^{i m a_j}.
+//
+// k_soft_maxima_q (n a multiple of 4; k_soft_maxima otherwise) takes a particle and a run of
+// consecutive polar nodes per workgroup and tests every node for a local maximum against its 26
+// neighbours (six axis neighbours first, then the exact test); each maximum's 64-bit key
+// (ordered value, inverted linear index) is appended to the particle's list in the workspace.
 //
 // k_soft_rank takes one particle per workgroup, sorts its list and writes the Kc best keys, so
 // the ranking is exact whatever order the maxima arrived in.  A particle whose list overflowed,
@@ -44,8 +45,9 @@ struct GridGeom {
     int MT;   // 16-row tiles of m (B+1 rows)
     int KP;   // stage-1 K, 2(2B+1) padded to a multiple of 4
     int NP;   // k (and j) padded to a multiple of 16
-    int K2R;  // rows of T' held: 32 MT (two per m)
     int KS2;  // stage-2 K steps: ceil(2(B+1) / 4)
+    int K2R;  // rows of T' held: the 4 KS2 that stage 2 reads (two per m)
+    int TF;   // floats of the DFT tables: B1r, B1i [KP][NP], A2 [NP][4 KS2]
 };
 
 __host__ __device__ inline GridGeom grid_geom(int n, int B)
@@ -54,35 +56,49 @@ __host__ __device__ inline GridGeom grid_geom(int n, int B)
     g.MT = (B + 16) / 16;
     g.KP = 4 * ((2 * (2 * B + 1) + 3) / 4);
     g.NP = 16 * ((n + 15) / 16);
-    g.K2R = 32 * g.MT;
     g.KS2 = (2 * (B + 1) + 3) / 4;
+    g.K2R = 4 * g.KS2;
+    g.TF = 2 * g.KP * g.NP + g.NP * 4 * g.KS2;
     return g;
 }
 
 __host__ __device__ inline int grid_wave_floats(const GridGeom &g) { return 16 * g.MT * g.KP + g.K2R * g.NP; }
 
-__host__ __device__ inline size_t soft_grid_smem(int n, int B, int waves)
+// LDS of a workgroup of `waves` waves, with the DFT tables in LDS (tab_lds) or read from memory.
+__host__ __device__ inline size_t soft_grid_smem(int n, int B, int waves, bool tab_lds)
 {
-    return sizeof(float) * (size_t)waves * grid_wave_floats(grid_geom(n, B));
+    const GridGeom g = grid_geom(n, B);
+    return sizeof(float) * ((size_t)waves * grid_wave_floats(g) + (tab_lds ? (size_t)g.TF : 0));
 }
 
-// Waves per workgroup: four when their LDS fits 64 KB, else fewer.
-inline int soft_grid_waves(int n, int B)
+// Launch shape: the tables go to LDS whenever one wave fits beside them; then up to four waves
+// while the workgroup stays within 80 KB (two workgroups per CU).  Otherwise the tables are read
+// through the caches and up to four waves share 64 KB.
+struct GridShape {
+    int waves;
+    bool tab_lds;
+};
+
+inline GridShape soft_grid_shape(int n, int B)
 {
+    if (soft_grid_smem(n, B, 1, true) <= 160 * 1024) {
+        for (int w : {4, 2})
+            if (soft_grid_smem(n, B, w, true) <= 80 * 1024) return {w, true};
+        return {1, true};
+    }
     for (int w : {4, 2})
-        if (soft_grid_smem(n, B, w) <= 64 * 1024) return w;
-    return 1;
+        if (soft_grid_smem(n, B, w, false) <= 64 * 1024) return {w, false};
+    return {1, false};
 }
 
-// S_i for one wedge pair into the interleaved rows of Sf (row stride KP):
-// S[pair] = sum_l C^l_pair dg0^l_pair(b_i), S[partner] = sum_l C^l_partner dg1^l_pair(b_i).
-// Entries (0, n < 0) are never written and stay zero.  Four degrees per trip keep eight
-// independent loads in flight.
-__device__ inline void wigner_pair(const float4 *__restrict__ Cp, const float2 *__restrict__ dg, const PairInfo &pi,
-                                   int q, int B, int KP, float *Sf)
+// The two l-sums of one wedge pair at polar node b_i:
+// u0 = sum_l C^l_pair dg0^l_pair(b_i), u1 = sum_l C^l_partner dg1^l_pair(b_i).  Four degrees per
+// trip keep eight independent loads in flight.
+__device__ __forceinline__ void wigner_sums(const float4 *__restrict__ Cp, const float2 *__restrict__ dg, int m, int q, int B,
+                                   float2 &u0, float2 &u1)
 {
-    const int m = pi.m, n = pi.n;
-    float2 u0 = make_float2(0.f, 0.f), u1 = u0;
+    u0 = make_float2(0.f, 0.f);
+    u1 = u0;
     int row = (int)wedge_row(m) + q;
     int l = m;
     for (; l + 3 <= B; l += 4) {
@@ -116,18 +132,59 @@ __device__ inline void wigner_pair(const float4 *__restrict__ Cp, const float2 *
         u1.x = fmaf(cc.z, d.y, u1.x);
         u1.y = fmaf(cc.w, d.y, u1.y);
     }
-    Sf[m * KP + 2 * (n + B)] = u0.x;
-    Sf[m * KP + 2 * (n + B) + 1] = u0.y;
-    if (n != m && n != -m) {  // diagonal pairs are their own partners
-        const int a2 = n >= 0 ? n : -n, b2 = n >= 0 ? m : -m;
-        Sf[a2 * KP + 2 * (b2 + B)] = u1.x;
-        Sf[a2 * KP + 2 * (b2 + B) + 1] = u1.y;
+}
+
+// Wigner-d transform of every polar node of the launch's particles into the half-plane array
+// S[m][n + B] of the workspace; the pair's value goes to (m, n), its partner's to (n, m) (n >= 0)
+// or (-n, -m) (n < 0).  One workgroup per particle: its coefficients up to band B are staged in
+// LDS once (when they fit, CP_LDS), and each thread takes (node, pair) tasks with consecutive
+// threads on consecutive pairs, so the node tables are read coalesced.  The entries (0, n < 0),
+// the Hermitian mirrors of (0, -n), are written as zero by the (0, 0) pair's task.
+constexpr int kWignerThreads = 256;
+
+template <bool CP_LDS>
+__global__ void __launch_bounds__(kWignerThreads) k_soft_wigner(SoftArgs a)
+{
+    extern __shared__ __align__(16) float4 cs[];
+    const int B = a.B, N = a.n, W = 2 * B + 1;
+    const int npairs = (B + 1) * (B + 1);
+    const int pl = blockIdx.x, p = a.p0 + pl;
+    const float4 *Cg = a.C + a.C_off[p] / 2;
+    const float4 *Cp = Cg;
+    if (CP_LDS) {
+        const int rows = (int)wedge_row(B + 1);
+        for (int t = threadIdx.x; t < rows; t += kWignerThreads) cs[t] = Cg[t];
+        __syncthreads();
+        Cp = cs;
+    }
+    const int64_t drow = wedge_row(B + 1);
+    float2 *Sp = a.S + (int64_t)pl * N * (B + 1) * W;
+    for (int t = threadIdx.x; t < N * npairs; t += kWignerThreads) {
+        const int i = t / npairs, q = t - (t / npairs) * npairs;
+        const PairInfo pi = a.pinfo[q];
+        const int m = pi.m, n = pi.n;
+        float2 u0, u1;
+        wigner_sums(Cp, a.dgrid + i * drow, m, q, B, u0, u1);
+        float2 *S = Sp + (int64_t)i * (B + 1) * W;
+        S[m * W + n + B] = u0;
+        if (n != m && n != -m) {  // diagonal pairs are their own partners
+            const int a2 = n >= 0 ? n : -n, b2 = n >= 0 ? m : -m;
+            S[a2 * W + b2 + B] = u1;
+        }
+        if (q == 0)
+            for (int k = 0; k < B; ++k) S[k] = make_float2(0.f, 0.f);
     }
 }
 
+inline bool soft_wigner_cp_lds(int B) { return wedge_row(B + 1) * sizeof(float4) <= 64 * 1024; }
+
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kGridChunk = 8;  // K steps whose operands are loaded before their MFMAs
+// float2 values of a node's half-plane array prefetched per lane: all of it while
+// (B+1)(2B+1) <= 8 * 64, i.e. B <= 15
+constexpr int kGridSReg = 8;
 
+template <bool TAB_LDS>
 __global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
 {
     extern __shared__ __align__(16) float smem_f[];
@@ -140,22 +197,60 @@ __global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
     const int p = a.p0 + pl;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int col = lane % 16, kq = lane / 16;
-    float *Sf = smem_f + wave * grid_wave_floats(g);  // [16 MT][KP]
-    float *Tf = Sf + 16 * g.MT * g.KP;                // [K2R][NP]
-    const float *B1r = a.dft, *B1i = B1r + g.KP * g.NP, *A2 = B1i + g.KP * g.NP;
+    const float *tabs = a.dft;
+    float *wbase = smem_f;
+    if (TAB_LDS) {
+        // the DFT tables, shared by the workgroup's waves (TF is a multiple of 4)
+        for (int t = threadIdx.x; t < g.TF / 4; t += blockDim.x)
+            reinterpret_cast<float4 *>(smem_f)[t] = reinterpret_cast<const float4 *>(a.dft)[t];
+        __syncthreads();
+        tabs = smem_f;
+        wbase = smem_f + g.TF;
+    }
+    float *Sf = wbase + wave * grid_wave_floats(g);  // [16 MT][KP]
+    float *Tf = Sf + 16 * g.MT * g.KP;              // [K2R][NP]
+    const float *B1r = tabs, *B1i = B1r + g.KP * g.NP, *A2 = B1i + g.KP * g.NP;
     const int A2W = 4 * g.KS2;
-    const float4 *Cp = a.C + a.C_off[p] / 2;
     if (ib == 0 && threadIdx.x == 0) a.mcount[pl] = 0u;  // the maxima kernel that follows appends from 0
-    const int npairs = (B + 1) * (B + 1);
-    const int64_t drow = wedge_row(B + 1);
+    (void)p;
     const int KS1 = g.KP / 4, NT = g.NP / 16;
-    for (int si = 0; si < kGridSPW; ++si) {
-        const int i = ib + wave * kGridSPW + si;  // the wave's polar node
-        if (i >= N) break;
-        for (int t = lane; t < 16 * g.MT * g.KP; t += kWave) Sf[t] = 0.f;
+    // the padding rows and columns of S stay zero; each node overwrites the rest
+    for (int t = lane; t < 16 * g.MT * g.KP; t += kWave) Sf[t] = 0.f;
+    const int W = 2 * B + 1, SW = (B + 1) * W;
+    const float2 *Sb = a.S + (int64_t)pl * N * SW;
+    const int i_first = ib + wave * kGridSPW;
+    const int i_last = min(i_first + kGridSPW, N) - 1;  // the wave's polar nodes
+    // S of a node is read at clamped addresses, all of a lane's loads in flight together; the
+    // next node's values are loaded while the current node runs on the matrix cores
+    float2 sv[kGridSReg];
+    auto load_s = [&](int i) {
+        const float2 *Sg = Sb + (int64_t)min(i, N - 1) * SW;
+#pragma unroll
+        for (int u = 0; u < kGridSReg; ++u) sv[u] = Sg[min(u * kWave + lane, SW - 1)];
+    };
+    if (i_first < N) load_s(i_first);
+    auto put_s = [&](int t, float2 v) {
+        const int mm = t / W, nn = t - (t / W) * W;
+        Sf[mm * g.KP + 2 * nn] = v.x;
+        Sf[mm * g.KP + 2 * nn + 1] = v.y;
+    };
+    for (int i = i_first; i <= i_last; ++i) {
+        // S into the interleaved rows of Sf (the padding stays zero): the prefetched head, then
+        // (B > 15) the rest, eight loads in flight per lane
+#pragma unroll
+        for (int u = 0; u < kGridSReg; ++u)
+            if (u * kWave + lane < SW) put_s(u * kWave + lane, sv[u]);
+        const float2 *Sg = Sb + (int64_t)i * SW;
+        for (int t0 = kGridSReg * kWave; t0 < SW; t0 += 8 * kWave) {
+            float2 v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = Sg[min(t0 + u * kWave + lane, SW - 1)];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (t0 + u * kWave + lane < SW) put_s(t0 + u * kWave + lane, v[u]);
+        }
         wave_sync();
-        for (int q = lane; q < npairs; q += kWave) wigner_pair(Cp, a.dgrid + i * drow, a.pinfo[q], q, B, g.KP, Sf);
-        wave_sync();
+        if (i < i_last) load_s(i + 1);
         // stage 1: Re T and Im T, rows m, columns k
         for (int tn = 0; tn < NT; ++tn)
             for (int tm = 0; tm < g.MT; ++tm) {
@@ -182,9 +277,11 @@ __global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
                 }
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const int m = 16 * tm + 4 * kq + v;
-                    Tf[(2 * m) * g.NP + 16 * tn + col] = cr[v];
-                    Tf[(2 * m + 1) * g.NP + 16 * tn + col] = ci[v];
+                    const int m = 16 * tm + 4 * kq + v;  // rows past K2R are zero and never read
+                    if (2 * m + 1 < g.K2R) {
+                        Tf[(2 * m) * g.NP + 16 * tn + col] = cr[v];
+                        Tf[(2 * m + 1) * g.NP + 16 * tn + col] = ci[v];
+                    }
                 }
             }
         wave_sync();
@@ -464,54 +561,28 @@ __device__ inline float4 key_to_cand(unsigned long long key, int N)
 
 // ---------------------------------------------------------------- parallel maxima
 constexpr int kMaxThreads = 256;
-constexpr int kMaxSlices = 8;  // polar nodes tested per workgroup
+constexpr int kMaxSlices = 8;    // polar nodes tested per workgroup, any n
+constexpr int kMaxQSlices = 16;  // polar nodes tested per workgroup, n a multiple of 4
 
 __host__ __device__ inline size_t soft_maxima_smem(int n) { return 3 * soft_align16(sizeof(float) * n * n); }
-
-// Appends the key of node t of slice ic to the particle's list if it beats its 26 neighbours.
-__device__ __forceinline__ void maxima_exact(const SoftArgs &a, const SoftSmem &sm, int pl, int ic, int t, int pslot, int cslot,
-                                    int nslot, float v)
+// Candidate queue of the n-multiple-of-4 maxima kernel: n^2 / 2 entries for a run of up to 16
+// slices (a band-limited grid has far fewer nodes that top their six axis neighbours).
+__host__ __device__ inline int soft_maxima_qcap(int n) { return n * n / 2; }
+// two slice planes and the queue
+__host__ __device__ inline size_t soft_maxima_q_smem(int n)
 {
-    if (!beats_all<kMaxThreads>(a, sm, ic, t, pslot, cslot, nslot)) return;
+    return 2 * soft_align16(sizeof(float) * n * n) + soft_align16(sizeof(uint32_t) * soft_maxima_qcap(n));
+}
+
+__device__ __forceinline__ void append_maximum(const SoftArgs &a, int pl, float v, uint32_t idx)
+{
     const uint32_t slot = atomicAdd(a.mcount + pl, 1u);
-    if (slot < (uint32_t)a.mcap) a.mlist[(int64_t)pl * a.mcap + slot] = make_key(v, (uint32_t)(ic * a.n * a.n + t));
+    if (slot < (uint32_t)a.mcap) a.mlist[(int64_t)pl * a.mcap + slot] = make_key(v, idx);
 }
 
-// Four nodes (j, k0 .. k0+3) of slice ic (n a multiple of 4): a node is a candidate when its
-// value is at least the largest of its six axis neighbours (absent slices count as -inf);
-// candidates take the exact test.
-__device__ __forceinline__ void maxima_quad(const SoftArgs &a, const SoftSmem &sm, int pl, int ic, int j, int k0, int pslot,
-                                   int cslot, int nslot)
-{
-    const int N = a.n;
-    const float *cur = sm.ring(cslot);
-    const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
-    const float4 c = *reinterpret_cast<const float4 *>(cur + j * N + k0);
-    const float4 up = *reinterpret_cast<const float4 *>(cur + jm * N + k0);
-    const float4 dn = *reinterpret_cast<const float4 *>(cur + jp * N + k0);
-    const float left = cur[j * N + (k0 == 0 ? N - 1 : k0 - 1)];
-    const float right = cur[j * N + (k0 + 4 == N ? 0 : k0 + 4)];
-    const float ninf = -__builtin_huge_valf();
-    float4 pv = make_float4(ninf, ninf, ninf, ninf), nv = pv;
-    if (pslot >= 0) pv = *reinterpret_cast<const float4 *>(sm.ring(pslot) + j * N + k0);
-    if (nslot >= 0) nv = *reinterpret_cast<const float4 *>(sm.ring(nslot) + j * N + k0);
-    const float vv[4] = {c.x, c.y, c.z, c.w}, uu[4] = {up.x, up.y, up.z, up.w}, dd[4] = {dn.x, dn.y, dn.z, dn.w};
-    const float ll[4] = {left, c.x, c.y, c.z}, rr[4] = {c.y, c.z, c.w, right};
-    const float pp[4] = {pv.x, pv.y, pv.z, pv.w}, qq[4] = {nv.x, nv.y, nv.z, nv.w};
-    unsigned cand = 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const float mx = fmaxf(fmaxf(fmaxf(uu[q], dd[q]), fmaxf(ll[q], rr[q])), fmaxf(pp[q], qq[q]));
-        cand |= (vv[q] >= mx ? 1u : 0u) << q;
-    }
-    while (cand) {  // rare: candidates take the exact test
-        const int q = __builtin_ctz(cand);
-        cand &= cand - 1;
-        const float v = q == 0 ? c.x : (q == 1 ? c.y : (q == 2 ? c.z : c.w));
-        maxima_exact(a, sm, pl, ic, j * N + k0 + q, pslot, cslot, nslot, v);
-    }
-}
-
+// Any n: a workgroup streams its slices (plus one neighbour slice on each side) through an LDS
+// ring of three; a node whose value is at least the largest of its six axis neighbours (absent
+// slices count as -inf) takes the exact test.
 __global__ void __launch_bounds__(kMaxThreads) k_soft_maxima(SoftArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -519,82 +590,213 @@ __global__ void __launch_bounds__(kMaxThreads) k_soft_maxima(SoftArgs a)
     const int NG = (N + kMaxSlices - 1) / kMaxSlices;
     const int pl = blockIdx.x / NG, i0 = (blockIdx.x - pl * NG) * kMaxSlices;
     const int i1 = min(i0 + kMaxSlices, N);  // tests slices i0 .. i1-1
-    const bool quads = (N & 3) == 0;         // rows split into float4 quads (slices 16-byte aligned)
     SoftSmem sm;
     sm.ring0 = reinterpret_cast<float *>(smem_raw);
     sm.plane = (int)(soft_align16(sizeof(float) * NN) / sizeof(float));
     const float *grid = a.grid + (int64_t)pl * N * NN;
-    constexpr int PER = (kSelMaxN * kSelMaxN / 4 + kMaxThreads - 1) / kMaxThreads;
-    const int NQ = NN / 4, QR = N / 4;  // quads per slice and per row
-    // slice s lives in ring slot s mod 3; each slice's loads are all in flight before the stores
-    for (int s = max(i0 - 1, 0); s <= min(i0 + 1, N - 1); ++s) {
-        const float *src = grid + (int64_t)s * NN;
-        float *dst = sm.ring(s % 3);
-        if (quads) {
-            float4 v[PER];
-#pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int t = threadIdx.x + u * kMaxThreads;
-                v[u] = t < NQ ? reinterpret_cast<const float4 *>(src)[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-#pragma unroll
-            for (int u = 0; u < PER; ++u) {
-                const int t = threadIdx.x + u * kMaxThreads;
-                if (t < NQ) reinterpret_cast<float4 *>(dst)[t] = v[u];
-            }
-        } else {
-            for (int t = threadIdx.x; t < NN; t += kMaxThreads) dst[t] = src[t];
-        }
-    }
+    // slice s lives in ring slot s mod 3
+    for (int s = max(i0 - 1, 0); s <= min(i0 + 1, N - 1); ++s)
+        for (int t = threadIdx.x; t < NN; t += kMaxThreads) sm.ring(s % 3)[t] = grid[(int64_t)s * NN + t];
     __syncthreads();
     for (int ic = i0; ic < i1; ++ic) {
-        // slice ic+2 is needed when slice ic+1 is tested here; it is read as float4 quads, or as
-        // single values when n is not a multiple of 4
-        const bool pre = ic + 1 < i1 && ic + 2 < N;
-        const float *src = grid + (int64_t)(ic + 2) * NN;
-        float4 nxt[PER];
-        const bool preq = pre && quads;
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int t = threadIdx.x + u * kMaxThreads;
-            nxt[u] = (preq && t < NQ) ? reinterpret_cast<const float4 *>(src)[t] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
         const int pslot = ic >= 1 ? (ic - 1) % 3 : -1;
         const int cslot = ic % 3;
         const int nslot = ic + 1 < N ? (ic + 1) % 3 : -1;
-        if (quads) {
-            for (int qd = threadIdx.x; qd < NQ; qd += kMaxThreads) {
-                const int j = qd / QR, k0 = 4 * (qd - (qd / QR) * QR);
-                maxima_quad(a, sm, pl, ic, j, k0, pslot, cslot, nslot);
-            }
-        } else {
-            const float *cur = sm.ring(cslot);
-            for (int t = threadIdx.x; t < NN; t += kMaxThreads) {
-                const float v = cur[t];
-                const int j = t / N, k = t - (t / N) * N;
-                const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
-                const int km = k == 0 ? N - 1 : k - 1, kp = k == N - 1 ? 0 : k + 1;
-                float mx = fmaxf(fmaxf(cur[jm * N + k], cur[jp * N + k]), fmaxf(cur[j * N + km], cur[j * N + kp]));
-                if (pslot >= 0) mx = fmaxf(mx, sm.ring(pslot)[t]);
-                if (nslot >= 0) mx = fmaxf(mx, sm.ring(nslot)[t]);
-                if (v >= mx) maxima_exact(a, sm, pl, ic, t, pslot, cslot, nslot, v);
-            }
+        const float *cur = sm.ring(cslot);
+        for (int t = threadIdx.x; t < NN; t += kMaxThreads) {
+            const float v = cur[t];
+            const int j = t / N, k = t - (t / N) * N;
+            const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
+            const int km = k == 0 ? N - 1 : k - 1, kp = k == N - 1 ? 0 : k + 1;
+            float mx = fmaxf(fmaxf(cur[jm * N + k], cur[jp * N + k]), fmaxf(cur[j * N + km], cur[j * N + kp]));
+            if (pslot >= 0) mx = fmaxf(mx, sm.ring(pslot)[t]);
+            if (nslot >= 0) mx = fmaxf(mx, sm.ring(nslot)[t]);
+            if (v >= mx && beats_all<kMaxThreads>(a, sm, ic, t, pslot, cslot, nslot))
+                append_maximum(a, pl, v, (uint32_t)(ic * NN + t));
         }
         __syncthreads();
-        if (pre) {
-            float *dst = sm.ring((ic + 2) % 3);
-            if (quads) {
-#pragma unroll
-                for (int u = 0; u < PER; ++u) {
-                    const int t = threadIdx.x + u * kMaxThreads;
-                    if (t < NQ) reinterpret_cast<float4 *>(dst)[t] = nxt[u];
-                }
-            } else {
-                for (int t = threadIdx.x; t < NN; t += kMaxThreads) dst[t] = src[t];
-            }
-        }
+        if (ic + 1 < i1 && ic + 2 < N)  // slice ic+2 replaces ic-1
+            for (int t = threadIdx.x; t < NN; t += kMaxThreads)
+                sm.ring((ic + 2) % 3)[t] = grid[(int64_t)(ic + 2) * NN + t];
         __syncthreads();
     }
+}
+
+// Exact test of node t of slice i (value v) against its 26 neighbours, read from the grid in
+// memory: a neighbour beats it with a larger key (ordered value bits, then the smaller linear
+// index).  Loads take a uniform slice base and a 32-bit byte offset.
+__device__ __forceinline__ bool beats_all_mem(const float *grid, int N, int i, int t, float v)
+{
+    const int NN = N * N;
+    const int j = t / N, k = t - (t / N) * N;
+    const uint32_t rows[3] = {(uint32_t)((j == 0 ? N - 1 : j - 1) * N), (uint32_t)(j * N),
+                              (uint32_t)((j == N - 1 ? 0 : j + 1) * N)};
+    const uint32_t cols[3] = {(uint32_t)(k == 0 ? N - 1 : k - 1), (uint32_t)k, (uint32_t)(k == N - 1 ? 0 : k + 1)};
+    const uint32_t ov = ordered_bits(v);
+    const uint32_t idx = (uint32_t)(i * NN + t);
+    bool win = true;
+#pragma unroll 1
+    for (int di = 0; di < 3; ++di) {
+        const int s = i + di - 1;
+        if (s < 0 || s >= N) continue;
+        const char *pl = reinterpret_cast<const char *>(grid + (int64_t)s * NN);
+        float nb[9];
+#pragma unroll
+        for (int d = 0; d < 9; ++d) nb[d] = *reinterpret_cast<const float *>(pl + 4u * (rows[d / 3] + cols[d % 3]));
+        // bitwise operators keep the compares branch-free; the node itself never beats itself
+#pragma unroll
+        for (int d = 0; d < 9; ++d) {
+            const uint32_t o = (uint32_t)(s * NN) + rows[d / 3] + cols[d % 3];
+            const uint32_t ou = ordered_bits(nb[d]);
+            win &= !((ou > ov) | ((ou == ov) & (o < idx)));
+        }
+    }
+    return win;
+}
+
+// One slice's float4 quads of this thread (quad threadIdx.x + u * kMaxThreads), slice s clamped
+// to [0, n): unconditional loads at clamped addresses, so that the number in flight is known
+// where they are consumed (a load skipped on some path would force a full wait).
+template <int PER>
+__device__ __forceinline__ void load_quads(const float *grid, int N, int NQ, int s, float4 (&dst)[PER])
+{
+    const char *base = reinterpret_cast<const char *>(grid + (int64_t)min(max(s, 0), N - 1) * 4 * NQ);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const uint32_t qd = (uint32_t)min((int)threadIdx.x + u * kMaxThreads, NQ - 1);
+        dst[u] = *reinterpret_cast<const float4 *>(base + 16u * qd);
+    }
+}
+
+// n a multiple of 4: each thread owns up to PER float4 quads of a slice and carries them through
+// the workgroup's slices with the previous and next slice's quads in registers, so the three-
+// slice window costs no LDS.  Only the current slice goes to LDS (double-buffered), for the row
+// and column neighbours.  The slice after next is loaded while the current one is tested; the
+// four register sets change roles from slice to slice (the slice loop is unrolled by four), so
+// no register copy waits for those loads.
+//   A node at least the largest of its six axis neighbours is a candidate.  Candidates are
+// queued in LDS (linear node index) for the whole run of slices and take the exact test in one
+// pass at the end, reading the grid in memory: memory loads are counted in issue order, so an
+// exact test between two slices would wait for the prefetched slice too.  A queue that
+// overflows (a flat grid, where every node ties with its neighbours) is ignored and every node
+// of the run takes the exact test instead.
+//   One barrier per slice: the LDS plane written for slice ic was last read for slice ic-2,
+// before the barrier of slice ic-1.
+struct MaximaQ {
+    const float *grid;
+    float *lds0;
+    uint32_t *queue;
+    uint32_t *qcount;
+    int N, NN, NQ, QR, plane, i1, qcap;
+};
+
+template <int PER>
+__device__ __forceinline__ void maxima_q_slice(const MaximaQ &M, int ic, const float4 (&prv)[PER], const float4 (&cur)[PER],
+                                               const float4 (&nxt)[PER], float4 (&nn2)[PER])
+{
+    // Past the run's end (its length not a multiple of four) a step still loads and waits, so
+    // that every path issues the same loads, and tests nothing.
+    const int N = M.N, QR = M.QR;
+    float *lc = M.lds0 + (ic & 1) * M.plane;
+    float4 *lc4 = reinterpret_cast<float4 *>(lc);
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int qd = threadIdx.x + u * kMaxThreads;
+        if (qd < M.NQ) lc4[qd] = cur[u];
+    }
+    // slice ic+2, needed from slice ic+1 on; past the run's last slice, slice i1 is reloaded
+    load_quads<PER>(M.grid, N, M.NQ, min(ic + 2, M.i1), nn2);
+    __syncthreads();
+    const bool hp = ic >= 1, hn = ic + 1 < N;  // absent slices count as -inf
+    const float ninf = -__builtin_huge_valf();
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+        const int qd = threadIdx.x + u * kMaxThreads;
+        if (qd < M.NQ && ic < M.i1) {
+            const int j = qd / QR, kq = qd - (qd / QR) * QR, k0 = 4 * kq;
+            const int jm = j == 0 ? N - 1 : j - 1, jp = j == N - 1 ? 0 : j + 1;
+            const float4 c = cur[u], up = lc4[jm * QR + kq], dn = lc4[jp * QR + kq];
+            const float left = lc[j * N + (k0 == 0 ? N - 1 : k0 - 1)];
+            const float right = lc[j * N + (k0 + 4 == N ? 0 : k0 + 4)];
+            const float4 pv = hp ? prv[u] : make_float4(ninf, ninf, ninf, ninf);
+            const float4 nv = hn ? nxt[u] : make_float4(ninf, ninf, ninf, ninf);
+            const float vv[4] = {c.x, c.y, c.z, c.w}, uu[4] = {up.x, up.y, up.z, up.w};
+            const float dd[4] = {dn.x, dn.y, dn.z, dn.w};
+            const float ll[4] = {left, c.x, c.y, c.z}, rr[4] = {c.y, c.z, c.w, right};
+            const float pp[4] = {pv.x, pv.y, pv.z, pv.w}, qq[4] = {nv.x, nv.y, nv.z, nv.w};
+            unsigned cand = 0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const float mx = fmaxf(fmaxf(fmaxf(uu[q], dd[q]), fmaxf(ll[q], rr[q])), fmaxf(pp[q], qq[q]));
+                cand |= (vv[q] >= mx ? 1u : 0u) << q;
+            }
+            if (cand) {
+                uint32_t e = atomicAdd(M.qcount, (uint32_t)__builtin_popcount(cand));
+                for (; cand; ++e) {
+                    if (e < (uint32_t)M.qcap) M.queue[e] = (uint32_t)(ic * M.NN + j * N + k0 + __builtin_ctz(cand));
+                    cand &= cand - 1;
+                }
+            }
+        }
+    }
+}
+
+template <int PER>
+__global__ void __launch_bounds__(kMaxThreads) k_soft_maxima_q(SoftArgs a)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ uint32_t qcount;
+    MaximaQ M;
+    M.N = a.n;
+    M.NN = M.N * M.N;
+    M.NQ = M.NN / 4;
+    M.QR = M.N / 4;
+    const int NG = (M.N + kMaxQSlices - 1) / kMaxQSlices;
+    const int pl = blockIdx.x / NG;
+    const int i0 = (blockIdx.x - pl * NG) * kMaxQSlices;
+    M.i1 = min(i0 + kMaxQSlices, M.N);  // tests slices i0 .. i1-1
+    M.plane = (int)(soft_align16(sizeof(float) * M.NN) / sizeof(float));
+    M.lds0 = reinterpret_cast<float *>(smem_raw);
+    M.queue = reinterpret_cast<uint32_t *>(M.lds0 + 2 * M.plane);
+    M.qcap = soft_maxima_qcap(M.N);
+    M.qcount = &qcount;
+    M.grid = a.grid + (int64_t)pl * M.N * M.NN;
+    float4 r0[PER], r1[PER], r2[PER], r3[PER];
+    load_quads<PER>(M.grid, M.N, M.NQ, i0 - 1, r0);
+    load_quads<PER>(M.grid, M.N, M.NQ, i0, r1);
+    load_quads<PER>(M.grid, M.N, M.NQ, i0 + 1, r2);
+    if (threadIdx.x == 0) qcount = 0u;
+    for (int ic = i0; ic < M.i1; ic += 4) {
+        maxima_q_slice<PER>(M, ic, r0, r1, r2, r3);
+        maxima_q_slice<PER>(M, ic + 1, r1, r2, r3, r0);
+        maxima_q_slice<PER>(M, ic + 2, r2, r3, r0, r1);
+        maxima_q_slice<PER>(M, ic + 3, r3, r0, r1, r2);
+    }
+    __syncthreads();
+    const uint32_t nc = qcount;
+    if (nc <= (uint32_t)M.qcap) {
+        for (uint32_t e = threadIdx.x; e < nc; e += kMaxThreads) {
+            const uint32_t idx = M.queue[e];
+            const int i = (int)(idx / (uint32_t)M.NN), t = (int)(idx - (uint32_t)i * M.NN);
+            const float v = M.grid[idx];
+            if (beats_all_mem(M.grid, M.N, i, t, v)) append_maximum(a, pl, v, idx);
+        }
+    } else {
+        for (int idx = i0 * M.NN + threadIdx.x; idx < M.i1 * M.NN; idx += kMaxThreads) {
+            const int i = idx / M.NN, t = idx - i * M.NN;
+            const float v = M.grid[idx];
+            if (beats_all_mem(M.grid, M.N, i, t, v)) append_maximum(a, pl, v, (uint32_t)idx);
+        }
+    }
+}
+
+// Quads per thread of the n-multiple-of-4 maxima kernel.
+inline int soft_maxima_per(int n)
+{
+    const int nq = n * n / 4;
+    for (int per : {3, 4, 6, 9})
+        if (nq <= per * kMaxThreads) return per;
+    return 0;
 }
 
 // Ranking of one particle's maxima (fast path), or the streaming search when its list
@@ -656,28 +858,43 @@ __global__ void __launch_bounds__(NT) k_soft_rank(SoftArgs a)
     if (threadIdx.x == 0) a.status[p] = nmax < Kc ? 16u : 0u;
 }
 
-size_t soft_grid_smem_bytes(int n, int B) { return soft_grid_smem(n, B, 1); }
+size_t soft_grid_smem_bytes(int n, int B)
+{
+    const GridShape sh = soft_grid_shape(n, B);
+    return soft_grid_smem(n, B, sh.waves, sh.tab_lds);
+}
 
 size_t soft_select_smem_bytes(int n, int threads)
 {
     return std::max(soft_select_smem(n, 2 * threads), soft_maxima_smem(n));
 }
 
-hipError_t launch_soft_grid(const SoftArgs &a0, int P, hipStream_t s)
+hipError_t launch_soft_wigner(const SoftArgs &a, int P, hipStream_t s)
 {
-    SoftArgs a = a0;
-    a.gslices = soft_grid_waves(a.n, a.B);
-    const int SB = a.gslices * kGridSPW;
-    const int NG = (a.n + SB - 1) / SB;
-    hipLaunchKernelGGL(k_soft_grid, dim3(P * NG), dim3(kWave * a.gslices), soft_grid_smem(a.n, a.B, a.gslices), s, a);
+    if (soft_wigner_cp_lds(a.B))
+        hipLaunchKernelGGL(k_soft_wigner<true>, dim3(P), dim3(kWignerThreads), wedge_row(a.B + 1) * sizeof(float4), s,
+                           a);
+    else
+        hipLaunchKernelGGL(k_soft_wigner<false>, dim3(P), dim3(kWignerThreads), 0, s, a);
     return hipGetLastError();
 }
 
-size_t soft_dft_floats(int n, int B)
+hipError_t launch_soft_grid(const SoftArgs &a0, int P, hipStream_t s)
 {
-    const GridGeom g = grid_geom(n, B);
-    return (size_t)2 * g.KP * g.NP + (size_t)g.NP * 4 * g.KS2;
+    SoftArgs a = a0;
+    const GridShape sh = soft_grid_shape(a.n, a.B);
+    a.gslices = sh.waves;
+    const int SB = a.gslices * kGridSPW;
+    const int NG = (a.n + SB - 1) / SB;
+    const size_t smem = soft_grid_smem(a.n, a.B, sh.waves, sh.tab_lds);
+    if (sh.tab_lds)
+        hipLaunchKernelGGL(k_soft_grid<true>, dim3(P * NG), dim3(kWave * a.gslices), smem, s, a);
+    else
+        hipLaunchKernelGGL(k_soft_grid<false>, dim3(P * NG), dim3(kWave * a.gslices), smem, s, a);
+    return hipGetLastError();
 }
+
+size_t soft_dft_floats(int n, int B) { return (size_t)grid_geom(n, B).TF; }
 
 // The DFT tables of k_soft_grid for (B, n), in FP64 with each angle reduced exactly as
 // (integer mod n) / n, rounded once: B1r, B1i [KP][NP], then A2 [NP][4 KS2]; padding is zero.
@@ -713,8 +930,19 @@ hipError_t launch_soft_select(const SoftArgs &a0, int P, int threads, hipStream_
     if (a0.n > kSelMaxN || (threads != 256 && threads != 512)) return hipErrorInvalidValue;
     SoftArgs a = a0;
     a.mcap = 2 * threads;  // == list_cap<threads>()
-    const int NG = (a.n + kMaxSlices - 1) / kMaxSlices;
-    hipLaunchKernelGGL(k_soft_maxima, dim3(P * NG), dim3(kMaxThreads), soft_maxima_smem(a.n), s, a);
+    const int per = a.n % 4 == 0 ? soft_maxima_per(a.n) : 0;
+    const int NGq = (a.n + kMaxQSlices - 1) / kMaxQSlices, NG = (a.n + kMaxSlices - 1) / kMaxSlices;
+    const size_t qs = soft_maxima_q_smem(a.n);
+    if (per == 3)
+        hipLaunchKernelGGL(k_soft_maxima_q<3>, dim3(P * NGq), dim3(kMaxThreads), qs, s, a);
+    else if (per == 4)
+        hipLaunchKernelGGL(k_soft_maxima_q<4>, dim3(P * NGq), dim3(kMaxThreads), qs, s, a);
+    else if (per == 6)
+        hipLaunchKernelGGL(k_soft_maxima_q<6>, dim3(P * NGq), dim3(kMaxThreads), qs, s, a);
+    else if (per == 9)
+        hipLaunchKernelGGL(k_soft_maxima_q<9>, dim3(P * NGq), dim3(kMaxThreads), qs, s, a);
+    else
+        hipLaunchKernelGGL(k_soft_maxima, dim3(P * NG), dim3(kMaxThreads), soft_maxima_smem(a.n), s, a);
     if (threads == 256)
         hipLaunchKernelGGL(k_soft_rank<256>, dim3(P), dim3(256), soft_select_smem(a.n, list_cap<256>()), s, a);
     else

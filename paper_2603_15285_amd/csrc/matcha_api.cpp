@@ -199,31 +199,41 @@ matcha_status ensure_grid(matcha_ctx *ctx, int B, int n)
     return MATCHA_OK;
 }
 
-// The SOFFT grid of a particle (n^3 floats) lives in a workspace between the kernels, with the
-// particle's list of maxima keys and their count; batches whose workspace would exceed
-// kSoftWsCap run in chunks of particles.  Layout of a chunk of pc particles: the grids, then
-// pc lists of kSoftListMax keys, then pc counts.
-constexpr size_t kSoftWsCap = (size_t)2 << 30;
+// The SOFFT search of a particle keeps in a workspace, between its kernels: the Wigner
+// transforms of its n polar nodes ((B+1)(2B+1) complex each), its grid (n^3 floats) and its list
+// of maxima keys with their count.  Batches whose workspace would exceed kSoftWsCap run in chunks
+// of particles.  Layout of a chunk of pc particles (each region 256-byte aligned): the grids, pc
+// lists of kSoftListMax keys, pc counts, the Wigner transforms.
+constexpr size_t kSoftWsCap = (size_t)4 << 30;
 constexpr size_t kSoftListMax = 1024;  // keys per particle: the larger select workgroup's list
 
 size_t soft_grid_bytes(int n) { return (size_t)n * n * n * sizeof(float); }
-size_t soft_particle_bytes(int n)
+size_t soft_s_bytes(int n, int B) { return (size_t)n * (B + 1) * (2 * B + 1) * sizeof(float2); }
+size_t soft_particle_bytes(int n, int B)
 {
-    return soft_grid_bytes(n) + kSoftListMax * sizeof(unsigned long long) + sizeof(uint32_t);
+    return soft_grid_bytes(n) + kSoftListMax * sizeof(unsigned long long) + sizeof(uint32_t) + soft_s_bytes(n, B);
 }
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Bytes for a chunk of pc particles (each region 256-byte aligned).
-size_t soft_chunk_bytes(size_t pc, int n)
+struct SoftChunk {
+    size_t grid, list, count, S, total;  // region offsets and total bytes
+};
+
+SoftChunk soft_chunk(size_t pc, int n, int B)
 {
-    return align256(pc * soft_grid_bytes(n)) + align256(pc * kSoftListMax * sizeof(unsigned long long)) +
-           align256(pc * sizeof(uint32_t));
+    SoftChunk c;
+    c.grid = 0;
+    c.list = align256(pc * soft_grid_bytes(n));
+    c.count = c.list + align256(pc * kSoftListMax * sizeof(unsigned long long));
+    c.S = c.count + align256(pc * sizeof(uint32_t));
+    c.total = c.S + align256(pc * soft_s_bytes(n, B));
+    return c;
 }
 
-size_t soft_ws_need(int P, int n)
+size_t soft_ws_need(int P, int n, int B)
 {
-    const size_t pc = std::max<size_t>(1, std::min<size_t>((size_t)P, kSoftWsCap / soft_particle_bytes(n)));
-    return soft_chunk_bytes(pc, n);
+    const size_t pc = std::max<size_t>(1, std::min<size_t>((size_t)P, kSoftWsCap / soft_particle_bytes(n, B)));
+    return soft_chunk(pc, n, B).total;
 }
 
 matcha_status ensure_soft_ws(matcha_ctx *ctx, size_t bytes)
@@ -471,11 +481,12 @@ matcha_status soft_check(matcha_ctx *ctx, const matcha_batch *batch, const float
 matcha_status soft_search_ws(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *cfg,
                              float *cand, uint32_t *status, int nt, float *ws, size_t ws_bytes, hipStream_t s)
 {
-    const int P = batch->n_particles, n = cfg->n_grid;
-    if (!ws || ws_bytes < soft_chunk_bytes(1, n)) return MATCHA_ERR_INVALID_ARG;
-    size_t pcs = std::min<size_t>((size_t)P, ws_bytes / soft_particle_bytes(n));
-    while (pcs > 1 && soft_chunk_bytes(pcs, n) > ws_bytes) --pcs;
+    const int P = batch->n_particles, n = cfg->n_grid, B = cfg->B;
+    if (!ws || ws_bytes < soft_chunk(1, n, B).total) return MATCHA_ERR_INVALID_ARG;
+    size_t pcs = std::min<size_t>((size_t)P, ws_bytes / soft_particle_bytes(n, B));
+    while (pcs > 1 && soft_chunk(pcs, n, B).total > ws_bytes) --pcs;
     const int pc = (int)std::max<size_t>(pcs, 1);
+    const SoftChunk ch = soft_chunk((size_t)pc, n, B);
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     char *base = reinterpret_cast<char *>(ws);
     SoftArgs a;
@@ -485,18 +496,19 @@ matcha_status soft_search_ws(matcha_ctx *ctx, const matcha_batch *batch, const f
     a.dgrid = ctx->dgrid;
     a.dft = ctx->dft;
     a.pinfo = ctx->pinfo;
-    a.B = cfg->B;
+    a.B = B;
     a.n = n;
     a.Kc = cfg->Kc;
-    a.grid = reinterpret_cast<float *>(base);
-    a.mlist = reinterpret_cast<unsigned long long *>(base + align256((size_t)pc * soft_grid_bytes(n)));
-    a.mcount = reinterpret_cast<uint32_t *>(base + align256((size_t)pc * soft_grid_bytes(n)) +
-                                            align256((size_t)pc * kSoftListMax * sizeof(unsigned long long)));
+    a.grid = reinterpret_cast<float *>(base + ch.grid);
+    a.mlist = reinterpret_cast<unsigned long long *>(base + ch.list);
+    a.mcount = reinterpret_cast<uint32_t *>(base + ch.count);
+    a.S = reinterpret_cast<float2 *>(base + ch.S);
     a.cand = reinterpret_cast<float4 *>(cand);
     a.status = status;
     for (int p0 = 0; p0 < P; p0 += pc) {
         const int cnt = std::min(pc, P - p0);
         a.p0 = p0;
+        if (launch_soft_wigner(a, cnt, s) != hipSuccess) return MATCHA_ERR_HIP;
         if (launch_soft_grid(a, cnt, s) != hipSuccess) return MATCHA_ERR_HIP;
         if (launch_soft_select(a, cnt, nt, s) != hipSuccess) return MATCHA_ERR_HIP;
     }
@@ -513,7 +525,7 @@ matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, con
     int nt = 0;
     matcha_status st = soft_check(ctx, batch, C, cfg, cand, status, &nt);
     if (st != MATCHA_OK || batch->n_particles == 0) return st;
-    st = ensure_soft_ws(ctx, soft_ws_need(batch->n_particles, cfg->n_grid));
+    st = ensure_soft_ws(ctx, soft_ws_need(batch->n_particles, cfg->n_grid, cfg->B));
     if (st != MATCHA_OK) return st;
     return soft_search_ws(ctx, batch, C, cfg, cand, status, nt, ctx->soft_ws, ctx->soft_ws_bytes,
                           static_cast<hipStream_t>(stream));
@@ -680,7 +692,7 @@ matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *bat
     if (!g) return MATCHA_ERR_HIP;
     g->device = ctx->device;
     const int P = batch->n_particles;
-    const size_t ws_bytes = P > 0 ? soft_ws_need(P, soft->n_grid) : 0;
+    const size_t ws_bytes = P > 0 ? soft_ws_need(P, soft->n_grid, soft->B) : 0;
     if (P > 0 && hipMalloc(&g->soft_ws, ws_bytes) != hipSuccess) {
         delete g;
         return MATCHA_ERR_HIP;

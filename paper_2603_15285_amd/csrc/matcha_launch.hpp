@@ -42,6 +42,7 @@ struct SoftArgs {
     int gslices;              // waves per workgroup of the grid kernel (set by its launcher)
     int p0;                   // first particle of this launch
     float *grid;              // [launch particles][n][n][n] workspace: C_B on the grid
+    float2 *S;                // [launch particles][n][(B+1)(2B+1)] workspace: Wigner transforms
     unsigned long long *mlist;  // [launch particles][mcap] keys of the local maxima (workspace)
     uint32_t *mcount;         // [launch particles] maxima found (may exceed mcap)
     int mcap;                 // keys kept per particle (set by the select launcher)
@@ -111,6 +112,7 @@ size_t soft_grid_smem_bytes(int n, int B);
 size_t soft_dft_floats(int n, int B);
 void build_soft_dft(int B, int n, float *t);
 size_t soft_select_smem_bytes(int n, int threads);
+hipError_t launch_soft_wigner(const SoftArgs &a, int P, hipStream_t s);
 hipError_t launch_soft_grid(const SoftArgs &a, int P, hipStream_t s);
 hipError_t launch_soft_select(const SoftArgs &a, int P, int threads, hipStream_t s);
 

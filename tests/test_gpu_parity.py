@@ -154,6 +154,41 @@ def test_soft_search_few_maxima(M, ctx):
         assert status[p] & M.ST_FEW_MAXIMA
 
 
+@pytest.mark.parametrize("n", [30, 27])
+def test_soft_search_grid_not_multiple_of_4(M, ctx, n):
+    """Grid sizes that do not split into float4 quads take the general maxima kernel."""
+    b = S.make_batch(12, 6, 2, seed=31 + n, snr=0.1)
+    batch, f, h, w = upload(M, b)
+    C = M.coeff_assemble(ctx, batch, f, h, w)
+    cand, status = M.soft_search(ctx, batch, C, 7, n, 12)
+    cand, status = cand.cpu().numpy(), status.cpu().numpy()
+    for p in range(2):
+        check_soft(b, p, cand[p], int(status[p]), 7, n, 12)
+
+
+@pytest.mark.parametrize("n", [48, 30])
+def test_soft_search_flat_grid(M, ctx, n):
+    """Zero data give a grid of exact zeros, where every node ties with all its neighbours: only
+    node 0 is a local maximum under the index tie-break (every other node has a neighbour with a
+    smaller index), and the rest of the list is the next nodes in index order.  Every node of
+    the grid is a candidate, which overflows the candidate queue of the quad maxima kernel and
+    sends it to its node-by-node path.  The result is unique and must equal the oracle's."""
+    B, Kc = 12, 16
+    b = S.make_batch(16, 4, 2, seed=3, snr=0.1)
+    batch, f, h, w = upload(M, b)
+    f.zero_()
+    C = M.coeff_assemble(ctx, batch, f, h, w)
+    assert not torch.any(C != 0)
+    cand, status = M.soft_search(ctx, batch, C, B, n, Kc)
+    cand, status = cand.cpu().numpy(), status.cpu().numpy()
+    idx, val, nmx = O.soft_select(O.soft_grid(B, np.zeros_like(oracle_C(b, 0)), n), Kc)
+    assert nmx == 1 and np.array_equal(idx, np.arange(Kc))
+    for p in range(2):
+        assert status[p] & M.ST_FEW_MAXIMA
+        assert np.all(cand[p, :, 3] == 0)
+        assert np.allclose(cand[p, :, :3], O.grid_euler(idx, n).astype(np.float32), atol=1e-6)
+
+
 @pytest.mark.parametrize("L,B,n", [(16, 16, 64), (24, 24, 48)])
 def test_soft_search_many_maxima(M, L, B, n):
     """Noise-dominated grids with 763 (B=16, n=64) and 1440 (B=24, n=48) local maxima (oracle

@@ -4,17 +4,22 @@
 // wedge layout: the value at (m, n) lands in slot 0 of the wedge pair (m, n) when |n| <= m,
 // otherwise in slot 1 (the partner slot) of the pair (n, m) (n > 0) or (-n, -m) (n < 0).
 //
-// Per degree the half plane is the complex product (l+1) x R times R x (2l+1).  In real form,
-// with the shells interleaved (Re, Im) along K = 2R,
-//   Cr[m][j] = sum_k A[m][k] Br[k][j],  Ci[m][j] = sum_k A[m][k] Bi[k][j],
-//   A[m][2r] = Re f,  A[m][2r+1] = Im f,
-//   Br[2r][j] = w_r Re h,  Br[2r+1][j] = w_r Im h,  Bi[2r][j] = -w_r Im h,  Bi[2r+1][j] = w_r Re h,
-// it runs on the matrix cores in FP32 (v_mfma_f32_16x16x4_f32: lane i supplies A[i%16][i/16]
-// and B[i/16][i%16] of a 16 x 4 x 16 step and holds D rows 4(i/16) .. +3 of column i%16).
-// Operands come straight from memory: a wave owns a 16-row tile of one degree, keeps its A
-// column (one float per K step) in registers, and sweeps the 16-column tiles of B, whose
-// template rows are shared by every particle and stay in L2.  The waves of a workgroup take
-// the (degree, row tile) units of one particle's degree chunk in turn, with no barrier.
+// The template h is shared by every particle, so per degree the whole batch is one tall
+// product: the rows (p, m), m <= l, of all particles stacked, times the template's (2l+1)
+// columns.  In real form, with the shells interleaved (Re, Im) along K = 2R,
+//   Cr[row][j] = sum_k A[row][k] Br[k][j],  Ci[row][j] = sum_k A[row][k] Bi[k][j],
+//   A[(p,m)][2r] = w_r Re f_lm(r),  A[(p,m)][2r+1] = w_r Im f_lm(r),
+//   Br[2r][j] = Re h,  Br[2r+1][j] = Im h,  Bi[2r][j] = -Im h,  Bi[2r+1][j] = Re h,
+// on the matrix cores in FP32 (v_mfma_f32_16x16x4_f32: lane i supplies A[i%16][i/16] and
+// B[i/16][i%16] of a 16 x 4 x 16 step and holds D rows 4(i/16) .. +3 of column i%16).
+//
+// A workgroup takes one degree and a run of 16-row tiles of its stacked rows.  It copies the
+// template's degree-l row, h_l(r) for all shells, into LDS once; each wave then loads the A
+// column of a row tile straight from f (every f value is read once), keeps it in registers
+// and sweeps the column tiles with B from LDS.  Rows of one tile may belong to several
+// particles, so small degrees still fill the 16-row tiles.  Rows of particles with L_p < l
+// and shells r >= R_p are masked to zero.  Workgroups of the highest degrees (most column
+// tiles) are launched first.
 #include "matcha_launch.hpp"
 
 namespace matcha {
@@ -22,7 +27,10 @@ namespace matcha {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kAsmThreads = 256;
-constexpr int kAsmMaxSteps = 16;  // K steps (of 2 shells) held in registers at a time
+constexpr int kAsmWaves = kAsmThreads / kWave;
+constexpr int kAsmMaxSteps = 16;     // K steps (of 2 shells) held in registers at a time
+constexpr int kAsmTilesPerWave = 4;  // row tiles per wave and workgroup
+constexpr int kAsmTilesPerBlock = kAsmWaves * kAsmTilesPerWave;
 
 __device__ inline void store_half_plane(float2 *Cp2, int l, int m, int n, float2 v)
 {
@@ -42,83 +50,111 @@ __device__ inline void store_half_plane(float2 *Cp2, int l, int m, int n, float2
     }
 }
 
+// Columns of degree l padded to whole 16-column tiles.
+__host__ __device__ inline int asm_cols(int l) { return 16 * ((2 * l + 1 + 15) / 16); }
+
 __global__ void __launch_bounds__(kAsmThreads) k_assemble_f32(AsmArgs a)
 {
-    const int p = blockIdx.x / a.n_chunks, chunk = blockIdx.x % a.n_chunks;
-    const int L = a.Lp[p], R = a.Rp[p];
-    const int l_lo = a.chunk_lo[chunk], l_hi = min(a.chunk_lo[chunk + 1] - 1, L);
-    // element offsets within one particle's f and within h fit 32 bits (the library bounds
-    // R_h (L_h+1)^2 below 2^31), so loads take a uniform base and a 32-bit per-lane offset
-    const int sf = (L + 1) * (L + 1), sh = (a.Lh + 1) * (a.Lh + 1);
-    const float2 *fp = a.f + a.f_off[p];
-    float2 *Cp2 = reinterpret_cast<float2 *>(a.C + a.C_off[p] / 2);
+    extern __shared__ __align__(16) float2 hs[];  // [Rmax][asm_cols(l)]: h_l(r) of the degree
+    // the workgroup's degree: blocks of degree Lmax - d start at blk_lo[d]
+    int d = 0;
+    while ((int)blockIdx.x >= a.blk_lo[d + 1]) ++d;
+    const int l = a.Lmax - d, blk = blockIdx.x - a.blk_lo[d];
+    const int N = 2 * l + 1, NP = asm_cols(l), ntn = NP / 16;
+    const int R = a.Rmax, sh = (a.Lh + 1) * (a.Lh + 1);
+    float *ws = reinterpret_cast<float *>(hs + R * NP);  // [Rmax] shell weights
+    for (int t = threadIdx.x; t < R * NP; t += kAsmThreads) {
+        const int r = t / NP, j = t - (t / NP) * NP;
+        hs[t] = j < N ? a.h[r * sh + l * l + j] : make_float2(0.f, 0.f);
+    }
+    for (int t = threadIdx.x; t < R; t += kAsmThreads) ws[t] = a.w[t];
+    __syncthreads();
+    const int rows = a.P * (l + 1), RT = (rows + 15) / 16;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int nwaves = kAsmThreads / kWave;
     const int col = lane % 16, kq = lane / 16;
     const int par = kq & 1, rsub = kq >> 1;  // K index 4 s + kq = 2 (2 s + rsub) + par
     const int nsteps = (R + 1) / 2;
-    int u = 0;
-    // heaviest degrees first, so the units spread evenly over the waves
-    for (int l = l_hi; l >= l_lo; --l) {
-        const int ntm = (l + 16) / 16, ntn = (2 * l + 16) / 16;
-        const int lrow = l * l;
-        for (int tm = 0; tm < ntm; ++tm, ++u) {
-            if (u % nwaves != wave) continue;
-            const int m = 16 * tm + col;
-            const bool mok = m <= l;
-            const int mc = min(m, l);
-            float av[kAsmMaxSteps], wv[kAsmMaxSteps];
-            for (int tn = 0; tn < ntn; ++tn) {
-                const int j = 16 * tn + col;
-                const bool jok = j < 2 * l + 1;
-                const int jc = min(j, 2 * l);
-                f32x4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-                for (int s0 = 0; s0 < nsteps; s0 += kAsmMaxSteps) {
-                    // Loads are unconditional at clamped (valid, finite) addresses and masked by a
-                    // 0/1 factor afterwards, so that all of a chunk's loads are in flight together.
-                    // With one chunk (R <= 32) the A column and the weights are loaded once per
-                    // tile row.
-                    if (tn == 0 || nsteps > kAsmMaxSteps) {
+    for (int it = 0; it < kAsmTilesPerWave; ++it) {
+        const int rt = blk * kAsmTilesPerBlock + it * kAsmWaves + wave;
+        if (rt >= RT) break;
+        // the lane's A row
+        const int rho = min(16 * rt + col, rows - 1);
+        const int p = rho / (l + 1), m = rho - p * (l + 1);
+        const int Lp = a.Lp[p], Rp = a.Rp[p];
+        const bool rok = 16 * rt + col < rows && l <= Lp;
+        const int sf = (Lp + 1) * (Lp + 1);
+        const float2 *fp = a.f + a.f_off[p] + (l <= Lp ? l * l + l + m : 0);  // in the particle's f
+        // the lane's output rows: C of their particles and their m (rows past the batch or of
+        // particles with L_p < l are not stored)
+        float2 *cp[4];
+        int mo[4];
+        bool ook[4];
 #pragma unroll
-                        for (int s = 0; s < kAsmMaxSteps; ++s) {
-                            const int r = 2 * (s0 + s) + rsub;
-                            const int rc = min(r, R - 1);
-                            const float2 v = fp[rc * sf + lrow + l + mc];
-                            const float keep = (r < R && mok) ? 1.f : 0.f;
-                            av[s] = (par ? v.y : v.x) * keep;
-                            wv[s] = a.w[rc] * (r < R ? 1.f : 0.f);
-                        }
-                    }
-                    float2 hv[kAsmMaxSteps];
-#pragma unroll
-                    for (int s = 0; s < kAsmMaxSteps; ++s)
-                        hv[s] = a.h[min(2 * (s0 + s) + rsub, R - 1) * sh + lrow + jc];
-                    __builtin_amdgcn_sched_barrier(0);
-                    const float jmask = jok ? 1.f : 0.f;
+        for (int v = 0; v < 4; ++v) {
+            const int ro = 16 * rt + 4 * kq + v;
+            const int po = min(ro, rows - 1) / (l + 1);
+            const int Lpo = a.Lp[po];
+            mo[v] = ro - po * (l + 1);
+            ook[v] = (ro < rows) & (l <= Lpo);
+            cp[v] = reinterpret_cast<float2 *>(a.C + a.C_off[po] / 2);
+        }
+        float av[kAsmMaxSteps];
+        for (int tn = 0; tn < ntn; ++tn) {
+            f32x4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
+            for (int s0 = 0; s0 < nsteps; s0 += kAsmMaxSteps) {
+                // A: unconditional loads at clamped (valid, finite) addresses, masked by the
+                // shell weight or 0 afterwards, so that all of a chunk's loads are in flight
+                // together.  With one chunk (R <= 32) the A column is loaded once per row tile.
+                if (tn == 0 || nsteps > kAsmMaxSteps) {
 #pragma unroll
                     for (int s = 0; s < kAsmMaxSteps; ++s) {
-                        const float wr = wv[s] * jmask;
-                        const float br = wr * (par ? hv[s].y : hv[s].x);
-                        const float bi = par ? wr * hv[s].x : -(wr * hv[s].y);
-                        cr = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], br, cr, 0, 0, 0);
-                        ci = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bi, ci, 0, 0, 0);
+                        const int r = 2 * (s0 + s) + rsub;
+                        const int rc = min(r, Rp - 1);
+                        const float2 v = fp[rc * sf];
+                        const float keep = ws[rc] * ((r < Rp && rok) ? 1.f : 0.f);
+                        av[s] = (par ? v.y : v.x) * keep;
                     }
                 }
+                __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int mo = 16 * tm + 4 * kq + v;
-                    if (mo <= l && jok) store_half_plane(Cp2, l, mo, j - l, make_float2(cr[v], ci[v]));
+                for (int s = 0; s < kAsmMaxSteps; ++s) {
+                    const float2 hv = hs[min(2 * (s0 + s) + rsub, R - 1) * NP + 16 * tn + col];
+                    const float br = par ? hv.y : hv.x;
+                    const float bi = par ? hv.x : -hv.y;
+                    cr = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], br, cr, 0, 0, 0);
+                    ci = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], bi, ci, 0, 0, 0);
                 }
+            }
+            const int j = 16 * tn + col;
+            if (j < N) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    if (ook[v]) store_half_plane(cp[v], l, mo[v], j - l, make_float2(cr[v], ci[v]));
             }
         }
     }
 }
 
-size_t assemble_smem_bytes(int, int) { return 0; }
-
-hipError_t launch_assemble_f32(const AsmArgs &a, int P, int, int, hipStream_t s)
+size_t assemble_smem_bytes(int Lmax, int Rmax)
 {
-    hipLaunchKernelGGL(k_assemble_f32, dim3(P * a.n_chunks), dim3(kAsmThreads), 0, s, a);
+    return sizeof(float2) * (size_t)Rmax * asm_cols(Lmax) + sizeof(float) * (size_t)Rmax;
+}
+
+hipError_t launch_assemble_f32(const AsmArgs &a0, int P, int Lmax, int Rmax, hipStream_t s)
+{
+    AsmArgs a = a0;
+    a.P = P;
+    a.Lmax = Lmax;
+    a.Rmax = Rmax;
+    int nb = 0;
+    for (int d = 0; d <= Lmax; ++d) {
+        const int l = Lmax - d;
+        const int64_t rt = ((int64_t)P * (l + 1) + 15) / 16;
+        a.blk_lo[d] = nb;
+        nb += (int)((rt + kAsmTilesPerBlock - 1) / kAsmTilesPerBlock);
+    }
+    a.blk_lo[Lmax + 1] = nb;
+    hipLaunchKernelGGL(k_assemble_f32, dim3(nb), dim3(kAsmThreads), assemble_smem_bytes(Lmax, Rmax), s, a);
     return hipGetLastError();
 }
 

@@ -408,19 +408,6 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
     const size_t smem = prec == MATCHA_FP32 ? assemble_smem_bytes(hi, rmax) : assemble_bf16_smem_bytes(hi, rmax);
     if (smem > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    // split 0..hi into up to 4 chunks of about equal work, sum_l (l+1)(2l+1)
-    int n_chunks = 0, chunk_lo[9] = {0};
-    {
-        double total = 0.0;
-        for (int l = 0; l <= hi; ++l) total += (l + 1.0) * (2.0 * l + 1.0);
-        const int want = hi >= 8 ? 4 : 1;
-        double acc = 0.0;
-        for (int l = 0; l <= hi; ++l) {
-            acc += (l + 1.0) * (2.0 * l + 1.0);
-            if (acc >= total * (n_chunks + 1) / want && n_chunks + 1 < want && l < hi) chunk_lo[++n_chunks] = l + 1;
-        }
-        chunk_lo[++n_chunks] = hi + 1;
-    }
     if (prec == MATCHA_BF16_FP32ACC) {
         AsmBArgs b;
         std::memset(&b, 0, sizeof b);
@@ -433,8 +420,6 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
         b.Lh = batch->L_h;
         b.C = reinterpret_cast<float4 *>(C);
         b.C_off = batch->C_offset;
-        b.n_chunks = n_chunks;
-        for (int c = 0; c <= n_chunks; ++c) b.chunk_lo[c] = chunk_lo[c];
         return launched(launch_assemble_bf16(b, batch->n_particles, hi, rmax, static_cast<hipStream_t>(stream)));
     }
     AsmArgs a;
@@ -448,8 +433,6 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
     a.Lh = batch->L_h;
     a.C = reinterpret_cast<float4 *>(C);
     a.C_off = batch->C_offset;
-    a.n_chunks = n_chunks;
-    for (int c = 0; c <= n_chunks; ++c) a.chunk_lo[c] = chunk_lo[c];
     return launched(launch_assemble_f32(a, batch->n_particles, hi, rmax, static_cast<hipStream_t>(stream)));
 }
 

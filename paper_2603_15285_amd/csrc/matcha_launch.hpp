@@ -14,8 +14,8 @@ struct AsmArgs {
     int Lh;
     float4 *C;
     const int64_t *C_off;
-    int n_chunks;             // degrees are split into chunks [chunk_lo[c], chunk_lo[c+1])
-    int chunk_lo[9];
+    int P, Lmax, Rmax;        // set by the launcher
+    int blk_lo[kMaxL + 2];    // first workgroup of degree Lmax - d, d = 0 .. Lmax; [Lmax+1]: total
 };
 
 struct AsmBArgs {
@@ -28,8 +28,8 @@ struct AsmBArgs {
     int Lh;
     float4 *C;
     const int64_t *C_off;
-    int n_chunks;
-    int chunk_lo[9];
+    int P, Lmax, Rmax;        // set by the launcher
+    int blk_lo[kMaxL + 2];    // first workgroup of degree Lmax - d, d = 0 .. Lmax; [Lmax+1]: total
 };
 
 struct SoftArgs {

@@ -166,7 +166,10 @@ matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg
  * the radial index:  C^l_mn = sum_{r < R_p} w_r f_lm(r) conj(h_ln(r)), l <= L_p.
  * f, h: complex float32 (MATCHA_FP32) or complex bfloat16 (MATCHA_BF16_FP32ACC,
  * interleaved (re, im) bf16 pairs); w: float32 [R_h]; C: complex float32, wedge
- * layout.  Accumulation is FP32 in both modes. */
+ * layout.  Accumulation is FP32 in both modes.  The template's degree-L_max row over
+ * R_max = max_p R_p shells is staged in one workgroup's LDS: MATCHA_ERR_UNSUPPORTED when
+ * 8 R_max 16 ceil((2 L_max + 1) / 16) bytes (FP32; BF16: 4 (2 R_max rounded up to 32, + 8)
+ * 16 ceil((2 L_max + 1) / 16)) exceed 160 KB, e.g. R_max > 142 at L_max = 64 in FP32. */
 matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
                                     const float *w, float *C, matcha_precision prec, void *stream);
 

@@ -28,7 +28,6 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kAsmThreads = 256;
 constexpr int kAsmWaves = kAsmThreads / kWave;
-constexpr int kAsmMaxSteps = 16;     // K steps (of 2 shells) held in registers at a time
 constexpr int kAsmTilesPerWave = 4;  // row tiles per wave and workgroup
 constexpr int kAsmTilesPerBlock = kAsmWaves * kAsmTilesPerWave;
 
@@ -53,6 +52,9 @@ __device__ inline void store_half_plane(float2 *Cp2, int l, int m, int n, float2
 // Columns of degree l padded to whole 16-column tiles.
 __host__ __device__ inline int asm_cols(int l) { return 16 * ((2 * l + 1 + 15) / 16); }
 
+// MS: K steps (of 2 shells) held in registers at a time; 16 for R <= 32, 32 for R <= 64, so that
+// the A column of a row tile is loaded once; with more shells it is reloaded per column tile.
+template <int MS>
 __global__ void __launch_bounds__(kAsmThreads) k_assemble_f32(AsmArgs a)
 {
     extern __shared__ __align__(16) float2 hs[];  // [Rmax][asm_cols(l)]: h_l(r) of the degree
@@ -98,16 +100,16 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_f32(AsmArgs a)
             ook[v] = (ro < rows) & (l <= Lpo);
             cp[v] = reinterpret_cast<float2 *>(a.C + a.C_off[po] / 2);
         }
-        float av[kAsmMaxSteps];
+        float av[MS];
         for (int tn = 0; tn < ntn; ++tn) {
             f32x4 cr = {0.f, 0.f, 0.f, 0.f}, ci = {0.f, 0.f, 0.f, 0.f};
-            for (int s0 = 0; s0 < nsteps; s0 += kAsmMaxSteps) {
+            for (int s0 = 0; s0 < nsteps; s0 += MS) {
                 // A: unconditional loads at clamped (valid, finite) addresses, masked by the
                 // shell weight or 0 afterwards, so that all of a chunk's loads are in flight
-                // together.  With one chunk (R <= 32) the A column is loaded once per row tile.
-                if (tn == 0 || nsteps > kAsmMaxSteps) {
+                // together.  With one chunk the A column is loaded once per row tile.
+                if (tn == 0 || nsteps > MS) {
 #pragma unroll
-                    for (int s = 0; s < kAsmMaxSteps; ++s) {
+                    for (int s = 0; s < MS; ++s) {
                         const int r = 2 * (s0 + s) + rsub;
                         const int rc = min(r, Rp - 1);
                         const float2 v = fp[rc * sf];
@@ -117,7 +119,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_f32(AsmArgs a)
                 }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                for (int s = 0; s < kAsmMaxSteps; ++s) {
+                for (int s = 0; s < MS; ++s) {
                     const float2 hv = hs[min(2 * (s0 + s) + rsub, R - 1) * NP + 16 * tn + col];
                     const float br = par ? hv.y : hv.x;
                     const float bi = par ? hv.x : -hv.y;
@@ -154,7 +156,11 @@ hipError_t launch_assemble_f32(const AsmArgs &a0, int P, int Lmax, int Rmax, hip
         nb += (int)((rt + kAsmTilesPerBlock - 1) / kAsmTilesPerBlock);
     }
     a.blk_lo[Lmax + 1] = nb;
-    hipLaunchKernelGGL(k_assemble_f32, dim3(nb), dim3(kAsmThreads), assemble_smem_bytes(Lmax, Rmax), s, a);
+    const size_t smem = assemble_smem_bytes(Lmax, Rmax);
+    if (Rmax > 32 && Rmax <= 64)
+        hipLaunchKernelGGL(k_assemble_f32<32>, dim3(nb), dim3(kAsmThreads), smem, s, a);
+    else
+        hipLaunchKernelGGL(k_assemble_f32<16>, dim3(nb), dim3(kAsmThreads), smem, s, a);
     return hipGetLastError();
 }
 

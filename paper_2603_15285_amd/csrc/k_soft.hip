@@ -316,6 +316,139 @@ __global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
     }
 }
 
+// ---------------------------------------------------------------- grid synthesis in registers
+//
+// The same two products for small bands, with no LDS: every operand lives in registers.
+//   * The DFT tables are the same for every node and particle: each lane loads its B1 operands
+//     (stage 1) and A2 operands (stage 2) once, 2 (B+1) NT + NT (B+2)/2 floats.
+//   * Stage 1's A operand, lane (q, c) taking S[m = c][4 s + q], is loaded straight from the
+//     workspace; the next node's is loaded while the current one runs on the matrix cores (two
+//     register sets in turn, so no register copy waits for those loads).
+//   * Stage 2's B operand is T' = (Re T, Im T) interleaved by row, 2m + c.  Stage 1 leaves lane
+//     (q, c) holding rows m = 4q .. 4q+3 of column c; stage 2 wants in lane (q, c), for K step s,
+//     row 2s + (q >> 1), part q & 1.  For s = 2r that is register q (of Re T0, Im T0, Re T1,
+//     Im T1) of lane row r, for s = 2r + 1 register q of (Re T2, Im T2, Re T3, Im T3): a 4 x 4
+//     transpose between the four 16-lane rows, done with two rounds of lane-row swaps
+//     (v_permlane32_swap exchanges rows 2-3 of one register with rows 0-1 of another,
+//     v_permlane16_swap rows 1 and 3 of one with rows 0 and 2 of another).
+// A wave takes kGridRegNodes consecutive nodes (in a particle-major order) on its own.
+constexpr int kGridRegNodes = 8;  // even: the node loop is unrolled by two
+
+// In-register 4 x 4 transpose across lane rows: x[j] of row r becomes x[r] of row j.
+__device__ __forceinline__ void transpose_rows(float (&x)[4])
+{
+    auto s02 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[0]), __float_as_uint(x[2]), false, false);
+    auto s13 = __builtin_amdgcn_permlane32_swap(__float_as_uint(x[1]), __float_as_uint(x[3]), false, false);
+    auto s01 = __builtin_amdgcn_permlane16_swap(s02[0], s13[0], false, false);
+    auto s23 = __builtin_amdgcn_permlane16_swap(s02[1], s13[1], false, false);
+    x[0] = __uint_as_float(s01[0]);
+    x[1] = __uint_as_float(s01[1]);
+    x[2] = __uint_as_float(s23[0]);
+    x[3] = __uint_as_float(s23[1]);
+}
+
+// Stage 1's A operand of node nd (clamped to the launch): S[m = col][4 s + kq], zero outside.
+template <int BB>
+__device__ __forceinline__ void load_node_s(const SoftArgs &a, int nd, int nodes, int col, int kq, float (&v)[BB + 1])
+{
+    constexpr int W = 2 * BB + 1, SWF = 2 * W;
+    const float *base = reinterpret_cast<const float *>(a.S + (int64_t)min(nd, nodes - 1) * (BB + 1) * W);
+    const float mok = col <= BB ? 1.f : 0.f;
+    const int row = min(col, BB) * SWF;
+#pragma unroll
+    for (int s = 0; s <= BB; ++s) {
+        const int K = 4 * s + kq;
+        v[s] = base[row + min(K, SWF - 1)] * (K < SWF ? mok : 0.f);
+    }
+}
+
+template <int BB, int NT>
+__device__ __forceinline__ void grid_reg_node(const SoftArgs &a, int nd, bool active, int col, int kq,
+                                              const float (&br)[NT][BB + 1], const float (&bi)[NT][BB + 1],
+                                              const float (&a2)[NT][(BB + 2) / 2], const float (&s1)[BB + 1])
+{
+    constexpr int KS1 = BB + 1, KS2 = (BB + 2) / 2;
+    if (!active) return;
+    const int N = a.n;
+    const int pl = nd / N, i = nd - (nd / N) * N;
+    if (i == 0 && threadIdx.x % kWave == 0) a.mcount[pl] = 0u;  // the maxima kernel that follows appends from 0
+    // stage 1: Re T and Im T, rows m, columns k of each column tile
+    f32x4 cr[NT], ci[NT];
+#pragma unroll
+    for (int tn = 0; tn < NT; ++tn) cr[tn] = ci[tn] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS1; ++s)
+#pragma unroll
+        for (int tn = 0; tn < NT; ++tn) {
+            cr[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(s1[s], br[tn][s], cr[tn], 0, 0, 0);
+            ci[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(s1[s], bi[tn][s], ci[tn], 0, 0, 0);
+        }
+    // T' operands of stage 2: b2[tn][s], s = 0 .. 7
+    float b2[NT][8];
+#pragma unroll
+    for (int tn = 0; tn < NT; ++tn) {
+        float x[4] = {cr[tn][0], ci[tn][0], cr[tn][1], ci[tn][1]};
+        float y[4] = {cr[tn][2], ci[tn][2], cr[tn][3], ci[tn][3]};
+        transpose_rows(x);
+        transpose_rows(y);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            b2[tn][2 * r] = x[r];
+            b2[tn][2 * r + 1] = y[r];
+        }
+    }
+    // stage 2: g[j][k] = sum_K A2[j][K] T'[K][k], straight to the workspace
+    float *out = a.grid + (int64_t)nd * N * N;
+#pragma unroll
+    for (int tj = 0; tj < NT; ++tj)
+#pragma unroll
+        for (int tk = 0; tk < NT; ++tk) {
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int s = 0; s < KS2; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a2[tj][s], b2[tk][s], acc, 0, 0, 0);
+            const int k = 16 * tk + col;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int j = 16 * tj + 4 * kq + v;
+                if (j < N && k < N) out[j * N + k] = acc[v];
+            }
+        }
+}
+
+template <int BB, int NT>
+__global__ void __launch_bounds__(256) k_soft_grid_reg(SoftArgs a)
+{
+    constexpr int KS1 = BB + 1, KS2 = (BB + 2) / 2, KP = 4 * KS1, NP = 16 * NT, A2W = 4 * KS2;
+    const int lane = threadIdx.x % kWave, col = lane % 16, kq = lane / 16;
+    const int nodes = a.np * a.n;
+    const int nd0 = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kGridRegNodes;
+    if (nd0 >= nodes) return;  // no barrier in this kernel
+    const int nd1 = min(nd0 + kGridRegNodes, nodes);
+    const float *B1r = a.dft, *B1i = a.dft + KP * NP, *A2 = a.dft + 2 * KP * NP;
+    float br[NT][KS1], bi[NT][KS1], a2[NT][KS2];
+#pragma unroll
+    for (int tn = 0; tn < NT; ++tn) {
+#pragma unroll
+        for (int s = 0; s < KS1; ++s) {
+            br[tn][s] = B1r[(4 * s + kq) * NP + 16 * tn + col];
+            bi[tn][s] = B1i[(4 * s + kq) * NP + 16 * tn + col];
+        }
+#pragma unroll
+        for (int s = 0; s < KS2; ++s) a2[tn][s] = A2[(16 * tn + col) * A2W + 4 * s + kq];
+    }
+    float s0[KS1], s1[KS1];
+    load_node_s<BB>(a, nd0, nodes, col, kq, s0);
+    for (int nd = nd0; nd < nd1; nd += 2) {
+        load_node_s<BB>(a, nd + 1, nodes, col, kq, s1);
+        grid_reg_node<BB, NT>(a, nd, true, col, kq, br, bi, a2, s0);
+        load_node_s<BB>(a, nd + 2, nodes, col, kq, s0);
+        grid_reg_node<BB, NT>(a, nd + 1, nd + 1 < nd1, col, kq, br, bi, a2, s1);
+    }
+}
+
+// The register-resident kernel serves B = 12 on grids of 33 .. 48 nodes per axis.
+inline bool soft_grid_reg_shape(int n, int B) { return B == 12 && n > 32 && n <= 48; }
+
 // ---------------------------------------------------------------- maxima and ranking
 constexpr int kSelMaxN = 96;
 
@@ -674,9 +807,11 @@ __device__ __forceinline__ void load_quads(const float *grid, int N, int NQ, int
 // and column neighbours.  The slice after next is loaded while the current one is tested; the
 // four register sets change roles from slice to slice (the slice loop is unrolled by four), so
 // no register copy waits for those loads.
-//   A node at least the largest of its six axis neighbours is a candidate.  Candidates are
-// queued in LDS (linear node index) for the whole run of slices and take the exact test in one
-// pass at the end, reading the grid in memory: memory loads are counted in issue order, so an
+//   A node at least the largest of up to 14 of its neighbours (the 6 axis ones, and the
+// k-neighbours in the rows above and below and in the previous and next slice where the quad
+// holds them, with no further loads) is a candidate: about 3 per local maximum on band-limited
+// grids, against 7 with the axis neighbours alone.  Candidates are queued in LDS (linear node index) for the whole run of
+// slices and take the exact test in one pass at the end, reading the grid in memory: memory loads are counted in issue order, so an
 // exact test between two slices would wait for the prefetched slice too.  A queue that
 // overflows (a flat grid, where every node ties with its neighbours) is ignored and every node
 // of the run takes the exact test instead.
@@ -724,10 +859,15 @@ __device__ __forceinline__ void maxima_q_slice(const MaximaQ &M, int ic, const f
             const float dd[4] = {dn.x, dn.y, dn.z, dn.w};
             const float ll[4] = {left, c.x, c.y, c.z}, rr[4] = {c.y, c.z, c.w, right};
             const float pp[4] = {pv.x, pv.y, pv.z, pv.w}, qq[4] = {nv.x, nv.y, nv.z, nv.w};
+            // the 6 axis neighbours, and the k-neighbours in the rows above and below and in the
+            // previous and next slice where the quad holds them (a true maximum passes any subset
+            // of its 26 neighbours)
             unsigned cand = 0;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const float mx = fmaxf(fmaxf(fmaxf(uu[q], dd[q]), fmaxf(ll[q], rr[q])), fmaxf(pp[q], qq[q]));
+                float mx = fmaxf(fmaxf(fmaxf(uu[q], dd[q]), fmaxf(ll[q], rr[q])), fmaxf(pp[q], qq[q]));
+                if (q > 0) mx = fmaxf(mx, fmaxf(fmaxf(uu[q - 1], dd[q - 1]), fmaxf(pp[q - 1], qq[q - 1])));
+                if (q < 3) mx = fmaxf(mx, fmaxf(fmaxf(uu[q + 1], dd[q + 1]), fmaxf(pp[q + 1], qq[q + 1])));
                 cand |= (vv[q] >= mx ? 1u : 0u) << q;
             }
             if (cand) {
@@ -882,6 +1022,12 @@ hipError_t launch_soft_wigner(const SoftArgs &a, int P, hipStream_t s)
 hipError_t launch_soft_grid(const SoftArgs &a0, int P, hipStream_t s)
 {
     SoftArgs a = a0;
+    a.np = P;
+    if (soft_grid_reg_shape(a.n, a.B)) {
+        const int waves = (P * a.n + kGridRegNodes - 1) / kGridRegNodes;
+        hipLaunchKernelGGL((k_soft_grid_reg<12, 3>), dim3((waves + 3) / 4), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     const GridShape sh = soft_grid_shape(a.n, a.B);
     a.gslices = sh.waves;
     const int SB = a.gslices * kGridSPW;

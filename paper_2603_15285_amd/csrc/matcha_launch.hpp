@@ -41,6 +41,7 @@ struct SoftArgs {
     int B, n, Kc;
     int gslices;              // waves per workgroup of the grid kernel (set by its launcher)
     int p0;                   // first particle of this launch
+    int np;                   // particles in this launch (set by the grid launcher)
     float *grid;              // [launch particles][n][n][n] workspace: C_B on the grid
     float2 *S;                // [launch particles][n][(B+1)(2B+1)] workspace: Wigner transforms
     unsigned long long *mlist;  // [launch particles][mcap] keys of the local maxima (workspace)

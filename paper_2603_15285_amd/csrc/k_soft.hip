@@ -319,8 +319,11 @@ __global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
 // ---------------------------------------------------------------- grid synthesis in registers
 //
 // The same two products for small bands, with no LDS: every operand lives in registers.
-//   * The DFT tables are the same for every node and particle: each lane loads its B1 operands
-//     (stage 1) and A2 operands (stage 2) once, 2 (B+1) NT + NT (B+2)/2 floats.
+//   * The DFT tables are the same for every node and particle: each lane loads its B1r operands
+//     (stage 1) and A2 operands (stage 2) once, (B+1) NT + NT (B+2)/2 floats.  B1i's rows are
+//     B1r's rows swapped in pairs (2n' <-> 2n'+1, the even ones negated), and the rows of a pair
+//     sit in lane rows q and q^1, so each B1i operand is formed just before its use with one
+//     v_permlane16_swap (exchanging lane rows 0 <-> 1 and 2 <-> 3) and a sign.
 //   * Stage 1's A operand, lane (q, c) taking S[m = c][4 s + q], is loaded straight from the
 //     workspace; the next node's is loaded while the current one runs on the matrix cores (two
 //     register sets in turn, so no register copy waits for those loads).
@@ -332,7 +335,7 @@ __global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
 //     (v_permlane32_swap exchanges rows 2-3 of one register with rows 0-1 of another,
 //     v_permlane16_swap rows 1 and 3 of one with rows 0 and 2 of another).
 // A wave takes kGridRegNodes consecutive nodes (in a particle-major order) on its own.
-constexpr int kGridRegNodes = 8;  // even: the node loop is unrolled by two
+constexpr int kGridRegNodes = 16;  // even: the node loop is unrolled by two
 
 // In-register 4 x 4 transpose across lane rows: x[j] of row r becomes x[r] of row j.
 __device__ __forceinline__ void transpose_rows(float (&x)[4])
@@ -364,7 +367,7 @@ __device__ __forceinline__ void load_node_s(const SoftArgs &a, int nd, int nodes
 
 template <int BB, int NT>
 __device__ __forceinline__ void grid_reg_node(const SoftArgs &a, int nd, bool active, int col, int kq,
-                                              const float (&br)[NT][BB + 1], const float (&bi)[NT][BB + 1],
+                                              const float (&br)[NT][BB + 1],
                                               const float (&a2)[NT][(BB + 2) / 2], const float (&s1)[BB + 1])
 {
     constexpr int KS1 = BB + 1, KS2 = (BB + 2) / 2;
@@ -381,7 +384,10 @@ __device__ __forceinline__ void grid_reg_node(const SoftArgs &a, int nd, bool ac
 #pragma unroll
         for (int tn = 0; tn < NT; ++tn) {
             cr[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(s1[s], br[tn][s], cr[tn], 0, 0, 0);
-            ci[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(s1[s], bi[tn][s], ci[tn], 0, 0, 0);
+            // B1i[2n'][k] = -B1r[2n'+1][k], B1i[2n'+1][k] = B1r[2n'][k]: lane row q takes row q^1
+            const auto sw = __builtin_amdgcn_permlane16_swap(__float_as_uint(br[tn][s]), __float_as_uint(br[tn][s]), false, false);
+            const float bis = (kq & 1) ? __uint_as_float(sw[0]) : -__uint_as_float(sw[1]);
+            ci[tn] = __builtin_amdgcn_mfma_f32_16x16x4f32(s1[s], bis, ci[tn], 0, 0, 0);
         }
     // T' operands of stage 2: b2[tn][s], s = 0 .. 7
     float b2[NT][8];
@@ -424,14 +430,13 @@ __global__ void __launch_bounds__(256) k_soft_grid_reg(SoftArgs a)
     const int nd0 = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kGridRegNodes;
     if (nd0 >= nodes) return;  // no barrier in this kernel
     const int nd1 = min(nd0 + kGridRegNodes, nodes);
-    const float *B1r = a.dft, *B1i = a.dft + KP * NP, *A2 = a.dft + 2 * KP * NP;
-    float br[NT][KS1], bi[NT][KS1], a2[NT][KS2];
+    const float *B1r = a.dft, *A2 = a.dft + 2 * KP * NP;
+    float br[NT][KS1], a2[NT][KS2];
 #pragma unroll
     for (int tn = 0; tn < NT; ++tn) {
 #pragma unroll
         for (int s = 0; s < KS1; ++s) {
             br[tn][s] = B1r[(4 * s + kq) * NP + 16 * tn + col];
-            bi[tn][s] = B1i[(4 * s + kq) * NP + 16 * tn + col];
         }
 #pragma unroll
         for (int s = 0; s < KS2; ++s) a2[tn][s] = A2[(16 * tn + col) * A2W + 4 * s + kq];
@@ -440,9 +445,9 @@ __global__ void __launch_bounds__(256) k_soft_grid_reg(SoftArgs a)
     load_node_s<BB>(a, nd0, nodes, col, kq, s0);
     for (int nd = nd0; nd < nd1; nd += 2) {
         load_node_s<BB>(a, nd + 1, nodes, col, kq, s1);
-        grid_reg_node<BB, NT>(a, nd, true, col, kq, br, bi, a2, s0);
+        grid_reg_node<BB, NT>(a, nd, true, col, kq, br, a2, s0);
         load_node_s<BB>(a, nd + 2, nodes, col, kq, s0);
-        grid_reg_node<BB, NT>(a, nd + 1, nd + 1 < nd1, col, kq, br, bi, a2, s1);
+        grid_reg_node<BB, NT>(a, nd + 1, nd + 1 < nd1, col, kq, br, a2, s1);
     }
 }
 

@@ -1,6 +1,7 @@
 // k_soft.hip -- low-bandwidth SOFFT search (Sec. 2.3; Alg. 1, its first two steps).
 //
-// Two kernels per batch of particles, with the grid in an HBM workspace between them.
+// Four kernels per chunk of particles, with the node transforms, the grid and the maxima lists in
+// an HBM workspace between them.
 //
 // k_soft_wigner forms, for every polar node b_i = pi (2i+1) / (2n) of a particle, the Wigner-d
 // transform over l of the coefficients,
@@ -8,13 +9,14 @@
 // one workgroup per particle with its coefficients staged in LDS, one step of the sum serving a
 // pair and its partner; the d values at the nodes come from a table shared by all particles.
 //
-// k_soft_grid synthesises C_B on the n^3 grid (a_j = 2 pi j / n, c_k = 2 pi k / n) with the 2-D
-// inverse DFT over (a, c), each wave taking a few polar nodes of one particle: first
+// k_soft_grid_reg (small bands, operands in registers) or k_soft_grid (any band, operands in LDS)
+// synthesises C_B on the n^3 grid (a_j = 2 pi j / n, c_k = 2 pi k / n) with the 2-D inverse DFT
+// over (a, c), each wave taking a few polar nodes of one particle: first
 // T[m][k] = sum_n S[m, n] e^{i n c_k}, then g[j][k] = 2 Re sum_m T[m][k] e^{i m a_j}.
 //
 // k_soft_maxima_q (n a multiple of 4; k_soft_maxima otherwise) takes a particle and a run of
 // consecutive polar nodes per workgroup and tests every node for a local maximum against its 26
-// neighbours (six axis neighbours first, then the exact test); each maximum's 64-bit key
+// neighbours (a subset of the neighbours first, then the exact test); each maximum's 64-bit key
 // (ordered value, inverted linear index) is appended to the particle's list in the workspace.
 //
 // k_soft_rank takes one particle per workgroup, sorts its list and writes the Kc best keys, so
@@ -38,7 +40,8 @@ namespace matcha {
 //   stage 1  T = S B1:  A = S with (Re, Im) interleaved along K = 2(n+B) + c, B1r / B1i the
 //            twiddles of e^{i n c_k} in the matching real form, giving Re T and Im T;
 //   stage 2  g = A2 T':  A2[j][2m + c] = 2 cos(m a_j) / -2 sin(m a_j), T'[2m + c][k] = Re / Im T.
-// S and T' live in the wave's own LDS; B1 and A2 are host-built tables read through the caches.
+// In k_soft_grid, S and T' live in the wave's own LDS; B1 and A2 are host-built tables, in the
+// workgroup's LDS or read through the caches.
 constexpr int kGridSPW = 3;  // polar nodes per wave
 
 struct GridGeom {
@@ -194,7 +197,6 @@ __global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
     const int SB = WB * kGridSPW;
     const int NG = (N + SB - 1) / SB;
     const int pl = blockIdx.x / NG, ib = (blockIdx.x - pl * NG) * SB;
-    const int p = a.p0 + pl;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int col = lane % 16, kq = lane / 16;
     const float *tabs = a.dft;
@@ -212,7 +214,6 @@ __global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
     const float *B1r = tabs, *B1i = B1r + g.KP * g.NP, *A2 = B1i + g.KP * g.NP;
     const int A2W = 4 * g.KS2;
     if (ib == 0 && threadIdx.x == 0) a.mcount[pl] = 0u;  // the maxima kernel that follows appends from 0
-    (void)p;
     const int KS1 = g.KP / 4, NT = g.NP / 16;
     // the padding rows and columns of S stay zero; each node overwrites the rest
     for (int t = lane; t < 16 * g.MT * g.KP; t += kWave) Sf[t] = 0.f;
@@ -424,6 +425,7 @@ __device__ __forceinline__ void grid_reg_node(const SoftArgs &a, int nd, bool ac
 template <int BB, int NT>
 __global__ void __launch_bounds__(256) k_soft_grid_reg(SoftArgs a)
 {
+    static_assert(BB + 1 <= 16 && (BB + 2) / 2 <= 8, "one 16-row tile of m, at most 8 stage-2 K steps");
     constexpr int KS1 = BB + 1, KS2 = (BB + 2) / 2, KP = 4 * KS1, NP = 16 * NT, A2W = 4 * KS2;
     const int lane = threadIdx.x % kWave, col = lane % 16, kq = lane / 16;
     const int nodes = a.np * a.n;
@@ -451,8 +453,10 @@ __global__ void __launch_bounds__(256) k_soft_grid_reg(SoftArgs a)
     }
 }
 
-// The register-resident kernel serves B = 12 on grids of 33 .. 48 nodes per axis.
-inline bool soft_grid_reg_shape(int n, int B) { return B == 12 && n > 32 && n <= 48; }
+// The register-resident kernel needs the B+1 rows of m in one 16-row tile and stage 2's K steps
+// within the 8 that the transpose forms (B <= 14); it is built for B = 12 on grids of 33 .. 48
+// nodes per axis and B = 8 on grids of 17 .. 32.
+inline bool soft_grid_reg_shape(int n, int B) { return (B == 12 && n > 32 && n <= 48) || (B == 8 && n > 16 && n <= 32); }
 
 // ---------------------------------------------------------------- maxima and ranking
 constexpr int kSelMaxN = 96;
@@ -1030,7 +1034,10 @@ hipError_t launch_soft_grid(const SoftArgs &a0, int P, hipStream_t s)
     a.np = P;
     if (soft_grid_reg_shape(a.n, a.B)) {
         const int waves = (P * a.n + kGridRegNodes - 1) / kGridRegNodes;
-        hipLaunchKernelGGL((k_soft_grid_reg<12, 3>), dim3((waves + 3) / 4), dim3(256), 0, s, a);
+        if (a.B == 12)
+            hipLaunchKernelGGL((k_soft_grid_reg<12, 3>), dim3((waves + 3) / 4), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_soft_grid_reg<8, 2>), dim3((waves + 3) / 4), dim3(256), 0, s, a);
         return hipGetLastError();
     }
     const GridShape sh = soft_grid_shape(a.n, a.B);

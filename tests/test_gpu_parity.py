@@ -143,6 +143,19 @@ def test_soft_search_matches_oracle(M, ctx, name):
         check_soft(b, p, cand[p], int(status[p]), wl.B, wl.n_grid, wl.Kc)
 
 
+@pytest.mark.parametrize("L,B,n,Kc", [(16, 12, 40, 16), (12, 8, 24, 8)])
+def test_soft_search_partial_tiles(M, ctx, L, B, n, Kc):
+    """Grid sizes that leave the last 16-wide column tile of the register-resident grid kernel
+    partly empty."""
+    b = S.make_batch(L, 8, 2, seed=40 + n, snr=0.1)
+    batch, f, h, w = upload(M, b)
+    C = M.coeff_assemble(ctx, batch, f, h, w)
+    cand, status = M.soft_search(ctx, batch, C, B, n, Kc)
+    cand, status = cand.cpu().numpy(), status.cpu().numpy()
+    for p in range(2):
+        check_soft(b, p, cand[p], int(status[p]), B, n, Kc)
+
+
 def test_soft_search_few_maxima(M, ctx):
     b = S.make_batch(4, 3, 2, seed=5, snr=1.0)
     batch, f, h, w = upload(M, b)

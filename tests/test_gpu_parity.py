@@ -84,8 +84,12 @@ def test_evaluate_matches_oracle(M, ctx, L, R):
 
 
 # ---------------------------------------------------------------- assembly
-def test_assembly_matches_oracle(M, ctx):
-    b = S.make_batch(32, 32, 3, seed=11, snr=0.1, L_per=[32, 20, 7], R_per=[32, 11, 3])
+@pytest.mark.parametrize("Lh,Rh,L_per,R_per", [(32, 32, [32, 20, 7], [32, 11, 3]),
+                                              (40, 48, [40, 33, 9], [48, 37, 2])])
+def test_assembly_matches_oracle(M, ctx, Lh, Rh, L_per, R_per):
+    """Up to 32 shells the kernel holds a row's 16 K steps in registers; 33 .. 64 shells take the
+    32-step instance (second case)."""
+    b = S.make_batch(Lh, Rh, 3, seed=11, snr=0.1, L_per=L_per, R_per=R_per)
     batch, f, h, w = upload(M, b)
     C = M.coeff_assemble(ctx, batch, f, h, w).cpu().numpy().view(np.complex64)
     for p in range(3):
@@ -379,10 +383,13 @@ def to_bf16(M, x_complex):
     return t.to(torch.bfloat16).cuda()
 
 
-def test_assembly_bf16_matches_rounded_oracle(M, ctx):
+@pytest.mark.parametrize("Lh,Rh,L_per,R_per", [(32, 32, [32, 17, 5], [32, 9, 3]),
+                                              (40, 48, [40, 29, 6], [48, 41, 1])])
+def test_assembly_bf16_matches_rounded_oracle(M, ctx, Lh, Rh, L_per, R_per):
     """BF16 inputs on the matrix cores: against the oracle on the same BF16-rounded inputs; the
-    kernel rounds w_r h once more to BF16, so each product may differ by 2^-8 relative."""
-    b = S.make_batch(32, 32, 3, seed=21, snr=0.1, L_per=[32, 17, 5], R_per=[32, 9, 3])
+    kernel rounds w_r h once more to BF16, so each product may differ by 2^-8 relative (bound
+    2^-7 in the test).  The second case has three 32-wide K steps (48 shells)."""
+    b = S.make_batch(Lh, Rh, 3, seed=21, snr=0.1, L_per=L_per, R_per=R_per)
     batch, _, _, w = upload(M, b)
     parts = [b.f(p).reshape(-1) for p in range(3)]
     f16 = to_bf16(M, np.concatenate(parts))

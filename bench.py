@@ -305,7 +305,8 @@ def main():
                      "hbm_GBps": a_b / (ms_asm / 1e3) / 1e9, "hbm_frac": a_b / (ms_asm / 1e3) / 1e9 / HBM_PEAK_GBPS,
                      "mfma_TFLOPs": a_f / (ms_asm / 1e3) / 1e12,
                      "mfma_frac": a_f / (ms_asm / 1e3) / 1e12 / MFMA_FP32_PEAK_TFLOPS},
-        "soft_search": {"kernels": "k_soft_wigner + k_soft_grid_reg (or k_soft_grid) + k_soft_maxima_q (or k_soft_maxima) + k_soft_rank", "ms": ms_soft,
+        "soft_search": {"kernels": ("k_soft_wigner + k_soft_grid_reg (or k_soft_grid) + k_soft_maxima_q "
+                                    "(or k_soft_maxima) + k_soft_rank"), "ms": ms_soft,
                         "hbm_GBps": s_b / (ms_soft / 1e3) / 1e9,
                         "hbm_frac": s_b / (ms_soft / 1e3) / 1e9 / HBM_PEAK_GBPS,
                         "mfma_TFLOPs": s_f / (ms_soft / 1e3) / 1e12,

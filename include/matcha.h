@@ -19,9 +19,10 @@
  *
  * Memory.  Every pointer is a device pointer unless its comment says (host).
  * The caller allocates every input, output and workspace buffer; the library
- * keeps no pointer after the enqueued work completes.  A context owns only
- * read-only tables (recurrence coefficients, SOFFT node data) that it builds on
- * the first call that needs them or in matcha_prepare().  Every call validates its
+ * keeps no pointer after the enqueued work completes.  A context owns read-only
+ * tables (recurrence coefficients, SOFFT node data) that it builds on the first call
+ * that needs them or in matcha_prepare(), and the SOFFT workspace of its eager
+ * matcha_soft_search calls (see there).  Every call validates its
  * arguments synchronously on the host and then enqueues its kernels on `stream`
  * (a hipStream_t passed as void*); nothing waits on the device.  A context is not
  * thread-safe.
@@ -128,7 +129,8 @@ typedef struct {
 
 /* Launch shapes.  Zero fields mean "library default".  march_nc: candidates per wavefront
  * of the march kernel (1, 2, 4 or 8; a workgroup holds ceil(Kc / march_nc) <= 8 waves).
- * soft_threads: threads per SOFFT workgroup (256 or 512). */
+ * soft_threads: threads per workgroup of the SOFFT ranking kernel (256 or 512; each
+ * particle's maxima list holds twice as many keys). */
 typedef struct {
     int32_t march_nc;
     int32_t soft_threads;
@@ -182,8 +184,10 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
  * filled with the best remaining nodes and MATCHA_ST_FEW_MAXIMA is set.
  * status [P] is overwritten.  Requires 1 <= B <= min_p L_p, B <= 32, 4 <= n_grid <= 96,
  * 1 <= Kc <= MATCHA_MAX_KC (MATCHA_ERR_UNSUPPORTED if the shape does not fit a workgroup's LDS).
- * The grid passes through a workspace owned by the context (n_grid^3 floats per particle,
- * at most 4 GiB; larger batches run in chunks of particles), allocated on first need and
+ * The node transforms, the grid and the maxima lists pass through a workspace owned by the
+ * context (n_grid^3 floats of grid, n_grid (B+1)(2B+1) complex values and a key list per
+ * particle: 575 KB at B = 12, n_grid = 48; at most 4 GiB, larger batches run in chunks of
+ * particles), allocated on first need and
  * grown synchronously; calls on one context must not overlap in time (use one stream per
  * context).  matcha_align_graph_create gives each graph a workspace of its own. */
 matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, const float *C,

@@ -19,16 +19,13 @@
 namespace matcha {
 
 
-// Phase tables and reduction scratch share one LDS region per wave.
+// Phase tables of the wave's candidates.
 template <int NC>
 struct __align__(16) WaveScratch {
-    union {
-        struct {
-            float2 ea[NC][kMaxL + 1];      // e^{i k a_c}, k = 0 .. L
-            float2 eg[NC][2 * kMaxL + 1];  // e^{i k c_c} at kMaxL + k, k = -L .. L
-        } ph;
-        float red[10 * NC][16];
-    };
+    struct {
+        float2 ea[NC][kMaxL + 1];      // e^{i k a_c}, k = 0 .. L
+        float2 eg[NC][2 * kMaxL + 1];  // e^{i k c_c} at kMaxL + k, k = -L .. L
+    } ph;
 };
 
 template <int NC>
@@ -41,19 +38,23 @@ struct WaveState {
     float fprev[NC];
 };
 
-// Inlined into its callers so that ea / eg are addressed as LDS, never through generic pointers.
-__device__ __forceinline__ void fill_phases(double a, double c, int L, float2 *ea, float2 *eg, int lane)
+// e^{i k a_c} and e^{i k c_c} of the wave's NC candidates, k = 0 .. L, one (candidate, k) per
+// lane.  Inlined into its callers so that the tables are addressed as LDS, never through generic
+// pointers.
+template <int NC>
+__device__ __forceinline__ void fill_phases(const WaveState<NC> &st, WaveScratch<NC> &ws, int L, int lane)
 {
-    for (int k = lane; k <= L; k += kWave) {
+    for (int i = lane; i < NC * (L + 1); i += kWave) {
+        const int c = i / (L + 1), k = i - c * (L + 1);
         // k a reduced to [-pi, pi] in FP64 (exact enough for |k a| < 1e6), then sin / cos in FP32
-        const double xa = (double)k * a, xc = (double)k * c;
+        const double xa = (double)k * st.th[c][0], xc = (double)k * st.th[c][2];
         const double ta = fma(-kTwoPi, rint(xa * (1.0 / kTwoPi)), xa), tc = fma(-kTwoPi, rint(xc * (1.0 / kTwoPi)), xc);
         float sa, ca, sc, cc;
         sincosf((float)ta, &sa, &ca);
         sincosf((float)tc, &sc, &cc);
-        ea[k] = make_float2(ca, sa);
-        eg[kMaxL + k] = make_float2(cc, sc);
-        eg[kMaxL - k] = make_float2(cc, -sc);
+        ws.ph.ea[c][k] = make_float2(ca, sa);
+        ws.ph.eg[c][kMaxL + k] = make_float2(cc, sc);
+        ws.ph.eg[c][kMaxL - k] = make_float2(cc, -sc);
     }
 }
 
@@ -64,8 +65,11 @@ __device__ __forceinline__ void fill_phases(double a, double c, int L, float2 *e
 // sum_l C^l PW_l D^l for the pair (0, 1) and C^l PWT_l D^l for the partner (2, 3), then the same
 // for D' (4..7) and D''/2 (8..11).  With u = A cos b - AC, v = A sin b, h = A cos b / 2:
 //   D'^l = u D'^{l-1} - v D^{l-1} - D'^{l-2},  (D''/2)^l = u (D''/2)^{l-1} - v D'^{l-1} - h D^{l-1} - (D''/2)^{l-2}.
-template <int NC, bool DERIV, typename T>
-__device__ __forceinline__ void row_step(const T A, const T AC, const float4 tb, const float4 cc, const T *cbv,
+// SEED: rows where pairs of the tile start; lanes with seed set take the edge values (S0, S1, S2)
+// instead.  Lanes whose pair starts later hold a zero state, which the step keeps at zero.
+template <int NC, bool DERIV, bool SEED, typename T>
+__device__ __forceinline__ void row_step(const T A, const T AC, const float4 tb, const float4 cc, const bool seed,
+                                         const T (&S0)[NC], const T (&S1)[NC], const T (&S2)[NC], const T *cbv,
                                          const T *sbv, const T *chv, T (&X)[NC], T (&Y)[NC], T (&X1)[NC],
                                          T (&Y1)[NC], T (&X2)[NC], T (&Y2)[NC], T (&U)[NC][DERIV ? 12 : 4])
 {
@@ -73,7 +77,8 @@ __device__ __forceinline__ void row_step(const T A, const T AC, const float4 tb,
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const T u = fma(A, cbv[c], -AC);
-        const T dn = fma(u, X[c], -Y[c]);
+        T dn = fma(u, X[c], -Y[c]);
+        if (SEED) dn = seed ? S0[c] : dn;
         U[c][0] = fma(s0r, dn, U[c][0]);
         U[c][1] = fma(s0i, dn, U[c][1]);
         U[c][2] = fma(s1r, dn, U[c][2]);
@@ -81,8 +86,12 @@ __device__ __forceinline__ void row_step(const T A, const T AC, const float4 tb,
         if (DERIV) {
             const T v = A * sbv[c];
             const T h = A * chv[c];
-            const T d1n = fma(u, X1[c], fma(-v, X[c], -Y1[c]));
-            const T d2n = fma(u, X2[c], fma(-v, X1[c], fma(-h, X[c], -Y2[c])));
+            T d1n = fma(u, X1[c], fma(-v, X[c], -Y1[c]));
+            T d2n = fma(u, X2[c], fma(-v, X1[c], fma(-h, X[c], -Y2[c])));
+            if (SEED) {
+                d1n = seed ? S1[c] : d1n;
+                d2n = seed ? S2[c] : d2n;
+            }
             Y1[c] = d1n;
             Y2[c] = d2n;
             U[c][4] = fma(s0r, d1n, U[c][4]);
@@ -178,17 +187,35 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
     }
     const int npairs = (L + 1) * (L + 1);
     const int ntiles = (npairs + kWave - 1) / kWave;
+    const int rowL = (int)wedge_row(L);
+    // each tile loads the next tile's pairs while it runs
+    PairInfo pn = pinfo[min(lane, npairs - 1)];
     for (int t = 0; t < ntiles; ++t) {
         const int q0 = t * kWave;
         const int q = q0 + lane;
         const bool valid = q < npairs;
-        const int qe = valid ? q : npairs - 1;
-        const uint32_t lb = (uint32_t)qe * 16u;
-        const PairInfo pi = pinfo[qe];
+        const uint32_t lb = (uint32_t)(valid ? q : npairs - 1) * 16u;
+        const PairInfo pi = pn;
+        pn = pinfo[min(q + kWave, npairs - 1)];
         const int m = pi.m, n = pi.n;
         // lane 0 holds the tile's smallest m, the last valid lane its largest
         const int mlo = __builtin_amdgcn_readfirstlane(m);
-        const int mhi = __builtin_amdgcn_readfirstlane(__shfl(m, min(npairs - 1 - q0, kWave - 1)));
+        const int mhi = __builtin_amdgcn_readlane(m, min(npairs - 1 - q0, kWave - 1));
+
+        // Rows mlo .. L, two per trip: the state ping-pongs between (D, Dm), and the loads of the
+        // next two rows are in flight meanwhile.  Every lane loads at its own pair's offset in
+        // every row, also before its pair starts (the offset then falls in a later row of the
+        // same array) and past row L (row L is re-read, never used), so no load needs a branch.
+        int l = mlo;
+        int row = (int)wedge_row(mlo);
+        float4 tb0 = ld_row(tab, row, lb), cc0 = ld_row(Cp, row, lb);
+        T A0, AC0, A1, AC1;
+        Coef<T>::get(tb0, tab64, row, lb, A0, AC0);
+        row += (l + 1) * (l + 1);
+        int r1 = min(row, rowL);
+        float4 tb1 = ld_row(tab, r1, lb), cc1 = ld_row(Cp, r1, lb);
+        Coef<T>::get(tb1, tab64, r1, lb, A1, AC1);
+        row += (l + 2) * (l + 2);
 
         // edge values of every lane's pair, computed once per tile without divergence
         T sd0[NC], sd1[NC], sd2[NC];
@@ -197,116 +224,60 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
             seed_T<T>(m, n, pi.lbh2, bc[c0 + c], sd0[c], sd1[c], sd2[c]);
             sd2[c] *= (T)0.5;
         }
-
-        // first row l = mlo: only lanes with m == mlo start; everything else is zero
         T D[NC], Dm[NC], D1[NC], D1m[NC], D2[NC], D2m[NC];
         T U[NC][NU];
-        int row = (int)wedge_row(mlo);
-        {
-            const bool act = valid && m == mlo;
-            float4 tb = make_float4(0.f, 0.f, 0.f, 0.f), cc = tb;
-            if (act) {
-                tb = tab[row + q];
-                cc = Cp[row + q];
-            }
-            row += (mlo + 1) * (mlo + 1);
-            const T s0r = (T)(cc.x * tb.z), s0i = (T)(cc.y * tb.z), s1r = (T)(cc.z * tb.w), s1i = (T)(cc.w * tb.w);
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                D[c] = act ? sd0[c] : (T)0;
-                D1[c] = act ? sd1[c] : (T)0;
-                D2[c] = act ? sd2[c] : (T)0;
-                Dm[c] = D1m[c] = D2m[c] = (T)0;
-                U[c][0] = s0r * D[c];
-                U[c][1] = s0i * D[c];
-                U[c][2] = s1r * D[c];
-                U[c][3] = s1i * D[c];
-                if (DERIV) {
-                    U[c][4] = s0r * D1[c];
-                    U[c][5] = s0i * D1[c];
-                    U[c][6] = s1r * D1[c];
-                    U[c][7] = s1i * D1[c];
-                    U[c][8] = s0r * D2[c];
-                    U[c][9] = s0i * D2[c];
-                    U[c][10] = s1r * D2[c];
-                    U[c][11] = s1i * D2[c];
-                }
-            }
-        }
-        // rows where some lanes of the tile are still before their edge l = m
-        for (int l = mlo + 1; l <= mhi; ++l) {
-            const bool act = valid && m <= l;
-            float4 tb = make_float4(0.f, 0.f, 0.f, 0.f), cc = tb;
-            T A = (T)0, AC = (T)0;
-            if (act) {
-                tb = tab[row + q];
-                cc = Cp[row + q];
-                Coef<T>::get(tb, tab64, row, (uint32_t)q * 16u, A, AC);
-            }
-            row += (l + 1) * (l + 1);
-            const T s0r = (T)(cc.x * tb.z), s0i = (T)(cc.y * tb.z), s1r = (T)(cc.z * tb.w), s1i = (T)(cc.w * tb.w);
-            const bool seed = (m == l);
+        for (int c = 0; c < NC; ++c) {
+            D[c] = Dm[c] = D1[c] = D1m[c] = D2[c] = D2m[c] = (T)0;
 #pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const T u = fma(A, cbv[c], -AC);
-                const T dn = seed ? sd0[c] : fma(u, D[c], -Dm[c]);
-                U[c][0] = fma(s0r, dn, U[c][0]);
-                U[c][1] = fma(s0i, dn, U[c][1]);
-                U[c][2] = fma(s1r, dn, U[c][2]);
-                U[c][3] = fma(s1i, dn, U[c][3]);
-                if (DERIV) {
-                    const T v = A * sbv[c];
-                    const T h = A * chv[c];
-                    const T d1n = seed ? sd1[c] : fma(u, D1[c], fma(-v, D[c], -D1m[c]));
-                    const T d2n = seed ? sd2[c] : fma(u, D2[c], fma(-v, D1[c], fma(-h, D[c], -D2m[c])));
-                    D1m[c] = D1[c];
-                    D1[c] = d1n;
-                    D2m[c] = D2[c];
-                    D2[c] = d2n;
-                    U[c][4] = fma(s0r, d1n, U[c][4]);
-                    U[c][5] = fma(s0i, d1n, U[c][5]);
-                    U[c][6] = fma(s1r, d1n, U[c][6]);
-                    U[c][7] = fma(s1i, d1n, U[c][7]);
-                    U[c][8] = fma(s0r, d2n, U[c][8]);
-                    U[c][9] = fma(s0i, d2n, U[c][9]);
-                    U[c][10] = fma(s1r, d2n, U[c][10]);
-                    U[c][11] = fma(s1i, d2n, U[c][11]);
-                }
-                Dm[c] = D[c];
-                D[c] = dn;
-            }
+            for (int v = 0; v < NU; ++v) U[c][v] = (T)0;
         }
-        // rows where every lane of the tile is past its edge: two rows per trip, the state
-        // ping-pongs between (D, Dm) and the next rows' loads are in flight meanwhile.  Loads
-        // past row L re-read row L (never used), so they need no branch.
-        {
-            const int rowL = (int)wedge_row(L);
-            int l = mhi + 1;
-            int r0 = min(row, rowL);
-            float4 tb0 = ld_row(tab, r0, lb), cc0 = ld_row(Cp, r0, lb);
-            T A0, AC0, A1, AC1;
-            Coef<T>::get(tb0, tab64, r0, lb, A0, AC0);
-            row += (l + 1) * (l + 1);
-            int r1 = min(row, rowL);
-            float4 tb1 = ld_row(tab, r1, lb), cc1 = ld_row(Cp, r1, lb);
-            Coef<T>::get(tb1, tab64, r1, lb, A1, AC1);
-            row += (l + 2) * (l + 2);
-            for (; l + 1 <= L; l += 2) {
-                row_step<NC, DERIV, T>(A0, AC0, tb0, cc0, cbv, sbv, chv, D, Dm, D1, D1m, D2, D2m, U);
-                r0 = min(row, rowL);
-                tb0 = ld_row(tab, r0, lb);
-                cc0 = ld_row(Cp, r0, lb);
-                Coef<T>::get(tb0, tab64, r0, lb, A0, AC0);
-                row += (l + 3) * (l + 3);
-                row_step<NC, DERIV, T>(A1, AC1, tb1, cc1, cbv, sbv, chv, Dm, D, D1m, D1, D2m, D2, U);
-                r1 = min(row, rowL);
-                tb1 = ld_row(tab, r1, lb);
-                cc1 = ld_row(Cp, r1, lb);
-                Coef<T>::get(tb1, tab64, r1, lb, A1, AC1);
-                row += (l + 4) * (l + 4);
-            }
-            if (l <= L) row_step<NC, DERIV, T>(A0, AC0, tb0, cc0, cbv, sbv, chv, D, Dm, D1, D1m, D2, D2m, U);
+#define MARCH_ROW0(SEEDROW)                                                                              \
+    row_step<NC, DERIV, SEEDROW, T>(A0, AC0, tb0, cc0, m == l, sd0, sd1, sd2, cbv, sbv, chv, D, Dm, D1, D1m, D2, \
+                                    D2m, U)
+#define MARCH_ROW1(SEEDROW)                                                                                  \
+    row_step<NC, DERIV, SEEDROW, T>(A1, AC1, tb1, cc1, m == l + 1, sd0, sd1, sd2, cbv, sbv, chv, Dm, D, D1m, D1, \
+                                    D2m, D2, U)
+#define MARCH_LOAD0()                                                                                    \
+    do {                                                                                                 \
+        __builtin_amdgcn_sched_barrier(0);                                                               \
+        const int r0 = min(row, rowL);                                                                   \
+        tb0 = ld_row(tab, r0, lb);                                                                       \
+        cc0 = ld_row(Cp, r0, lb);                                                                        \
+        Coef<T>::get(tb0, tab64, r0, lb, A0, AC0);                                                       \
+        row += (l + 3) * (l + 3);                                                                        \
+        __builtin_amdgcn_sched_barrier(0);                                                               \
+    } while (0)
+#define MARCH_LOAD1()                                                                                    \
+    do {                                                                                                 \
+        __builtin_amdgcn_sched_barrier(0);                                                               \
+        r1 = min(row, rowL);                                                                             \
+        tb1 = ld_row(tab, r1, lb);                                                                       \
+        cc1 = ld_row(Cp, r1, lb);                                                                        \
+        Coef<T>::get(tb1, tab64, r1, lb, A1, AC1);                                                       \
+        row += (l + 4) * (l + 4);                                                                        \
+        __builtin_amdgcn_sched_barrier(0);                                                               \
+    } while (0)
+        // rows where pairs of the tile start (mlo .. mhi, rounded up to an even count, at most L)
+        const int lseed = min(mhi + ((mhi - mlo) & 1 ? 0 : 1), L);
+        for (; l <= lseed; l += 2) {
+            MARCH_ROW0(true);
+            MARCH_LOAD0();
+            if (l < L) MARCH_ROW1(true);
+            MARCH_LOAD1();
         }
+        // rows where every pair of the tile has started
+        for (; l + 1 <= L; l += 2) {
+            MARCH_ROW0(false);
+            MARCH_LOAD0();
+            MARCH_ROW1(false);
+            MARCH_LOAD1();
+        }
+        if (l <= L) MARCH_ROW0(false);
+#undef MARCH_ROW0
+#undef MARCH_ROW1
+#undef MARCH_LOAD0
+#undef MARCH_LOAD1
         if (!valid) continue;
         // phases and the m, n weights of the a / c derivatives
         const int an = n >= 0 ? n : -n, b2i = n >= 0 ? m : -m;
@@ -364,27 +335,49 @@ __device__ void eval_level_any(const float4 *Cp, const float4 *tab, const double
     }
 }
 
-// Lane-sums of the wave's NC x NV accumulators: two xor-shuffle stages fold the 64 lanes
-// onto 16, the 16 partial sums go through LDS, and lane v < NC*NV ends with total v in
-// st.tot.
-template <int NC, int NV>
-__device__ void wave_reduce(float (&acc)[NC][10], WaveScratch<NC> &ws, WaveState<NC> &st, int lane)
+// Sum of v over the 16 lanes of each lane row (DPP row mirror, half mirror and two quad
+// permutations); every lane of a row ends with its row's sum.
+__device__ __forceinline__ float row_sum16(float v)
 {
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xf, 0xf, false));  // lane i <-> 15 - i
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xf, 0xf, false));  // i <-> 7 - i in halves
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4e, 0xf, 0xf, false));   // i <-> i ^ 2
+    v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xb1, 0xf, 0xf, false));   // i <-> i ^ 1
+    return v;
+}
+
+// Lane-sums of the wave's NC x NV accumulators, on the VALU: v_permlane32_swap folds lanes
+// i and i + 32 of two values at once (the first value's sums land in lanes 0..31, the second's
+// in 32..63), v_permlane16_swap folds lanes i and i + 16 of two such registers, so that each
+// register then holds four values' partial sums, one per 16-lane row (rows 0..3: values 0, 2,
+// 1, 3 of its group of four), and the rows are summed with DPP.  Total v ends in st.tot.
+template <int NC, int NV>
+__device__ __forceinline__ void wave_reduce(float (&acc)[NC][10], WaveState<NC> &st, int lane)
+{
+    constexpr int NT = NC * NV, NG = (NT + 3) / 4;
+    float z[NG];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+    for (int k = 0; k < NG; ++k) {
+        float y[2];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            float x = acc[c][v];
-            x += __shfl_xor(x, 32);
-            x += __shfl_xor(x, 16);
-            if (lane < 16) ws.red[c * NV + v][lane] = x;
+        for (int j = 0; j < 2; ++j) {
+            const int i0 = 4 * k + 2 * j, i1 = i0 + 1;
+            const float x0 = i0 < NT ? acc[i0 / NV][i0 % NV] : 0.f;
+            const float x1 = i1 < NT ? acc[i1 / NV][i1 % NV] : 0.f;
+            const auto s = __builtin_amdgcn_permlane32_swap(__float_as_uint(x0), __float_as_uint(x1), false, false);
+            y[j] = __uint_as_float(s[0]) + __uint_as_float(s[1]);
         }
-    wave_sync();
-    for (int v = lane; v < NC * NV; v += kWave) {
-        const float4 *row = reinterpret_cast<const float4 *>(ws.red[v]);
-        const float4 x0 = row[0], x1 = row[1], x2 = row[2], x3 = row[3];
-        st.tot[v / NV][v % NV] = ((x0.x + x0.y) + (x0.z + x0.w)) + ((x1.x + x1.y) + (x1.z + x1.w)) +
-                                 (((x2.x + x2.y) + (x2.z + x2.w)) + ((x3.x + x3.y) + (x3.z + x3.w)));
+        const auto s = __builtin_amdgcn_permlane16_swap(__float_as_uint(y[0]), __float_as_uint(y[1]), false, false);
+        z[k] = row_sum16(__uint_as_float(s[0]) + __uint_as_float(s[1]));
+    }
+    if ((lane & 15) == 0) {
+        const int r = lane >> 4, e = ((r & 1) << 1) | (r >> 1);
+        float *tot = &st.tot[0][0];
+#pragma unroll
+        for (int k = 0; k < NG; ++k) {
+            const int i = 4 * k + e;
+            if (i < NT) tot[(i / NV) * 10 + i % NV] = z[k];
+        }
     }
     wave_sync();
 }
@@ -448,13 +441,12 @@ template <int NC>
 __device__ __forceinline__ void prepare_step(WaveState<NC> &st, WaveScratch<NC> &ws, int L, int lane)
 {
     if (lane < NC) st.bc[lane] = beta_const(st.th[lane][1]);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) fill_phases(st.th[c][0], st.th[c][2], L, ws.ph.ea[c], ws.ph.eg[c], lane);
+    fill_phases<NC>(st, ws, L, lane);
     wave_sync();
 }
 
 template <int NC>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))) k_march(MarchArgs a)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) k_march(MarchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int p = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
@@ -489,7 +481,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))
         for (int s = 0; s < a.steps; ++s) {
             prepare_step<NC>(st, ws, L, lane);
             eval_level_any<NC, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
-            wave_reduce<NC, 10>(acc, ws, st, lane);
+            wave_reduce<NC, 10>(acc, st, lane);
             if (lane < NC && !st.frozen[lane]) {
                 double e[10];
                 const float *tv = st.tot[lane];
@@ -529,7 +521,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 8))
     // value at the final points on the last level, then selection
     prepare_step<NC>(st, ws, Lp, lane);
     eval_level_any<NC, false>(Cp, a.tab, a.tab64, a.pinfo, Lp, a.fp64_above, st.bc, ws, acc, lane);
-    wave_reduce<NC, 1>(acc, ws, st, lane);
+    wave_reduce<NC, 1>(acc, st, lane);
     if (lane < NC) {
         const int k = wave * NC + lane;
         const float F = 2.f * st.tot[lane][0];
@@ -572,7 +564,7 @@ __global__ void __launch_bounds__(64) k_evaluate(EvalArgs a)
     prepare_step<1>(st, ws, L, lane);
     float acc[1][10];
     eval_level_any<1, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
-    wave_reduce<1, 10>(acc, ws, st, lane);
+    wave_reduce<1, 10>(acc, st, lane);
     if (lane < 10) {
         // signs and factors of the 10 sums; the b-b sum is accumulated from D''/2
         const float sgn = lane == 7 ? 4.f : ((lane == 0 || lane == 2) ? 2.f : -2.f);

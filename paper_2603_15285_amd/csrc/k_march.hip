@@ -35,6 +35,7 @@ struct WaveState {
     float tot[NC][10];
     uint32_t st[NC];
     int frozen[NC];
+    int moved[NC];  // a Newton step moved the candidate since the last prepare_step
     float fprev[NC];
 };
 
@@ -283,6 +284,7 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         const int an = n >= 0 ? n : -n, b2i = n >= 0 ? m : -m;
         const float a1 = (float)m, b1 = (float)n;
         const float a2 = (float)an, b2 = (float)b2i;
+        const float a11 = a1 * a1, a22 = a2 * a2, b11 = b1 * b1, b22 = b2 * b2, ab1 = a1 * b1, ab2 = a2 * b2;
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const int cw = c0 + c;
@@ -305,15 +307,15 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
                 const float J1 = p2.x * u[7] + p2.y * u[6];
                 const float R2 = p1.x * u[8] - p1.y * u[9];  // half of the D'' terms (D''/2 is carried)
                 const float T2 = p2.x * u[10] - p2.y * u[11];
-                acc[cw][1] += a1 * I0 + a2 * J0;
+                acc[cw][1] = fmaf(a1, I0, fmaf(a2, J0, acc[cw][1]));
                 acc[cw][2] += R1 + T1;
-                acc[cw][3] += b1 * I0 + b2 * J0;
-                acc[cw][4] += a1 * a1 * R0 + a2 * a2 * T0;
-                acc[cw][5] += a1 * I1 + a2 * J1;
-                acc[cw][6] += a1 * b1 * R0 + a2 * b2 * T0;
+                acc[cw][3] = fmaf(b1, I0, fmaf(b2, J0, acc[cw][3]));
+                acc[cw][4] = fmaf(a11, R0, fmaf(a22, T0, acc[cw][4]));
+                acc[cw][5] = fmaf(a1, I1, fmaf(a2, J1, acc[cw][5]));
+                acc[cw][6] = fmaf(ab1, R0, fmaf(ab2, T0, acc[cw][6]));
                 acc[cw][7] += R2 + T2;
-                acc[cw][8] += b1 * I1 + b2 * J1;
-                acc[cw][9] += b1 * b1 * R0 + b2 * b2 * T0;
+                acc[cw][8] = fmaf(b1, I1, fmaf(b2, J1, acc[cw][8]));
+                acc[cw][9] = fmaf(b11, R0, fmaf(b22, T0, acc[cw][9]));
             }
         }
     }
@@ -382,9 +384,16 @@ __device__ __forceinline__ void wave_reduce(float (&acc)[NC][10], WaveState<NC> 
     wave_sync();
 }
 
+// x mod 2 pi in [0, 2 pi).  For |x| < 4 pi the remainder is x -+ 2 pi, which FP64 forms exactly
+// (Sterbenz), so fmod is called only beyond that.
 __device__ inline double wrap2pi(double x)
 {
-    x = fmod(x, kTwoPi);
+    if (!(fabs(x) < 2.0 * kTwoPi))
+        x = fmod(x, kTwoPi);
+    else if (x >= kTwoPi)
+        x -= kTwoPi;
+    else if (x <= -kTwoPi)
+        x += kTwoPi;
     return x < 0.0 ? x + kTwoPi : x;
 }
 
@@ -435,12 +444,21 @@ __device__ uint32_t newton_step(const double *e, double max_step, double *th, do
     return st;
 }
 
-// Inlined into the kernels: the wave state and scratch are then addressed as LDS (a generic
-// pointer formed as base - offset can leave the shared aperture when the base sits at LDS 0).
-template <int NC>
+// Per-rotation constants and phase tables of the wave's candidates.  With POLE, a candidate that
+// a Newton step has moved is flagged (status bit 8) when its new b has sin b < 1e-3.  Inlined into
+// the kernels: the wave state and scratch are then addressed as LDS (a generic pointer formed as
+// base - offset can leave the shared aperture when the base sits at LDS 0).
+template <int NC, bool POLE>
 __device__ __forceinline__ void prepare_step(WaveState<NC> &st, WaveScratch<NC> &ws, int L, int lane)
 {
-    if (lane < NC) st.bc[lane] = beta_const(st.th[lane][1]);
+    if (lane < NC) {
+        const BetaConst k = beta_const(st.th[lane][1]);
+        st.bc[lane] = k;
+        if (POLE && st.moved[lane]) {
+            if (k.sbd < 1e-3) st.st[lane] |= 8u;
+            st.moved[lane] = 0;
+        }
+    }
     fill_phases<NC>(st, ws, L, lane);
     wave_sync();
 }
@@ -467,6 +485,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
         st.th[lane][2] = c0.z;
         st.st[lane] = 0;
         st.frozen[lane] = 0;
+        st.moved[lane] = 0;
         st.fprev[lane] = 0.f;
     }
     __syncthreads();
@@ -479,7 +498,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
         const int L = j + 1 < ns ? a.levels[j] : Lp;
         if (lane < NC) st.frozen[lane] = 0;
         for (int s = 0; s < a.steps; ++s) {
-            prepare_step<NC>(st, ws, L, lane);
+            prepare_step<NC, true>(st, ws, L, lane);
             eval_level_any<NC, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
             wave_reduce<NC, 10>(acc, st, lane);
             if (lane < NC && !st.frozen[lane]) {
@@ -508,7 +527,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
                 } else {
                     double sinf_ = 0.0;
                     st.st[lane] |= newton_step(e, a.max_step, st.th[lane], &sinf_);
-                    if (sin(st.th[lane][1]) < 1e-3) st.st[lane] |= 8u;
+                    st.moved[lane] = 1;  // near-pole test at the next prepare_step, from its sin b
                     if (a.early_stop && sinf_ <= a.tol_step) {
                         st.st[lane] |= 32u;
                         st.frozen[lane] = 1;
@@ -519,7 +538,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
         }
     }
     // value at the final points on the last level, then selection
-    prepare_step<NC>(st, ws, Lp, lane);
+    prepare_step<NC, true>(st, ws, Lp, lane);
     eval_level_any<NC, false>(Cp, a.tab, a.tab64, a.pinfo, Lp, a.fp64_above, st.bc, ws, acc, lane);
     wave_reduce<NC, 1>(acc, st, lane);
     if (lane < NC) {
@@ -561,7 +580,7 @@ __global__ void __launch_bounds__(64) k_evaluate(EvalArgs a)
         st.th[0][2] = t.z;
     }
     __syncthreads();
-    prepare_step<1>(st, ws, L, lane);
+    prepare_step<1, false>(st, ws, L, lane);
     float acc[1][10];
     eval_level_any<1, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
     wave_reduce<1, 10>(acc, st, lane);

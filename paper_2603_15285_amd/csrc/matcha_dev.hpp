@@ -37,7 +37,7 @@ struct BetaConst {
     float cb, sb;     // cos b, sin b
     double cbd, sbd;  // cos b, sin b in FP64 (for the FP64 recurrence)
     float ct, tn;     // cot(b/2), tan(b/2)
-    float qk, qp;     // -csc^2(b/2)/4, -sec^2(b/2)/4
+    float ct2, tn2;   // cot^2(b/2), tan^2(b/2)
     double lc2, ls2;  // log2 cos(b/2), log2 sin(b/2)
     double ch, sh;    // cos(b/2), sin(b/2), clamped
 };
@@ -55,8 +55,8 @@ __device__ __forceinline__ BetaConst beta_const(double b)
     k.sb = (float)k.sbd;
     k.ct = (float)(c / s);
     k.tn = (float)(s / c);
-    k.qk = (float)(-0.25 / (s * s));
-    k.qp = (float)(-0.25 / (c * c));
+    k.ct2 = (float)((c * c) / (s * s));
+    k.tn2 = (float)((s * s) / (c * c));
     k.lc2 = log2(c);
     k.ls2 = log2(s);
     k.ch = c;
@@ -67,6 +67,10 @@ __device__ __forceinline__ BetaConst beta_const(double b)
 // d^m_mn(b) and its first two b-derivatives on the edge l = m of the wedge pair:
 //   d = (-1)^k sqrt(binom(2m, p)) cos^p(b/2) sin^k(b/2),  p = m + n, k = m - n,
 //   d'/d = (k cot(b/2) - p tan(b/2)) / 2,  d''/d = (d'/d)^2 - (k csc^2(b/2) + p sec^2(b/2)) / 4.
+// With csc^2 = 1 + cot^2 and sec^2 = 1 + tan^2 the second ratio is
+//   d''/d = (k (k - 1) cot^2(b/2) + p (p - 1) tan^2(b/2) - 2 k p - k - p) / 4,
+// a sum of terms of one sign that does not cancel near the poles the way the first form does
+// (for k = 1 its two terms are each about csc^2(b/2) / 4).
 // The magnitude is formed as 2^x with x in FP64 and split into an exact power of two
 // and a fraction, so the seed keeps FP32 relative accuracy however small it is.
 __device__ inline void edge_seed(int m, int n, double lbh2, const BetaConst &k, float &d0, float &d1, float &d2)
@@ -78,10 +82,10 @@ __device__ inline void edge_seed(int m, int n, double lbh2, const BetaConst &k, 
     e = ldexpf(e, (int)fmax(fl, -1000.0));
     if (kk & 1) e = -e;
     const float h1 = 0.5f * ((float)kk * k.ct - (float)p * k.tn);
-    const float h2 = (float)kk * k.qk + (float)p * k.qp;
+    const float h2 = 0.25f * ((float)(kk * (kk - 1)) * k.ct2 + (float)(p * (p - 1)) * k.tn2 - (float)(2 * kk * p + kk + p));
     d0 = e;
     d1 = e * h1;
-    d2 = e * fmaf(h1, h1, h2);
+    d2 = e * h2;
 }
 
 // The same edge values in FP64 (for the FP64 recurrence above the threshold degree).
@@ -93,10 +97,11 @@ __device__ inline void edge_seed_d(int m, int n, double lbh2, const BetaConst &k
     if (kk & 1) e = -e;
     const double c = k.ch, s = k.sh;
     const double h1 = 0.5 * ((double)kk * (c / s) - (double)p * (s / c));
-    const double h2 = -0.25 * ((double)kk / (s * s) + (double)p / (c * c));
+    const double h2 = 0.25 * ((double)(kk * (kk - 1)) * ((c * c) / (s * s)) + (double)(p * (p - 1)) * ((s * s) / (c * c)) -
+                              (double)(2 * kk * p + kk + p));
     d0 = e;
     d1 = e * h1;
-    d2 = e * (h1 * h1 + h2);
+    d2 = e * h2;
 }
 
 // Orders the LDS accesses of one wave's lanes.  A wave's LDS operations complete in issue

@@ -95,3 +95,30 @@ def test_longest_first_order_keeps_results(M, ctx):
     got = eager(M, ctx, batch, f, h, w, wl)
     for x, y in zip(got, ref):
         assert torch.equal(x, y)
+
+
+def test_march_near_pole_candidates_independent_of_grouping(M):
+    """Candidates at and next to the poles beside ordinary ones: every candidate's result must be the
+    same however the candidates are grouped into waves (march_nc)."""
+    c = M.Context(0)
+    wl = S.WORKLOADS["L32_R32_B12_K16"]
+    b = S.make_workload("L32_R32_B12_K16", n_particles=6)
+    batch, f, h, w = upload(M, b)
+    C = M.coeff_assemble(c, batch, f, h, w)
+    cand0, st0 = M.soft_search(c, batch, C, wl.B, wl.n_grid, wl.Kc)
+    cand0[:, 1, 1] = 5e-5
+    cand0[:, 6, 1] = float(np.pi - 3e-5)
+    cand0[::2, 9, 1] = 2e-4
+    cand0[1::2, 13, 1] = 0.0
+    out = {}
+    for nc in (1, 2, 4, 8):
+        c.set_tuning(nc, 0)
+        cand, st = cand0.clone(), st0.clone()
+        best, bi, st = M.march_newton(c, batch, C, wl.levels, wl.steps, cand, st)
+        torch.cuda.synchronize()
+        out[nc] = (cand, best, bi, st)
+    for nc in (2, 4, 8):
+        for x, y in zip(out[nc], out[1]):
+            assert torch.equal(x, y), nc
+    assert torch.isfinite(out[1][0]).all()
+    c.close()

@@ -69,7 +69,10 @@ def test_evaluate_matches_oracle(M, ctx, L, R):
     batch, f, h, w = upload(M, b)
     C = M.coeff_assemble(ctx, batch, f, h, w)
     rng = np.random.default_rng(L)
-    thetas = [S.haar_euler(rng, 1)[0] for _ in range(4)] + [np.array([1.0, 0.02, 2.0]), np.array([4.0, math.pi - 0.03, 0.5])]
+    # b near the poles, where the edge values of d'' must not lose precision to cancellation
+    thetas = [S.haar_euler(rng, 1)[0] for _ in range(4)] + [np.array([1.0, 0.02, 2.0]), np.array([4.0, math.pi - 0.03, 0.5]),
+                                                            np.array([2.5, 1.5e-4, 0.3]), np.array([0.7, math.pi - 1.2e-4, 5.0]),
+                                                            np.array([5.0, 5e-5, 1.0])]
     for th in thetas:
         for Le in sorted({4, L // 2, L}):
             theta = torch.tensor(np.tile(np.r_[th, 0.0], (3, 1)), dtype=torch.float32).cuda()
@@ -434,7 +437,7 @@ def test_fp64_recurrence_above_40(M, ctx):
     batch, f, h, w = upload(M, b)
     C = M.coeff_assemble(ctx, batch, f, h, w)
     rng = np.random.default_rng(48)
-    for th in [S.haar_euler(rng, 1)[0], np.array([1.0, 0.05, 2.0])]:
+    for th in [S.haar_euler(rng, 1)[0], np.array([1.0, 0.05, 2.0]), np.array([3.0, 2e-4, 1.0]), np.array([1.0, 5e-5, 6.0])]:
         theta = torch.tensor(np.tile(np.r_[th, 0.0], (2, 1)), dtype=torch.float32).cuda()
         out = M.evaluate(ctx, batch, C, 48, theta, fp64_above=40).cpu().numpy().astype(np.float64)
         th32 = theta[0, :3].cpu().numpy().astype(np.float64)

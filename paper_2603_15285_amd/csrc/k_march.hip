@@ -68,7 +68,9 @@ __device__ __forceinline__ void fill_phases(const WaveState<NC> &st, WaveScratch
 //   D'^l = u D'^{l-1} - v D^{l-1} - D'^{l-2},  (D''/2)^l = u (D''/2)^{l-1} - v D'^{l-1} - h D^{l-1} - (D''/2)^{l-2}.
 // SEED: rows where pairs of the tile start; lanes with seed set take the edge values (S0, S1, S2)
 // instead.  Lanes whose pair starts later hold a zero state, which the step keeps at zero.
-template <int NC, bool DERIV, bool SEED, typename T>
+// FIRST = 1: the tile's first row, where X and Y are zero (neither is read) and U is set rather
+// than accumulated; FIRST = 2: its second row, where Y is zero (not read).
+template <int NC, bool DERIV, bool SEED, typename T, int FIRST = 0>
 __device__ __forceinline__ void row_step(const T A, const T AC, const float4 tb, const float4 cc, const bool seed,
                                          const T (&S0)[NC], const T (&S1)[NC], const T (&S2)[NC], const T *cbv,
                                          const T *sbv, const T *chv, T (&X)[NC], T (&Y)[NC], T (&X1)[NC],
@@ -78,31 +80,54 @@ __device__ __forceinline__ void row_step(const T A, const T AC, const float4 tb,
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const T u = fma(A, cbv[c], -AC);
-        T dn = fma(u, X[c], -Y[c]);
+        T dn = FIRST == 1 ? (T)0 : FIRST == 2 ? u * X[c] : fma(u, X[c], -Y[c]);
         if (SEED) dn = seed ? S0[c] : dn;
-        U[c][0] = fma(s0r, dn, U[c][0]);
-        U[c][1] = fma(s0i, dn, U[c][1]);
-        U[c][2] = fma(s1r, dn, U[c][2]);
-        U[c][3] = fma(s1i, dn, U[c][3]);
+        if (FIRST == 1) {
+            U[c][0] = s0r * dn;
+            U[c][1] = s0i * dn;
+            U[c][2] = s1r * dn;
+            U[c][3] = s1i * dn;
+        } else {
+            U[c][0] = fma(s0r, dn, U[c][0]);
+            U[c][1] = fma(s0i, dn, U[c][1]);
+            U[c][2] = fma(s1r, dn, U[c][2]);
+            U[c][3] = fma(s1i, dn, U[c][3]);
+        }
         if (DERIV) {
-            const T v = A * sbv[c];
-            const T h = A * chv[c];
-            T d1n = fma(u, X1[c], fma(-v, X[c], -Y1[c]));
-            T d2n = fma(u, X2[c], fma(-v, X1[c], fma(-h, X[c], -Y2[c])));
+            T d1n, d2n;
+            if (FIRST == 1) {
+                d1n = d2n = (T)0;
+            } else {
+                const T v = A * sbv[c];
+                const T h = A * chv[c];
+                d1n = FIRST == 2 ? fma(u, X1[c], -v * X[c]) : fma(u, X1[c], fma(-v, X[c], -Y1[c]));
+                d2n = FIRST == 2 ? fma(u, X2[c], fma(-v, X1[c], -h * X[c])) : fma(u, X2[c], fma(-v, X1[c], fma(-h, X[c], -Y2[c])));
+            }
             if (SEED) {
                 d1n = seed ? S1[c] : d1n;
                 d2n = seed ? S2[c] : d2n;
             }
             Y1[c] = d1n;
             Y2[c] = d2n;
-            U[c][4] = fma(s0r, d1n, U[c][4]);
-            U[c][5] = fma(s0i, d1n, U[c][5]);
-            U[c][6] = fma(s1r, d1n, U[c][6]);
-            U[c][7] = fma(s1i, d1n, U[c][7]);
-            U[c][8] = fma(s0r, d2n, U[c][8]);
-            U[c][9] = fma(s0i, d2n, U[c][9]);
-            U[c][10] = fma(s1r, d2n, U[c][10]);
-            U[c][11] = fma(s1i, d2n, U[c][11]);
+            if (FIRST == 1) {
+                U[c][4] = s0r * d1n;
+                U[c][5] = s0i * d1n;
+                U[c][6] = s1r * d1n;
+                U[c][7] = s1i * d1n;
+                U[c][8] = s0r * d2n;
+                U[c][9] = s0i * d2n;
+                U[c][10] = s1r * d2n;
+                U[c][11] = s1i * d2n;
+            } else {
+                U[c][4] = fma(s0r, d1n, U[c][4]);
+                U[c][5] = fma(s0i, d1n, U[c][5]);
+                U[c][6] = fma(s1r, d1n, U[c][6]);
+                U[c][7] = fma(s1i, d1n, U[c][7]);
+                U[c][8] = fma(s0r, d2n, U[c][8]);
+                U[c][9] = fma(s0i, d2n, U[c][9]);
+                U[c][10] = fma(s1r, d2n, U[c][10]);
+                U[c][11] = fma(s1i, d2n, U[c][11]);
+            }
         }
         Y[c] = dn;
     }
@@ -225,20 +250,15 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
             seed_T<T>(m, n, pi.lbh2, bc[c0 + c], sd0[c], sd1[c], sd2[c]);
             sd2[c] *= (T)0.5;
         }
+        // the state before row mlo is zero: the first two rows take it as such (row_step FIRST)
         T D[NC], Dm[NC], D1[NC], D1m[NC], D2[NC], D2m[NC];
         T U[NC][NU];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            D[c] = Dm[c] = D1[c] = D1m[c] = D2[c] = D2m[c] = (T)0;
-#pragma unroll
-            for (int v = 0; v < NU; ++v) U[c][v] = (T)0;
-        }
-#define MARCH_ROW0(SEEDROW)                                                                              \
-    row_step<NC, DERIV, SEEDROW, T>(A0, AC0, tb0, cc0, m == l, sd0, sd1, sd2, cbv, sbv, chv, D, Dm, D1, D1m, D2, \
-                                    D2m, U)
-#define MARCH_ROW1(SEEDROW)                                                                                  \
-    row_step<NC, DERIV, SEEDROW, T>(A1, AC1, tb1, cc1, m == l + 1, sd0, sd1, sd2, cbv, sbv, chv, Dm, D, D1m, D1, \
-                                    D2m, D2, U)
+#define MARCH_ROW0(SEEDROW, FST)                                                                         \
+    row_step<NC, DERIV, SEEDROW, T, FST>(A0, AC0, tb0, cc0, m == l, sd0, sd1, sd2, cbv, sbv, chv, D, Dm, D1, D1m, D2, \
+                                         D2m, U)
+#define MARCH_ROW1(SEEDROW, FST)                                                                             \
+    row_step<NC, DERIV, SEEDROW, T, FST>(A1, AC1, tb1, cc1, m == l + 1, sd0, sd1, sd2, cbv, sbv, chv, Dm, D, D1m, D1, \
+                                         D2m, D2, U)
 #define MARCH_LOAD0()                                                                                    \
     do {                                                                                                 \
         __builtin_amdgcn_sched_barrier(0);                                                               \
@@ -261,20 +281,24 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
     } while (0)
         // rows where pairs of the tile start (mlo .. mhi, rounded up to an even count, at most L)
         const int lseed = min(mhi + ((mhi - mlo) & 1 ? 0 : 1), L);
-        for (; l <= lseed; l += 2) {
-            MARCH_ROW0(true);
+        MARCH_ROW0(true, 1);
+        MARCH_LOAD0();
+        if (l < L) MARCH_ROW1(true, 2);
+        MARCH_LOAD1();
+        for (l += 2; l <= lseed; l += 2) {
+            MARCH_ROW0(true, 0);
             MARCH_LOAD0();
-            if (l < L) MARCH_ROW1(true);
+            if (l < L) MARCH_ROW1(true, 0);
             MARCH_LOAD1();
         }
         // rows where every pair of the tile has started
         for (; l + 1 <= L; l += 2) {
-            MARCH_ROW0(false);
+            MARCH_ROW0(false, 0);
             MARCH_LOAD0();
-            MARCH_ROW1(false);
+            MARCH_ROW1(false, 0);
             MARCH_LOAD1();
         }
-        if (l <= L) MARCH_ROW0(false);
+        if (l <= L) MARCH_ROW0(false, 0);
 #undef MARCH_ROW0
 #undef MARCH_ROW1
 #undef MARCH_LOAD0

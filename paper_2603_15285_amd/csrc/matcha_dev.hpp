@@ -39,7 +39,7 @@ struct BetaConst {
     float ct, tn;     // cot(b/2), tan(b/2)
     float ct2, tn2;   // cot^2(b/2), tan^2(b/2)
     double lc2, ls2;  // log2 cos(b/2), log2 sin(b/2)
-    double ch, sh;    // cos(b/2), sin(b/2), clamped
+    double ctd, tnd;  // cot(b/2), tan(b/2) in FP64
 };
 
 __device__ __forceinline__ BetaConst beta_const(double b)
@@ -59,8 +59,8 @@ __device__ __forceinline__ BetaConst beta_const(double b)
     k.tn2 = (float)((s * s) / (c * c));
     k.lc2 = log2(c);
     k.ls2 = log2(s);
-    k.ch = c;
-    k.sh = s;
+    k.ctd = c / s;
+    k.tnd = s / c;
     return k;
 }
 
@@ -95,10 +95,9 @@ __device__ inline void edge_seed_d(int m, int n, double lbh2, const BetaConst &k
     const double x = lbh2 + (double)p * k.lc2 + (double)kk * k.ls2;
     double e = exp2(x);
     if (kk & 1) e = -e;
-    const double c = k.ch, s = k.sh;
-    const double h1 = 0.5 * ((double)kk * (c / s) - (double)p * (s / c));
-    const double h2 = 0.25 * ((double)(kk * (kk - 1)) * ((c * c) / (s * s)) + (double)(p * (p - 1)) * ((s * s) / (c * c)) -
-                              (double)(2 * kk * p + kk + p));
+    const double ct = k.ctd, tn = k.tnd;
+    const double h1 = 0.5 * ((double)kk * ct - (double)p * tn);
+    const double h2 = 0.25 * ((double)(kk * (kk - 1)) * (ct * ct) + (double)(p * (p - 1)) * (tn * tn) - (double)(2 * kk * p + kk + p));
     d0 = e;
     d1 = e * h1;
     d2 = e * h2;

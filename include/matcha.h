@@ -21,8 +21,9 @@
  * The caller allocates every input, output and workspace buffer; the library
  * keeps no pointer after the enqueued work completes.  A context owns read-only
  * tables (recurrence coefficients, SOFFT node data) that it builds on the first call
- * that needs them or in matcha_prepare(), and the SOFFT workspace of its eager
- * matcha_soft_search calls (see there).  Every call validates its
+ * that needs them or in matcha_prepare(), the SOFFT workspace of its eager
+ * matcha_soft_search calls (see there) and the particle order of its eager
+ * matcha_coeff_assemble calls on batches of mixed L_p (see there).  Every call validates its
  * arguments synchronously on the host and then enqueues its kernels on `stream`
  * (a hipStream_t passed as void*); nothing waits on the device.  A context is not
  * thread-safe.
@@ -171,7 +172,11 @@ matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg
  * layout.  Accumulation is FP32 in both modes.  The template's degree-L_max row over
  * R_max = max_p R_p shells is staged in one workgroup's LDS: MATCHA_ERR_UNSUPPORTED when
  * 8 R_max 16 ceil((2 L_max + 1) / 16) bytes (FP32; BF16: 4 (2 R_max rounded up to 32, + 8)
- * 16 ceil((2 L_max + 1) / 16)) exceed 160 KB, e.g. R_max > 142 at L_max = 64 in FP32. */
+ * 16 ceil((2 L_max + 1) / 16)) exceed 160 KB, e.g. R_max > 142 at L_max = 64 in FP32.
+ * When the L_p differ, a first kernel orders the particles by decreasing L_p into P int32
+ * owned by the context (allocated on first need and grown synchronously; a graph from
+ * matcha_align_graph_create owns its own), so that the rows of degree l cover only the
+ * particles with L_p >= l; results do not depend on that order. */
 matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
                                     const float *w, float *C, matcha_precision prec, void *stream);
 

@@ -17,9 +17,11 @@
 // template's degree-l row, h_l(r) for all shells, into LDS once; each wave then loads the A
 // column of a row tile straight from f (every f value is read once), keeps it in registers
 // and sweeps the column tiles with B from LDS.  Rows of one tile may belong to several
-// particles, so small degrees still fill the 16-row tiles.  Rows of particles with L_p < l
-// and shells r >= R_p are masked to zero.  Workgroups of the highest degrees (most column
-// tiles) are launched first.
+// particles, so small degrees still fill the 16-row tiles.  When the band limits differ, the
+// rows of degree l cover only the particles with L_p >= l: the particles are taken in the
+// order of decreasing L_p (k_order_by_L), of which the first np_l[l] qualify.  Shells
+// r >= R_p are masked to zero.  Workgroups of the highest degrees (most column tiles) are
+// launched first.
 #include "matcha_launch.hpp"
 
 namespace matcha {
@@ -71,7 +73,7 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_f32(AsmArgs a)
     }
     for (int t = threadIdx.x; t < R; t += kAsmThreads) ws[t] = a.w[t];
     __syncthreads();
-    const int rows = a.P * (l + 1), RT = (rows + 15) / 16;
+    const int rows = a.np_l[l] * (l + 1), RT = (rows + 15) / 16;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int col = lane % 16, kq = lane / 16;
     const int par = kq & 1, rsub = kq >> 1;  // K index 4 s + kq = 2 (2 s + rsub) + par
@@ -81,7 +83,8 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_f32(AsmArgs a)
         if (rt >= RT) break;
         // the lane's A row
         const int rho = min(16 * rt + col, rows - 1);
-        const int p = rho / (l + 1), m = rho - p * (l + 1);
+        const int pi = rho / (l + 1), m = rho - pi * (l + 1);
+        const int p = a.by_L ? a.by_L[pi] : pi;
         const int Lp = a.Lp[p], Rp = a.Rp[p];
         const bool rok = 16 * rt + col < rows && l <= Lp;
         const int sf = (Lp + 1) * (Lp + 1);
@@ -94,9 +97,10 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_f32(AsmArgs a)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int ro = 16 * rt + 4 * kq + v;
-            const int po = min(ro, rows - 1) / (l + 1);
+            const int pio = min(ro, rows - 1) / (l + 1);
+            const int po = a.by_L ? a.by_L[pio] : pio;
             const int Lpo = a.Lp[po];
-            mo[v] = ro - po * (l + 1);
+            mo[v] = ro - pio * (l + 1);
             ook[v] = (ro < rows) & (l <= Lpo);
             cp[v] = reinterpret_cast<float2 *>(a.C + a.C_off[po] / 2);
         }
@@ -137,6 +141,35 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_f32(AsmArgs a)
     }
 }
 
+// Counting sort of the particles by decreasing L_p in one workgroup: a histogram of L_p in LDS,
+// the start of each degree's run, then every particle takes the next slot of its run (the
+// order within a run is whatever the LDS atomics give; the assembly does not depend on it).
+constexpr int kOrderThreads = 1024;
+__global__ void __launch_bounds__(kOrderThreads) k_order_by_L(const int32_t *Lp, int P, int Lmax, int32_t *by_L)
+{
+    __shared__ int cnt[kMaxL + 1], start[kMaxL + 1];
+    for (int l = threadIdx.x; l <= Lmax; l += kOrderThreads) cnt[l] = 0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < P; p += kOrderThreads) atomicAdd(&cnt[min(max(Lp[p], 0), Lmax)], 1);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int l = Lmax; l >= 0; --l) {
+            start[l] = s;
+            s += cnt[l];
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < P; p += kOrderThreads) by_L[atomicAdd(&start[min(max(Lp[p], 0), Lmax)], 1)] = p;
+}
+
+hipError_t launch_order_by_L(const int32_t *Lp, int P, int Lmax, int32_t *by_L, hipStream_t s)
+{
+    if (P <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_order_by_L, dim3(1), dim3(kOrderThreads), 0, s, Lp, P, Lmax, by_L);
+    return hipGetLastError();
+}
+
 size_t assemble_smem_bytes(int Lmax, int Rmax)
 {
     return sizeof(float2) * (size_t)Rmax * asm_cols(Lmax) + sizeof(float) * (size_t)Rmax;
@@ -151,11 +184,13 @@ hipError_t launch_assemble_f32(const AsmArgs &a0, int P, int Lmax, int Rmax, hip
     int nb = 0;
     for (int d = 0; d <= Lmax; ++d) {
         const int l = Lmax - d;
-        const int64_t rt = ((int64_t)P * (l + 1) + 15) / 16;
+        if (!a.by_L) a.np_l[l] = P;
+        const int64_t rt = ((int64_t)a.np_l[l] * (l + 1) + 15) / 16;
         a.blk_lo[d] = nb;
         nb += (int)((rt + kAsmTilesPerBlock - 1) / kAsmTilesPerBlock);
     }
     a.blk_lo[Lmax + 1] = nb;
+    if (nb == 0) return hipSuccess;
     const size_t smem = assemble_smem_bytes(Lmax, Rmax);
     if (Rmax > 32 && Rmax <= 64)
         hipLaunchKernelGGL(k_assemble_f32<32>, dim3(nb), dim3(kAsmThreads), smem, s, a);

@@ -15,8 +15,9 @@
 // A workgroup takes one degree and a run of 16-row tiles of its stacked rows.  It builds B for
 // the degree in LDS once ([column][K], K contiguous, rows padded by 16 bytes); each wave loads
 // the A operands of a row tile straight from f (four 4-byte complex values per lane and step;
-// every f value is read once), keeps them in registers and sweeps the column tiles.  Rows of
-// particles with L_p < l and shells r >= R_p are masked to zero.  Workgroups of the highest
+// every f value is read once), keeps them in registers and sweeps the column tiles.  When the
+// band limits differ, the rows of degree l cover only the particles with L_p >= l, taken in
+// the order of decreasing L_p; shells r >= R_p are masked to zero.  Workgroups of the highest
 // degrees are launched first.
 #include "matcha_launch.hpp"
 
@@ -77,7 +78,7 @@ __global__ void __launch_bounds__(kAsmBThreads) k_assemble_bf16(AsmBArgs a)
         Bis[j * KS + 2 * r + 1] = (__bf16)hr;
     }
     __syncthreads();
-    const int rows = a.P * (l + 1), RT = (rows + 15) / 16;
+    const int rows = a.np_l[l] * (l + 1), RT = (rows + 15) / 16;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int col = lane % 16, kg = lane / 16;  // K elements 8 kg .. +7: shells 4 kg .. +3 of a step
     const int nk = K / 32;
@@ -86,7 +87,8 @@ __global__ void __launch_bounds__(kAsmBThreads) k_assemble_bf16(AsmBArgs a)
         const int rt = blk * kAsmBTilesPerBlock + it * kAsmBWaves + wave;
         if (rt >= RT) break;
         const int rho = min(16 * rt + col, rows - 1);
-        const int p = rho / (l + 1), m = rho - p * (l + 1);
+        const int pi = rho / (l + 1), m = rho - pi * (l + 1);
+        const int p = a.by_L ? a.by_L[pi] : pi;
         const int Lp = a.Lp[p], Rp = a.Rp[p];
         const bool rok = (16 * rt + col < rows) & (l <= Lp);
         const int sf = (Lp + 1) * (Lp + 1);
@@ -97,9 +99,10 @@ __global__ void __launch_bounds__(kAsmBThreads) k_assemble_bf16(AsmBArgs a)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int ro = 16 * rt + 4 * kg + v;
-            const int po = min(ro, rows - 1) / (l + 1);
+            const int pio = min(ro, rows - 1) / (l + 1);
+            const int po = a.by_L ? a.by_L[pio] : pio;
             const int Lpo = a.Lp[po];
-            mo[v] = ro - po * (l + 1);
+            mo[v] = ro - pio * (l + 1);
             ook[v] = (ro < rows) & (l <= Lpo);
             cp[v] = reinterpret_cast<float2 *>(a.C + a.C_off[po] / 2);
         }
@@ -158,11 +161,13 @@ hipError_t launch_assemble_bf16(const AsmBArgs &a0, int P, int Lmax, int Rmax, h
     int nb = 0;
     for (int d = 0; d <= Lmax; ++d) {
         const int l = Lmax - d;
-        const int64_t rt = ((int64_t)P * (l + 1) + 15) / 16;
+        if (!a.by_L) a.np_l[l] = P;
+        const int64_t rt = ((int64_t)a.np_l[l] * (l + 1) + 15) / 16;
         a.blk_lo[d] = nb;
         nb += (int)((rt + kAsmBTilesPerBlock - 1) / kAsmBTilesPerBlock);
     }
     a.blk_lo[Lmax + 1] = nb;
+    if (nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_assemble_bf16, dim3(nb), dim3(kAsmBThreads), assemble_bf16_smem_bytes(Lmax, Rmax), s, a);
     return hipGetLastError();
 }

@@ -27,6 +27,8 @@ struct matcha_ctx {
     float *dft = nullptr;           // DFT tables of the SOFFT grid kernel (build_soft_dft)
     float *soft_ws = nullptr;       // SOFFT grid workspace of the eager calls
     size_t soft_ws_bytes = 0;
+    int32_t *by_L = nullptr;        // particle order of the eager assembly calls on mixed L_p
+    int by_L_cap = 0;
 };
 
 namespace {
@@ -254,7 +256,26 @@ matcha_status ensure_soft_ws(matcha_ctx *ctx, size_t bytes)
     return MATCHA_OK;
 }
 
+matcha_status ensure_by_L(matcha_ctx *ctx, int P)
+{
+    if (ctx->by_L_cap >= P) return MATCHA_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    if (ctx->by_L) {
+        (void)hipDeviceSynchronize();  // earlier assemblies may still read it
+        (void)hipFree(ctx->by_L);
+        ctx->by_L = nullptr;
+        ctx->by_L_cap = 0;
+    }
+    if (hipMalloc(&ctx->by_L, sizeof(int32_t) * (size_t)P) != hipSuccess) {
+        ctx->by_L = nullptr;
+        return MATCHA_ERR_HIP;
+    }
+    ctx->by_L_cap = P;
+    return MATCHA_OK;
+}
+
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
 
 // Common batch checks; on success minL / maxL / maxR hold the host-side extents.
 matcha_status check_batch(const matcha_batch *b, int *minL, int *maxL, int *maxR)
@@ -291,6 +312,72 @@ int march_nc(const matcha_ctx *ctx, int Kc)
     return nc;
 }
 
+// Argument checks of the assembly (the batch itself is checked by check_batch).
+matcha_status assemble_check(const matcha_batch *batch, const void *f, const void *h, const float *w, const float *C,
+                             matcha_precision prec, int hi, int rmax)
+{
+    if (!f || !h || !w || !C || !batch->f_offset || !aligned16(C)) return MATCHA_ERR_INVALID_ARG;
+    if (prec != MATCHA_FP32 && prec != MATCHA_BF16_FP32ACC) return MATCHA_ERR_UNSUPPORTED;
+    // the kernels index within one particle's f and within h with 32-bit offsets
+    if ((int64_t)batch->R_h * (batch->L_h + 1) * (batch->L_h + 1) >= INT32_MAX) return MATCHA_ERR_UNSUPPORTED;
+    const size_t smem = prec == MATCHA_FP32 ? assemble_smem_bytes(hi, rmax) : assemble_bf16_smem_bytes(hi, rmax);
+    if (smem > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
+    return MATCHA_OK;
+}
+
+// The assembly launches.  With mixed L_p (lo < hi), by_L ([P] int32) receives the particles in
+// the order of decreasing L_p first, so that each degree's rows cover only the particles that
+// have it.
+matcha_status assemble_ws(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h, const float *w,
+                          float *C, matcha_precision prec, int lo, int hi, int rmax, int32_t *by_L, hipStream_t s)
+{
+    const int P = batch->n_particles;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    int np_l[kMaxL + 1];
+    const bool mixed = lo != hi;
+    if (mixed) {
+        for (int l = 0; l <= hi; ++l) np_l[l] = 0;
+        for (int p = 0; p < P; ++p) np_l[batch->L_host[p]] += 1;
+        for (int l = hi - 1; l >= 0; --l) np_l[l] += np_l[l + 1];  // particles with L_p >= l
+        const hipError_t e = launch_order_by_L(batch->L_dev, P, hi, by_L, s);
+        if (e != hipSuccess) return launched(e);
+    }
+    if (prec == MATCHA_BF16_FP32ACC) {
+        AsmBArgs b;
+        std::memset(&b, 0, sizeof b);
+        b.f = static_cast<const __bf16 *>(f);
+        b.f_off = batch->f_offset;
+        b.h = static_cast<const __bf16 *>(h);
+        b.w = w;
+        b.Lp = batch->L_dev;
+        b.Rp = batch->R_dev;
+        b.Lh = batch->L_h;
+        b.C = reinterpret_cast<float4 *>(C);
+        b.C_off = batch->C_offset;
+        if (mixed) {
+            b.by_L = by_L;
+            std::memcpy(b.np_l, np_l, sizeof(int) * (size_t)(hi + 1));
+        }
+        return launched(launch_assemble_bf16(b, P, hi, rmax, s));
+    }
+    AsmArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.f = static_cast<const float2 *>(f);
+    a.f_off = batch->f_offset;
+    a.h = static_cast<const float2 *>(h);
+    a.w = w;
+    a.Lp = batch->L_dev;
+    a.Rp = batch->R_dev;
+    a.Lh = batch->L_h;
+    a.C = reinterpret_cast<float4 *>(C);
+    a.C_off = batch->C_offset;
+    if (mixed) {
+        a.by_L = by_L;
+        std::memcpy(a.np_l, np_l, sizeof(int) * (size_t)(hi + 1));
+    }
+    return launched(launch_assemble_f32(a, P, hi, rmax, s));
+}
+
 }  // namespace
 
 extern "C" {
@@ -318,12 +405,13 @@ matcha_status matcha_destroy(matcha_ctx *ctx)
         (void)hipFree(ctx->tab64);
         (void)hipFree(ctx->pinfo);
     }
-    if (ctx->dgrid || ctx->soft_ws) {
+    if (ctx->dgrid || ctx->soft_ws || ctx->by_L) {
         (void)hipSetDevice(ctx->device);
         (void)hipDeviceSynchronize();
         if (ctx->dgrid) (void)hipFree(ctx->dgrid);
         if (ctx->dft) (void)hipFree(ctx->dft);
         if (ctx->soft_ws) (void)hipFree(ctx->soft_ws);
+        if (ctx->by_L) (void)hipFree(ctx->by_L);
     }
     delete ctx;
     return MATCHA_OK;
@@ -401,39 +489,13 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
     matcha_status st = check_batch(batch, &lo, &hi, &rmax);
     if (st != MATCHA_OK) return st;
     if (batch->n_particles == 0) return MATCHA_OK;
-    if (!f || !h || !w || !C || !batch->f_offset || !aligned16(C)) return MATCHA_ERR_INVALID_ARG;
-    if (prec != MATCHA_FP32 && prec != MATCHA_BF16_FP32ACC) return MATCHA_ERR_UNSUPPORTED;
-    // the kernels index within one particle's f and within h with 32-bit offsets
-    if ((int64_t)batch->R_h * (batch->L_h + 1) * (batch->L_h + 1) >= INT32_MAX) return MATCHA_ERR_UNSUPPORTED;
-    const size_t smem = prec == MATCHA_FP32 ? assemble_smem_bytes(hi, rmax) : assemble_bf16_smem_bytes(hi, rmax);
-    if (smem > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
-    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    if (prec == MATCHA_BF16_FP32ACC) {
-        AsmBArgs b;
-        std::memset(&b, 0, sizeof b);
-        b.f = static_cast<const __bf16 *>(f);
-        b.f_off = batch->f_offset;
-        b.h = static_cast<const __bf16 *>(h);
-        b.w = w;
-        b.Lp = batch->L_dev;
-        b.Rp = batch->R_dev;
-        b.Lh = batch->L_h;
-        b.C = reinterpret_cast<float4 *>(C);
-        b.C_off = batch->C_offset;
-        return launched(launch_assemble_bf16(b, batch->n_particles, hi, rmax, static_cast<hipStream_t>(stream)));
+    st = assemble_check(batch, f, h, w, C, prec, hi, rmax);
+    if (st != MATCHA_OK) return st;
+    if (lo != hi) {
+        st = ensure_by_L(ctx, batch->n_particles);
+        if (st != MATCHA_OK) return st;
     }
-    AsmArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.f = static_cast<const float2 *>(f);
-    a.f_off = batch->f_offset;
-    a.h = static_cast<const float2 *>(h);
-    a.w = w;
-    a.Lp = batch->L_dev;
-    a.Rp = batch->R_dev;
-    a.Lh = batch->L_h;
-    a.C = reinterpret_cast<float4 *>(C);
-    a.C_off = batch->C_offset;
-    return launched(launch_assemble_f32(a, batch->n_particles, hi, rmax, static_cast<hipStream_t>(stream)));
+    return assemble_ws(ctx, batch, f, h, w, C, prec, lo, hi, rmax, ctx->by_L, static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"
@@ -652,6 +714,7 @@ struct matcha_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     float *soft_ws = nullptr;  // the graph's own SOFFT grid workspace (the context's may be regrown)
+    int32_t *by_L = nullptr;   // the graph's own particle order for the assembly (mixed L_p)
     int device = 0;
 };
 
@@ -682,16 +745,22 @@ matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *bat
     }
     auto fail = [&](matcha_status e) {
         if (g->soft_ws) (void)hipFree(g->soft_ws);
+        if (g->by_L) (void)hipFree(g->by_L);
         delete g;
         return e;
     };
+    if (P > 0 && lo != hi && hipMalloc(&g->by_L, sizeof(int32_t) * (size_t)P) != hipSuccess) return fail(MATCHA_ERR_HIP);
+    if (P > 0) {
+        st = assemble_check(batch, f, h, w, C, prec, hi, rmax);
+        if (st != MATCHA_OK) return fail(st);
+    }
     hipStream_t cs = nullptr;
     if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(MATCHA_ERR_HIP);
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipStreamDestroy(cs);
         return fail(MATCHA_ERR_HIP);
     }
-    st = matcha_coeff_assemble(ctx, batch, f, h, w, C, prec, cs);
+    if (P > 0) st = assemble_ws(ctx, batch, f, h, w, C, prec, lo, hi, rmax, g->by_L, cs);
     if (st == MATCHA_OK && P > 0) st = soft_search_ws(ctx, batch, C, soft, cand, status, nt, g->soft_ws, ws_bytes, cs);
     if (st == MATCHA_OK) st = matcha_march_newton(ctx, batch, C, march, soft->Kc, cand, best, best_idx, status, cs);
     hipGraph_t graph = nullptr;
@@ -721,10 +790,11 @@ matcha_status matcha_graph_destroy(matcha_graph *g)
     if (!g) return MATCHA_ERR_INVALID_ARG;
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    if (g->soft_ws) {
+    if (g->soft_ws || g->by_L) {
         (void)hipSetDevice(g->device);
-        (void)hipDeviceSynchronize();  // replays may still read it
-        (void)hipFree(g->soft_ws);
+        (void)hipDeviceSynchronize();  // replays may still read them
+        if (g->soft_ws) (void)hipFree(g->soft_ws);
+        if (g->by_L) (void)hipFree(g->by_L);
     }
     delete g;
     return MATCHA_OK;

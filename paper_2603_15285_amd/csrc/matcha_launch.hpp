@@ -14,8 +14,10 @@ struct AsmArgs {
     int Lh;
     float4 *C;
     const int64_t *C_off;
+    const int32_t *by_L;      // nullable: particle indices by decreasing L_p (k_order_by_L); null: all L_p equal
     int P, Lmax, Rmax;        // set by the launcher
     int blk_lo[kMaxL + 2];    // first workgroup of degree Lmax - d, d = 0 .. Lmax; [Lmax+1]: total
+    int np_l[kMaxL + 1];      // particles with L_p >= l: the first np_l[l] entries of by_L (or all P)
 };
 
 struct AsmBArgs {
@@ -28,8 +30,10 @@ struct AsmBArgs {
     int Lh;
     float4 *C;
     const int64_t *C_off;
+    const int32_t *by_L;      // nullable: particle indices by decreasing L_p (k_order_by_L); null: all L_p equal
     int P, Lmax, Rmax;        // set by the launcher
     int blk_lo[kMaxL + 2];    // first workgroup of degree Lmax - d, d = 0 .. Lmax; [Lmax+1]: total
+    int np_l[kMaxL + 1];      // particles with L_p >= l: the first np_l[l] entries of by_L (or all P)
 };
 
 struct SoftArgs {
@@ -105,6 +109,8 @@ struct GradArgs {
 
 size_t assemble_smem_bytes(int Lmax, int Rmax);
 hipError_t launch_assemble_f32(const AsmArgs &a, int P, int Lmax, int Rmax, hipStream_t s);
+// by_L[0 .. P-1] = the particle indices ordered by decreasing L_p (equal L_p in any order).
+hipError_t launch_order_by_L(const int32_t *Lp, int P, int Lmax, int32_t *by_L, hipStream_t s);
 
 size_t assemble_bf16_smem_bytes(int Lmax, int Rmax);
 hipError_t launch_assemble_bf16(const AsmBArgs &a, int P, int Lmax, int Rmax, hipStream_t s);

@@ -122,3 +122,45 @@ def test_march_near_pole_candidates_independent_of_grouping(M):
             assert torch.equal(x, y), nc
     assert torch.isfinite(out[1][0]).all()
     c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_uneven_graph_and_assembly_order(M, ctx, prec):
+    """Mixed band limits: the assembly covers each degree's rows only for particles with L_p >= l,
+    in an order it computes on the device.  The graph (its own order buffer) must replay the
+    eager results, and the assembled C must not depend on the particles' order in the batch."""
+    wl = S.WORKLOADS["uneven_L24to48"]
+    b = S.make_workload("uneven_L24to48", n_particles=40)
+    batch, f, h, w = upload(M, b)
+    p = M.BF16_FP32ACC if prec == "bf16" else M.FP32
+    if prec == "bf16":
+        f, h = f.to(torch.bfloat16), h.to(torch.bfloat16)
+    C0 = M.coeff_assemble(ctx, batch, f, h, w, prec=p)
+    cand, st = M.soft_search(ctx, batch, C0, wl.B, wl.n_grid, wl.Kc)
+    best, bi, st = M.march_newton(ctx, batch, C0, wl.levels, wl.steps, cand, st, fp64_above=40)
+    torch.cuda.synchronize()
+    ref = (best.clone(), bi.clone(), st.clone())
+    g = M.AlignGraph(ctx, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, prec=p, fp64_above=40)
+    for rep in range(2):
+        M.coeff_assemble(ctx, batch, f, h, w, prec=p)  # eager work on the context's own order buffer
+        got = g.launch()
+        torch.cuda.synchronize()
+        for x, y in zip(got, ref):
+            assert torch.equal(x, y), rep
+    g.close()
+    # the same particles in reverse order: each particle's C is unchanged bit for bit
+    C = M.coeff_assemble(ctx, batch, f, h, w, prec=p).cpu().numpy()
+    rev = np.arange(b.n_particles)[::-1].copy()
+    sizes = [b.f(q).size for q in rev]
+    br = S.Batch(L_h=b.L_h, R_h=b.R_h, h=b.h, w=b.w, L=b.L[rev].copy(), R=b.R[rev].copy(),
+                 f_offset=np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64),
+                 f_flat=np.concatenate([b.f(q).reshape(-1) for q in rev]), euler_true=b.euler_true[rev],
+                 snr=np.asarray(b.snr)[rev])
+    batch_r, fr, _, _ = upload(M, br)
+    if prec == "bf16":
+        fr = fr.to(torch.bfloat16)
+    Cr = M.coeff_assemble(ctx, batch_r, fr, h, w, prec=p).cpu().numpy()
+    for i, q in enumerate(rev):
+        n = 2 * M.c_elems(int(b.L[q]))
+        o, orv = 2 * int(batch.C_offset[q]), 2 * int(batch_r.C_offset[i])
+        assert np.array_equal(C[o: o + n], Cr[orv: orv + n]), q

@@ -9,18 +9,26 @@
 // One workgroup per particle walks the degrees l = 0..L_p.  The wedge recurrences (one per
 // pair, normalised as in the march) advance one degree at a time in registers and write the
 // full d^l matrix into LDS through d_mn = (-1)^{m-n} d_nm = d_{-n,-m}; the d tables are
-// recomputed here, never stored.  The products with d run over shell chunks staged in LDS.
+// recomputed here, never stored.  The products with d run over shell chunks staged in LDS, on
+// the matrix cores: per degree and chunk of 16 shells, grad_f is the real product d . Hs^T and
+// the grad_h term d^T . Fs^T (v_mfma_f32_16x16x4_f32; lane i supplies A[i%16][i/16] and
+// B[i/16][i%16] of a 16 x 4 x 16 step and holds D rows 4(i/16) .. +3 of column i%16), with the
+// real and imaginary parts of the staged arrays as two B operands.
 // The particle's grad_h term goes to a workspace laid out like f; a second kernel sums the
 // particles in index order (no floating-point atomics, so the result is deterministic).
 #include "matcha_launch.hpp"
 
 namespace matcha {
 
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kAdjThreads = 256;
 constexpr int kAdjPairsPerThread = (65 * 65 + kAdjThreads - 1) / kAdjThreads;  // L <= 64
 constexpr int kAdjShellChunk = 16;
 
-__global__ void __launch_bounds__(kAdjThreads) k_grad_particle(GradArgs a)
+// 4 waves per SIMD (at most 128 registers): with one workgroup per particle, 4 workgroups per CU
+// take 1024 particles in one round.
+__global__ void __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) k_grad_particle(GradArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int p = blockIdx.x;
@@ -59,10 +67,12 @@ __global__ void __launch_bounds__(kAdjThreads) k_grad_particle(GradArgs a)
         // d^l for every wedge pair, then the four symmetric entries of the full matrix
 #pragma unroll
         for (int k = 0; k < kAdjPairsPerThread; ++k) {
-            const int q = threadIdx.x + k * kAdjThreads;
+            if (k * kAdjThreads >= np) break;
+            const int q = threadIdx.x + k * kAdjThreads, qc = min(q, np - 1);
+            // loads at clamped addresses outside the branch, so that they need not wait in turn
+            const PairInfo pi = a.pinfo[qc];
+            const float4 tb = a.tab[row + qc];
             if (q < np) {
-                const PairInfo pi = a.pinfo[q];
-                const float4 tb = a.tab[row + q];
                 float dn;
                 if (pi.m == l) {
                     float s1, s2;
@@ -95,52 +105,42 @@ __global__ void __launch_bounds__(kAdjThreads) k_grad_particle(GradArgs a)
                 Fs[t] = cmul(e2, fv);
             }
             __syncthreads();
-            // grad_f: 4 rows m per task;  grad_h term: 4 columns n per task
-            const int nb = (w + 3) / 4;
-            for (int task = threadIdx.x; task < 2 * rc * nb; task += kAdjThreads) {
-                const bool forf = task < rc * nb;
-                const int tt = forf ? task : task - rc * nb;
-                const int r = tt / nb, b0 = 4 * (tt - (tt / nb) * nb);
-                float2 acc[4] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-                if (forf) {
-                    for (int j = 0; j < w; ++j) {
-                        const float2 u = Hs[r * w + j];
-#pragma unroll
-                        for (int x = 0; x < 4; ++x) {
-                            const float d = dm[min(b0 + x, w - 1) * w + j];
-                            acc[x].x = fmaf(d, u.x, acc[x].x);
-                            acc[x].y = fmaf(d, u.y, acc[x].y);
-                        }
-                    }
-                } else {
-                    for (int i = 0; i < w; ++i) {
-                        const float2 u = Fs[r * w + i];
-                        const float *drow = dm + i * w;
-#pragma unroll
-                        for (int x = 0; x < 4; ++x) {
-                            const float d = drow[min(b0 + x, w - 1)];
-                            acc[x].x = fmaf(d, u.x, acc[x].x);
-                            acc[x].y = fmaf(d, u.y, acc[x].y);
-                        }
-                    }
+            // Output tiles of 16 rows (m for grad_f, n for the grad_h term) x 16 shells, one per wave
+            // at a time.  Operands outside the degree (index >= w) or the chunk (shell >= rc) are
+            // read at clamped addresses and zeroed.
+            const int MT = (w + 15) / 16, KS = (w + 3) / 4;
+            const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
+            const int col = lane % 16, kq = lane / 16;
+            for (int task = wave; task < 2 * MT; task += kAdjThreads / kWave) {
+                const bool forf = task < MT;
+                const int t0 = 16 * (forf ? task : task - MT);
+                const int ar = min(t0 + col, w - 1);
+                const bool aok = t0 + col < w, sok = col < rc;
+                const float2 *src = (forf ? Hs : Fs) + min(col, rc - 1) * w;
+                f32x4 gre = {0.f, 0.f, 0.f, 0.f}, gim = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 4
+                for (int ks = 0; ks < KS; ++ks) {
+                    const int k = 4 * ks + kq, kc = min(k, w - 1);
+                    const bool kok = k < w;
+                    // grad_f: A[m][n] = d_mn, B[n][r] = Hs[r][n];  grad_h: A[n][m] = d_mn, B[m][r] = Fs[r][m]
+                    const float av = (aok && kok) ? (forf ? dm[ar * w + kc] : dm[kc * w + ar]) : 0.f;
+                    const float2 bv = src[kc];
+                    const float bm = (sok && kok) ? 1.f : 0.f;
+                    gre = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.x * bm, gre, 0, 0, 0);
+                    gim = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv.y * bm, gim, 0, 0, 0);
                 }
-                const float sc = gp * a.w[r0 + r];
+                if (sok) {
+                    const float sc = gp * a.w[r0 + col];
+                    float2 *dst = forf ? gf : gw;
 #pragma unroll
-                for (int x = 0; x < 4; ++x) {
-                    const int j = b0 + x;
-                    if (j >= w) break;
-                    const int k = j - l;
-                    const int64_t idx = (int64_t)(r0 + r) * sf + l * l + j;
-                    if (forf) {
-                        if (gf) {
-                            const float2 e = k >= 0 ? cconj(ea[k]) : ea[-k];  // e^{-i m a}
-                            const float2 v = cmul(e, acc[x]);
-                            gf[idx] = make_float2(sc * v.x, sc * v.y);
-                        }
-                    } else if (gw) {
-                        const float2 e = k >= 0 ? eg[k] : cconj(eg[-k]);  // e^{i n c}
-                        const float2 v = cmul(e, acc[x]);
-                        gw[idx] = make_float2(sc * v.x, sc * v.y);
+                    for (int v = 0; v < 4; ++v) {
+                        const int j = t0 + 4 * kq + v;
+                        if (j >= w || !dst) continue;
+                        const int k = j - l;
+                        // grad_f: e^{-i m a};  grad_h term: e^{i n c}
+                        const float2 e = forf ? (k >= 0 ? cconj(ea[k]) : ea[-k]) : (k >= 0 ? eg[k] : cconj(eg[-k]));
+                        const float2 val = cmul(e, make_float2(gre[v], gim[v]));
+                        dst[(int64_t)(r0 + col) * sf + l * l + j] = make_float2(sc * val.x, sc * val.y);
                     }
                 }
             }
@@ -160,12 +160,23 @@ __global__ void __launch_bounds__(256) k_grad_reduce(GradArgs a)
     const int lm = (int)(e - (int64_t)r * nl);
     const int l = (int)sqrtf((float)lm + 0.5f);
     float2 s = make_float2(0.f, 0.f);
-    for (int p = 0; p < a.P; ++p) {
-        const int Lp = a.Lp[p], Rp = a.Rp[p];
-        if (r < Rp && l <= Lp) {
-            const float2 v = a.ws[a.f_off[p] + (int64_t)r * (Lp + 1) * (Lp + 1) + lm];
-            s.x += v.x;
-            s.y += v.y;
+    // 16 particles' loads in flight at a time (clamped to a valid address where the particle has
+    // no such term), then added in index order
+    constexpr int U = 16;
+    for (int p0 = 0; p0 < a.P; p0 += U) {
+        float2 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int p = min(p0 + u, a.P - 1);
+            const int Lp = a.Lp[p], Rp = a.Rp[p];
+            const bool ok = p0 + u < a.P && r < Rp && l <= Lp;
+            v[u] = a.ws[ok ? a.f_off[p] + (int64_t)r * (Lp + 1) * (Lp + 1) + lm : 0];
+            if (!ok) v[u] = make_float2(0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            s.x += v[u].x;
+            s.y += v[u].y;
         }
     }
     a.grad_h[e] = s;

@@ -124,8 +124,8 @@ typedef struct {
     double max_step;
     int32_t early_stop;
     double tol_grad, tol_step, tol_rel;
-    int32_t fp64_above;    /* levels above this degree run the Wigner-d recurrence and its l-sums
-                              in FP64 (FP64 coefficient table); 0 or >= MATCHA_MAX_L: FP32 only */
+    int32_t fp64_above;    /* levels above this degree run the Wigner-d recurrence in FP64 (FP64
+                              coefficient table; the l-sums stay FP32); 0 or >= MATCHA_MAX_L: FP32 only */
 } matcha_march_cfg;
 
 /* Launch shapes.  Zero fields mean "library default".  march_nc: candidates per wavefront

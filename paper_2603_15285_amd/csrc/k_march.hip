@@ -74,24 +74,26 @@ template <int NC, bool DERIV, bool SEED, typename T, int FIRST = 0>
 __device__ __forceinline__ void row_step(const T A, const T AC, const float4 tb, const float4 cc, const bool seed,
                                          const T (&S0)[NC], const T (&S1)[NC], const T (&S2)[NC], const T *cbv,
                                          const T *sbv, const T *chv, T (&X)[NC], T (&Y)[NC], T (&X1)[NC],
-                                         T (&Y1)[NC], T (&X2)[NC], T (&Y2)[NC], T (&U)[NC][DERIV ? 12 : 4])
+                                         T (&Y1)[NC], T (&X2)[NC], T (&Y2)[NC], float (&U)[NC][DERIV ? 12 : 4])
 {
-    const T s0r = (T)(cc.x * tb.z), s0i = (T)(cc.y * tb.z), s1r = (T)(cc.z * tb.w), s1i = (T)(cc.w * tb.w);
+    // the l-sums are FP32 in both arithmetics (an FP64 row's values are rounded once before them)
+    const float s0r = cc.x * tb.z, s0i = cc.y * tb.z, s1r = cc.z * tb.w, s1i = cc.w * tb.w;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const T u = fma(A, cbv[c], -AC);
         T dn = FIRST == 1 ? (T)0 : FIRST == 2 ? u * X[c] : fma(u, X[c], -Y[c]);
         if (SEED) dn = seed ? S0[c] : dn;
+        const float df = (float)dn;
         if (FIRST == 1) {
-            U[c][0] = s0r * dn;
-            U[c][1] = s0i * dn;
-            U[c][2] = s1r * dn;
-            U[c][3] = s1i * dn;
+            U[c][0] = s0r * df;
+            U[c][1] = s0i * df;
+            U[c][2] = s1r * df;
+            U[c][3] = s1i * df;
         } else {
-            U[c][0] = fma(s0r, dn, U[c][0]);
-            U[c][1] = fma(s0i, dn, U[c][1]);
-            U[c][2] = fma(s1r, dn, U[c][2]);
-            U[c][3] = fma(s1i, dn, U[c][3]);
+            U[c][0] = fmaf(s0r, df, U[c][0]);
+            U[c][1] = fmaf(s0i, df, U[c][1]);
+            U[c][2] = fmaf(s1r, df, U[c][2]);
+            U[c][3] = fmaf(s1i, df, U[c][3]);
         }
         if (DERIV) {
             T d1n, d2n;
@@ -109,24 +111,25 @@ __device__ __forceinline__ void row_step(const T A, const T AC, const float4 tb,
             }
             Y1[c] = d1n;
             Y2[c] = d2n;
+            const float d1f = (float)d1n, d2f = (float)d2n;
             if (FIRST == 1) {
-                U[c][4] = s0r * d1n;
-                U[c][5] = s0i * d1n;
-                U[c][6] = s1r * d1n;
-                U[c][7] = s1i * d1n;
-                U[c][8] = s0r * d2n;
-                U[c][9] = s0i * d2n;
-                U[c][10] = s1r * d2n;
-                U[c][11] = s1i * d2n;
+                U[c][4] = s0r * d1f;
+                U[c][5] = s0i * d1f;
+                U[c][6] = s1r * d1f;
+                U[c][7] = s1i * d1f;
+                U[c][8] = s0r * d2f;
+                U[c][9] = s0i * d2f;
+                U[c][10] = s1r * d2f;
+                U[c][11] = s1i * d2f;
             } else {
-                U[c][4] = fma(s0r, d1n, U[c][4]);
-                U[c][5] = fma(s0i, d1n, U[c][5]);
-                U[c][6] = fma(s1r, d1n, U[c][6]);
-                U[c][7] = fma(s1i, d1n, U[c][7]);
-                U[c][8] = fma(s0r, d2n, U[c][8]);
-                U[c][9] = fma(s0i, d2n, U[c][9]);
-                U[c][10] = fma(s1r, d2n, U[c][10]);
-                U[c][11] = fma(s1i, d2n, U[c][11]);
+                U[c][4] = fmaf(s0r, d1f, U[c][4]);
+                U[c][5] = fmaf(s0i, d1f, U[c][5]);
+                U[c][6] = fmaf(s1r, d1f, U[c][6]);
+                U[c][7] = fmaf(s1i, d1f, U[c][7]);
+                U[c][8] = fmaf(s0r, d2f, U[c][8]);
+                U[c][9] = fmaf(s0i, d2f, U[c][9]);
+                U[c][10] = fmaf(s1r, d2f, U[c][10]);
+                U[c][11] = fmaf(s1i, d2f, U[c][11]);
             }
         }
         Y[c] = dn;
@@ -195,7 +198,7 @@ __device__ inline double bcastT<double>(double x)
 // Sum over all wedge pairs of one level for the NC candidates c0 .. c0+NC-1 of a wave that owns
 // NCW.  acc[c0+c][0..9] receive the (positive-sign, undoubled) sums described at the top of the
 // file, the b-b sum (7) from D''/2, i.e. halved; with DERIV == false only acc[.][0] (the value)
-// is formed.  T is the arithmetic of the recurrence and the l-sums.
+// is formed.  T is the arithmetic of the recurrence; the l-sums are FP32.
 template <int NC, int NCW, bool DERIV, typename T>
 __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restrict__ tab,
                            const double2 *__restrict__ tab64, const PairInfo *__restrict__ pinfo, int L,
@@ -252,7 +255,7 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         }
         // the state before row mlo is zero: the first two rows take it as such (row_step FIRST)
         T D[NC], Dm[NC], D1[NC], D1m[NC], D2[NC], D2m[NC];
-        T U[NC][NU];
+        float U[NC][NU];
 #define MARCH_ROW0(SEEDROW, FST)                                                                         \
     row_step<NC, DERIV, SEEDROW, T, FST>(A0, AC0, tb0, cc0, m == l, sd0, sd1, sd2, cbv, sbv, chv, D, Dm, D1, D1m, D2, \
                                          D2m, U)
@@ -346,7 +349,7 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
 }
 
 // A whole level for the wave's NC candidates: FP32 recurrence at or below the FP64 threshold,
-// FP64 recurrence (two candidates per pass, to bound registers) above it.
+// FP64 recurrence (up to four candidates per pass, to bound registers) above it.
 template <int NC, bool DERIV>
 __device__ void eval_level_any(const float4 *Cp, const float4 *tab, const double2 *tab64, const PairInfo *pinfo,
                                int L, int fp64_above, const BetaConst *bc, const WaveScratch<NC> &ws,
@@ -355,7 +358,7 @@ __device__ void eval_level_any(const float4 *Cp, const float4 *tab, const double
     if (L <= fp64_above || tab64 == nullptr) {
         eval_level<NC, NC, DERIV, float>(Cp, tab, tab64, pinfo, L, bc, ws, acc, 0, lane);
     } else {
-        constexpr int H = NC < 2 ? NC : 2;
+        constexpr int H = NC < 4 ? NC : 4;
 #pragma unroll
         for (int c0 = 0; c0 < NC; c0 += H) eval_level<H, NC, DERIV, double>(Cp, tab, tab64, pinfo, L, bc, ws, acc, c0, lane);
     }

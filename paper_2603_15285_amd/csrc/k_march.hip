@@ -349,13 +349,15 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
 }
 
 // A whole level for the wave's NC candidates: FP32 recurrence at or below the FP64 threshold,
-// FP64 recurrence (up to four candidates per pass, to bound registers) above it.
-template <int NC, bool DERIV>
+// FP64 recurrence (up to four candidates per pass, to bound registers) above it.  F64 = false
+// builds the FP32 recurrence only, for launches with no level above the threshold (the FP64
+// path's registers would otherwise bound the whole kernel).
+template <int NC, bool DERIV, bool F64>
 __device__ void eval_level_any(const float4 *Cp, const float4 *tab, const double2 *tab64, const PairInfo *pinfo,
                                int L, int fp64_above, const BetaConst *bc, const WaveScratch<NC> &ws,
                                float (&acc)[NC][10], int lane)
 {
-    if (L <= fp64_above || tab64 == nullptr) {
+    if (!F64 || L <= fp64_above || tab64 == nullptr) {
         eval_level<NC, NC, DERIV, float>(Cp, tab, tab64, pinfo, L, bc, ws, acc, 0, lane);
     } else {
         constexpr int H = NC < 4 ? NC : 4;
@@ -490,7 +492,7 @@ __device__ __forceinline__ void prepare_step(WaveState<NC> &st, WaveScratch<NC> 
     wave_sync();
 }
 
-template <int NC>
+template <int NC, bool F64>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) k_march(MarchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -526,7 +528,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
         if (lane < NC) st.frozen[lane] = 0;
         for (int s = 0; s < a.steps; ++s) {
             prepare_step<NC, true>(st, ws, L, lane);
-            eval_level_any<NC, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
+            eval_level_any<NC, true, F64>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
             wave_reduce<NC, 10>(acc, st, lane);
             if (lane < NC && !st.frozen[lane]) {
                 double e[10];
@@ -566,7 +568,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
     // value at the final points on the last level, then selection
     prepare_step<NC, true>(st, ws, Lp, lane);
-    eval_level_any<NC, false>(Cp, a.tab, a.tab64, a.pinfo, Lp, a.fp64_above, st.bc, ws, acc, lane);
+    eval_level_any<NC, false, F64>(Cp, a.tab, a.tab64, a.pinfo, Lp, a.fp64_above, st.bc, ws, acc, lane);
     wave_reduce<NC, 1>(acc, st, lane);
     if (lane < NC) {
         const int k = wave * NC + lane;
@@ -609,7 +611,7 @@ __global__ void __launch_bounds__(64) k_evaluate(EvalArgs a)
     __syncthreads();
     prepare_step<1, false>(st, ws, L, lane);
     float acc[1][10];
-    eval_level_any<1, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
+    eval_level_any<1, true, true>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
     wave_reduce<1, 10>(acc, st, lane);
     if (lane < 10) {
         // signs and factors of the 10 sums; the b-b sum is accumulated from D''/2
@@ -625,21 +627,24 @@ size_t march_smem_bytes(int G)
 }
 
 template <int NC>
-hipError_t launch_march(const MarchArgs &a, int P, hipStream_t s)
+hipError_t launch_march(const MarchArgs &a, int P, bool f64, hipStream_t s)
 {
     const int G = (a.Kc + NC - 1) / NC;
     const size_t sm = march_smem_bytes<NC>(G);
-    hipLaunchKernelGGL(k_march<NC>, dim3(P), dim3(G * kWave), sm, s, a);
+    if (f64)
+        hipLaunchKernelGGL((k_march<NC, true>), dim3(P), dim3(G * kWave), sm, s, a);
+    else
+        hipLaunchKernelGGL((k_march<NC, false>), dim3(P), dim3(G * kWave), sm, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_march_any(const MarchArgs &a, int P, int nc, hipStream_t s)
+hipError_t launch_march_any(const MarchArgs &a, int P, int nc, bool f64, hipStream_t s)
 {
     switch (nc) {
-    case 1: return launch_march<1>(a, P, s);
-    case 2: return launch_march<2>(a, P, s);
-    case 4: return launch_march<4>(a, P, s);
-    case 8: return launch_march<8>(a, P, s);
+    case 1: return launch_march<1>(a, P, f64, s);
+    case 2: return launch_march<2>(a, P, f64, s);
+    case 4: return launch_march<4>(a, P, f64, s);
+    case 8: return launch_march<8>(a, P, f64, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -621,7 +621,8 @@ matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, co
     a.status = status;
     a.order = batch->order;
     const int nc = march_nc(ctx, Kc);
-    return launched(launch_march_any(a, batch->n_particles, nc, static_cast<hipStream_t>(stream)));
+    const bool f64 = a.fp64_above < hi;  // a level above the threshold: some particle's L_p
+    return launched(launch_march_any(a, batch->n_particles, nc, f64, static_cast<hipStream_t>(stream)));
 }
 
 matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const float *C, int32_t L_eval,

@@ -124,7 +124,8 @@ hipError_t launch_soft_grid(const SoftArgs &a, int P, hipStream_t s);
 hipError_t launch_soft_select(const SoftArgs &a, int P, int threads, hipStream_t s);
 
 size_t march_smem_any(int Kc, int nc);
-hipError_t launch_march_any(const MarchArgs &a, int P, int nc, hipStream_t s);
+// f64: some level of the batch lies above the FP64 threshold (otherwise the FP32-only kernel runs).
+hipError_t launch_march_any(const MarchArgs &a, int P, int nc, bool f64, hipStream_t s);
 hipError_t launch_evaluate(const EvalArgs &a, int P, hipStream_t s);
 
 size_t grad_smem_bytes(int Lmax);

@@ -1,4 +1,5 @@
-"""Host-side logic of libmatcha that needs no GPU: longest-first ordering and workspace sizing."""
+"""Host-side logic that needs no GPU: longest-first ordering, workspace sizing and the bench's
+use of the recorded march traffic."""
 import ctypes as ct
 
 import numpy as np
@@ -60,3 +61,23 @@ def test_workspace_is_one_template_term_per_particle():
     b, keep = host_batch(L, R, 32, 32)
     n = M.lib().matcha_workspace_size(ct.byref(b), 16)
     assert n == 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
+
+
+def test_march_traffic_reported_only_for_its_workload_and_sources(tmp_path, monkeypatch):
+    """The bench's HBM-traffic figure comes from a counter summary; it is used only while the
+    summary names the timed workload and the march sources still hash to the recorded digest."""
+    import bench
+
+    def summary(workload, digest, nbytes):
+        p = tmp_path / f"traffic_{workload}_{digest[:8]}.txt"
+        p.write_text(f"workload: {workload}\nkernel_source_sha256: {digest}\nhbm_bytes_per_launch: {nbytes}\n")
+        return str(p)
+
+    digest = bench.march_source_digest()
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", summary("L32_R32_B12_K16", digest, 123456))
+    assert bench.measured_march_traffic("L32_R32_B12_K16") == 123456.0
+    assert bench.measured_march_traffic("uneven_L24to48") is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", summary("L32_R32_B12_K16", "0" * 64, 123456))
+    assert bench.measured_march_traffic("L32_R32_B12_K16") is None
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.txt"))
+    assert bench.measured_march_traffic("L32_R32_B12_K16") is None

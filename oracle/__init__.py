@@ -22,6 +22,23 @@ _i64p = ct.POINTER(ct.c_int64)
 _up = ct.POINTER(ct.c_uint)
 
 
+def use_native():
+    """Rebuilds the oracle with -march=native on this host and loads that build (for CPU timing)."""
+    global _lib, _LIB_PATH
+    from . import build as _b
+    _LIB_PATH = _b.build(native=True)
+    _lib = None
+    return lib()
+
+
+def set_num_threads(n: int):
+    lib().mo_set_num_threads(int(n))
+
+
+def max_threads() -> int:
+    return int(lib().mo_max_threads())
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -29,6 +46,8 @@ def lib():
             from . import build as _b
             _b.build()
         L = ct.CDLL(_LIB_PATH)
+        L.mo_set_num_threads.argtypes = [ct.c_int]
+        L.mo_max_threads.restype = ct.c_int
         L.mo_term_count.restype = ct.c_long
         L.mo_term_count.argtypes = [ct.c_int]
         L.mo_wigner_d.argtypes = [ct.c_int, ct.c_double, _dp, _dp, _dp]

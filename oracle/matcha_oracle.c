@@ -24,6 +24,7 @@
  */
 #include <complex.h>
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -44,6 +45,10 @@ static long mo_lm(int l, int m) { return (long)l * l + l + m; }
 static long mo_at(int l, int m, int n) { return mo_blk(l) + (long)(m + l) * (2 * l + 1) + (n + l); }
 
 long mo_term_count(int L) { return mo_nterms(L); }
+
+/* Thread count of the OpenMP loops over particles and grid slices (timing plumbing only). */
+void mo_set_num_threads(int n) { omp_set_num_threads(n); }
+int mo_max_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ Wigner d
  * d^l_mn(b) on its "edge" l = max(|m|, |n|): the explicit finite sum of App. A.4

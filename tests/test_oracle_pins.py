@@ -527,3 +527,124 @@ def test_oracle_matches_its_golden_fixture():
         best, bi, st, _ = O.align_one(b.f(p), 6, 4, b.h, 6, b.w, fx["B"], fx["n"], fx["Kc"], fx["levels"], fx["steps"])
         assert bi == ref["best_idx"] and st == ref["status"]
         assert np.allclose(best, ref["best"], rtol=1e-10, atol=1e-12)
+
+
+# ------------------------------------------------------------- early stopping
+def _perturbed(Rt, deg, seed):
+    """Euler angles of Rt turned by `deg` degrees about a random axis."""
+    rng = np.random.default_rng(seed)
+    ax = rng.standard_normal(3)
+    ax /= np.linalg.norm(ax)
+    ang = math.radians(deg)
+    K = np.array([[0, -ax[2], ax[1]], [ax[2], 0, -ax[0]], [-ax[1], ax[0], 0]])
+    return S.matrix_to_euler_zyz((np.eye(3) + math.sin(ang) * K + (1 - math.cos(ang)) * K @ K) @ Rt)
+
+
+def _expected_level(Lj, C, th0, steps, tol_grad, tol_step, tol_rel):
+    """One level of the march with the Sec. 2.4 stopping rules, taken from the fixed-step
+    trajectory: before step t the level stops if |grad F(th_t)| <= tol_grad |F(th_t)| or (t > 0)
+    |F(th_t) - F(th_{t-1})| <= tol_rel |F(th_t)|; after step t it stops if the step's largest
+    component is <= tol_step.  The trajectory comes from the oracle's Newton step (pinned above)
+    and the fixed-step march; the stopping decisions are made here.  Returns (theta, stopped)."""
+    th = np.array(th0[:3], dtype=np.float64)
+    Fprev = None
+    for t in range(steps):
+        e = O.evaluate(Lj, C, th)
+        gn = float(np.linalg.norm(e[1:4]))
+        if gn <= tol_grad * abs(e[0]) or (t > 0 and abs(e[0] - Fprev) <= tol_rel * abs(e[0])):
+            return th, True
+        Fprev = e[0]
+        th, _, sinf = O.newton_step(e, th)
+        # the same point as the oracle's own fixed-step march after t + 1 steps
+        cf, _, _ = O.march(Lj, C, [], t + 1, np.r_[th0[:3], 0.0][None])
+        assert np.array_equal(cf[0, :3], th)
+        if sinf <= tol_step:
+            return th, True
+    return th, False
+
+
+def _trajectory(Lj, C, th0, steps):
+    """(|grad|/|F|, |dF|/|F|, step) along the fixed-step trajectory at band Lj."""
+    th = np.array(th0[:3], dtype=np.float64)
+    g, r, s = [], [], []
+    Fprev = None
+    for t in range(steps):
+        e = O.evaluate(Lj, C, th)
+        g.append(float(np.linalg.norm(e[1:4])) / abs(e[0]))
+        r.append(abs(e[0] - Fprev) / abs(e[0]) if t > 0 else np.inf)
+        Fprev = e[0]
+        th, _, sinf = O.newton_step(e, th)
+        s.append(sinf)
+    return np.array(g), np.array(r), np.array(s)
+
+
+@pytest.mark.parametrize("which", ["grad", "rel", "step"])
+def test_early_stop_each_criterion_truncates_the_fixed_march(which):
+    """Each Sec. 2.4 criterion alone (the other tolerances 0, which never fire on a moving
+    candidate) stops a level exactly where the criterion first holds on the fixed-step
+    trajectory, with the EARLY_STOP flag; the thresholds sit in the middle of a gap of the
+    trajectory's sequence, so the expected stopping step is unambiguous."""
+    L, R, steps = 10, 6, 6
+    b = S.make_batch(L, R, 1, seed=61, noiseless=True)
+    C = O.coeff_assemble(L, R, b.f(0), L, b.h, L, b.w)
+    th0 = _perturbed(b.R_true()[0], 4.0, 3)
+    g, r, s = _trajectory(L, C, th0, steps)
+    seq = {"grad": g, "rel": r, "step": s}[which]
+    # threshold between the 2nd and 3rd entries of the sequence (geometric mean), so the level
+    # stops at the third check; the sequence must fall by at least 100x there
+    k = 2 if which != "rel" else 3
+    assert seq[k - 1] > 100 * seq[k], seq
+    tol = math.sqrt(seq[k - 1] * seq[k])
+    tols = dict(tol_grad=0.0, tol_step=0.0, tol_rel=0.0)
+    tols["tol_" + which] = tol
+    start = np.r_[th0, 0.0][None]
+    got, _, cst = O.march(L, C, [], steps, start, early_stop=True, **tols)
+    exp, stopped = _expected_level(L, C, th0, steps, **tols)
+    assert stopped
+    assert bool(cst[0] & O.EARLY_STOP)
+    assert np.array_equal(got[0, :3], exp)
+    # with zero tolerances a level can only stop once the candidate no longer moves at all (an
+    # exactly zero step or change of F), so the result is the fixed-step one; before convergence
+    # (two steps) it is not flagged
+    full, _, _ = O.march(L, C, [], steps, start, early_stop=True, tol_grad=0.0, tol_step=0.0, tol_rel=0.0)
+    ref, _, _ = O.march(L, C, [], steps, start)
+    assert np.array_equal(full[0, :3], ref[0, :3])
+    _, _, cst2 = O.march(L, C, [], 2, start, early_stop=True, tol_grad=0.0, tol_step=0.0, tol_rel=0.0)
+    assert not cst2[0] & O.EARLY_STOP
+
+
+def test_early_stop_restarts_at_every_level():
+    """Two levels: the second level's stepping starts afresh (no relative-change test at its first
+    step) from where the first stopped."""
+    L, R, steps = 10, 6, 5
+    b = S.make_batch(L, R, 1, seed=62, noiseless=True)
+    C = O.coeff_assemble(L, R, b.f(0), L, b.h, L, b.w)
+    th0 = _perturbed(b.R_true()[0], 3.0, 4)
+    tols = dict(tol_grad=1e-6, tol_step=1e-9, tol_rel=1e-12)
+    th_a, s_a = _expected_level(6, C, th0, steps, **tols)
+    th_b, s_b = _expected_level(L, C, th_a, steps, **tols)
+    got, _, cst = O.march(L, C, [6], steps, np.r_[th0, 0.0][None], early_stop=True, **tols)
+    assert s_a or s_b
+    assert bool(cst[0] & O.EARLY_STOP) == (s_a or s_b)
+    assert np.array_equal(got[0, :3], th_b)
+
+
+def test_early_stop_noiseless_agrees_with_fixed_steps():
+    """With the default FP64 tolerances a noiseless particle stops early, and its rotation is the
+    fixed-step result (the true rotation) to 1e-8 degrees: a level stops once |grad F| <= 1e-9 |F|
+    or |dF| <= 1e-13 |F|, which leaves at most about 1e-9 degrees to the quadratically converging
+    steps it skips (measured: up to 1.2e-9 degrees from a 4-degree start)."""
+    wl_levels, steps = [8, 12, 16], 6
+    b = S.make_batch(16, 8, 3, seed=63, noiseless=True)
+    for p in range(3):
+        C = O.coeff_assemble(16, 8, b.f(p), 16, b.h, 16, b.w)
+        start = np.array([np.r_[_perturbed(b.R_true()[p], d, 10 + p), 0.0] for d in (1.0, 2.5, 4.0)])
+        es, bi_e, cst = O.march(16, C, wl_levels, steps, start, early_stop=True)
+        fx, bi_f, _ = O.march(16, C, wl_levels, steps, start)
+        assert np.all(cst & O.EARLY_STOP)
+        # all three reach the same maximum, so the selection is a near-tie: only its value is unique
+        assert abs(es[bi_e, 3] - fx[bi_f, 3]) <= 1e-12 * abs(fx[bi_f, 3])
+        err = S.geodesic_deg(S.euler_zyz_to_matrix(es[:, 0], es[:, 1], es[:, 2]),
+                             S.euler_zyz_to_matrix(fx[:, 0], fx[:, 1], fx[:, 2]))
+        assert np.all(err < 1e-8), err
+        assert np.all(S.geodesic_deg(b.R_true()[p], S.euler_zyz_to_matrix(es[:, 0], es[:, 1], es[:, 2])) < 1e-8)

@@ -18,8 +18,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "particles/sec rotationally refined at L=32, batched vs plain; % of roofline"
-# FP32 VALU peak without packed-FP32 instructions: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2.4 GHz
-VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+# MI355X's published FP32 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 flop (FMA) x 2 (packed FP32)
+# x 2.4 GHz.  This build issues no packed FP32 instructions, so its own ceiling is half of that.
+VALU_FP32_PEAK_TFLOPS = 157.3
+VALU_FP32_NONPACKED_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
 
 
 def wedge_terms(L):
@@ -103,7 +105,7 @@ def pmc_probe(args):
     wl = S.WORKLOADS[args.workload]
     b = S.make_workload(args.workload, n_particles=args.particles)
     ctx = M.Context(0)
-    ctx.prepare(int(b.L.max()), wl.B, wl.n_grid)
+    ctx.prepare(wl.B, wl.n_grid)
     batch = M.Batch.make(b.L, b.R, b.L_h, b.R_h, f_offset=b.f_offset)
     f = torch.from_numpy(b.f_flat.astype(np.complex64).view(np.float32)).cuda()
     h = torch.from_numpy(b.h.astype(np.complex64).view(np.float32).reshape(-1)).cuda()
@@ -144,21 +146,74 @@ def soft_work(B, n):
     return byts, flops
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(b, wl, budget_s=15.0):
+    """The FP64 oracle's whole path (built -O3 -march=native on this host) on an evenly spread
+    sample of the batch: OpenMP over particles on every available core, and one core on a few
+    particles.  Returns (report, sample, oracle best, oracle candidates)."""
     import oracle as O
+    O.use_native()
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     threads = max(1, min(threads, os.cpu_count() or 1))
+    O.set_num_threads(1)
+    n1 = 2
     t0 = time.time()
-    O.align_batch(b, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps, particles=[0])
-    t1 = time.time() - t0
+    O.align_batch(b, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps, particles=[0, b.n_particles - 1][:n1])
+    t1 = (time.time() - t0) / n1
+    O.set_num_threads(threads)
     n = int(max(threads, min(b.n_particles, round(budget_s / max(t1, 1e-3) * threads))))
     sample = np.linspace(0, b.n_particles - 1, n).astype(int)
     t0 = time.time()
-    O.align_batch(b, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps, particles=sample)
+    ob, obi, ost, ocand = O.align_batch(b, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps, particles=sample)
     dt = time.time() - t0
-    return {"value": n / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} particles of the same workload spread over the batch, whole path "
-                      f"(assembly, SOFFT, march, selection) in FP64, OpenMP over particles, {dt:.1f} s"}
+    rep = {"value": n / dt, "unit": "particles/s", "cores": threads, "kind": "oracle",
+           "single_core": {"value": 1.0 / t1, "unit": "particles/s", "particles": n1},
+           "cpu": cpu_model(),
+           "sample": f"{n} particles of the same workload spread over the batch, whole path "
+                     f"(assembly, SOFFT, march, selection) in FP64, OpenMP over particles, {dt:.1f} s"}
+    return rep, sample, ob, ocand
+
+
+def norm_bound(b, p):
+    """S = |f_p|_w |h|_w over the particle's shells and degrees: the Cauchy-Schwarz bound on |C_L|."""
+    Lp, Rp = int(b.L[p]), int(b.R[p])
+    f = b.f(p)
+    hh = b.h[:Rp, : (Lp + 1) ** 2]
+    w = b.w[:Rp, None]
+    return math.sqrt(float(np.sum(w * np.abs(f) ** 2))) * math.sqrt(float(np.sum(w * np.abs(hh) ** 2)))
+
+
+def errors_vs_oracle(S_mod, b, sample, ob, ocand, best):
+    """Rotation (degrees, geodesic) and objective (|dF| / S) errors of GPU results against the FP64
+    oracle on the sampled particles.  Particles whose two best oracle candidates lie within 1e-5 S of
+    each other are skipped: either basin is a correct selection."""
+    rot, obj = [], []
+    skipped = 0
+    for t, p in enumerate(sample):
+        Sb = norm_bound(b, p)
+        top = np.sort(ocand[t, :, 3])[::-1]
+        if top.size > 1 and top[0] - top[1] <= 1e-5 * Sb:
+            skipped += 1
+            continue
+        g = best[p].astype(np.float64)
+        rot.append(float(S_mod.geodesic_deg(S_mod.euler_zyz_to_matrix(g[0], g[1], g[2]),
+                                            S_mod.euler_zyz_to_matrix(ob[t, 0], ob[t, 1], ob[t, 2]))))
+        obj.append(abs(g[3] - ob[t, 3]) / Sb)
+    rot, obj = np.asarray(rot), np.asarray(obj)
+    return {"rot_err_vs_oracle_deg": {"max": float(rot.max()), "p90": float(np.percentile(rot, 90)),
+                                      "median": float(np.median(rot))},
+            "obj_err_vs_oracle_rel_S": {"max": float(obj.max()), "p90": float(np.percentile(obj, 90))},
+            "compared": int(rot.size), "near_ties_skipped": skipped}
 
 
 def main():
@@ -195,7 +250,7 @@ def main():
     log(f"generated {b.n_particles} particles in {time.time() - t0:.1f} s")
     P = b.n_particles
     ctx = M.Context(0)
-    ctx.prepare(int(b.L.max()), wl.B, wl.n_grid)
+    ctx.prepare(wl.B, wl.n_grid)
     batch = M.Batch.make(b.L, b.R, b.L_h, b.R_h, f_offset=b.f_offset)
     f = torch.from_numpy(b.f_flat.astype(np.complex64).view(np.float32)).cuda()
     h = torch.from_numpy(b.h.astype(np.complex64).view(np.float32).reshape(-1)).cuda()
@@ -275,25 +330,36 @@ def main():
     log(f"plain: {plain_value:.0f} particles/s over {n_plain} particles")
     ctx.set_tuning(plain_tuning["march_nc"], plain_tuning["soft_threads"])
 
-    # batched with BF16 coefficients on the matrix cores (FP32 accumulation, FP32 march)
+    # batched with BF16 coefficients on the matrix cores (FP32 accumulation) for the search and the
+    # lower levels, and each particle's final level on FP32-assembled coefficients (FP32 march)
     f16 = f.to(torch.bfloat16)
     h16 = h.to(torch.bfloat16)
+
+    def time_graph(g):
+        g.launch()
+        torch.cuda.synchronize()
+        q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        q0.record(stream)
+        for k in range(args.steps):
+            g.launch()
+        q1.record(stream)
+        torch.cuda.synchronize()
+        return P / (q0.elapsed_time(q1) / args.steps / 1e3), g.bufs["best"].cpu().numpy().astype(np.float64)
+
     g16 = M.AlignGraph(ctx, batch, f16, h16, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, prec=M.BF16_FP32ACC,
-                       fp64_above=fp64_above)
-    g16.launch()
-    torch.cuda.synchronize()
-    q0, q1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    q0.record(stream)
-    for k in range(args.steps):
-        g16.launch()
-    q1.record(stream)
-    torch.cuda.synchronize()
-    bf16_value = P / (q0.elapsed_time(q1) / args.steps / 1e3)
-    b16 = g16.bufs["best"].cpu().numpy().astype(np.float64)
+                       fp64_above=fp64_above, f32=f, h32=h)
+    bf16_value, b16 = time_graph(g16)
+    g16.close()
+    del g16
+    g16o = M.AlignGraph(ctx, batch, f16, h16, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, prec=M.BF16_FP32ACC,
+                        fp64_above=fp64_above)
+    bf16o_value, b16o = time_graph(g16o)
+    g16o.close()
+    del g16o
     err16 = S.geodesic_deg(b.R_true(), S.euler_zyz_to_matrix(b16[:, 0], b16[:, 1], b16[:, 2]))
     d16 = S.geodesic_deg(S.euler_zyz_to_matrix(best[:, 0], best[:, 1], best[:, 2]),
                          S.euler_zyz_to_matrix(b16[:, 0], b16[:, 1], b16[:, 2]))
-    log(f"batched bf16: {bf16_value:.0f} particles/s")
+    log(f"batched bf16 (FP32 final level): {bf16_value:.0f} particles/s; BF16 throughout: {bf16o_value:.0f}")
 
     flops = sum(march_flops_per_particle(wl.levels, int(Lp), wl.steps, wl.Kc) for Lp in b.L)
     traffic = measured_march_traffic(wl.name) if args.particles is None else None
@@ -325,10 +391,14 @@ def main():
         "roofline": {"kernel": "k_march (frequency march: value, gradient, Hessian, Newton, selection)",
                      "bound": "alu", "achieved": achieved, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / VALU_FP32_PEAK_TFLOPS, "traffic": traffic, "traffic_unit": "bytes/launch",
-                     "ms_per_launch": ms_march},
+                     "ms_per_launch": ms_march,
+                     "peak_without_packed_fp32": VALU_FP32_NONPACKED_TFLOPS,
+                     "frac_without_packed_fp32": achieved / VALU_FP32_NONPACKED_TFLOPS},
         "plain": {"value": plain_value, "unit": "particles/s", "particles": n_plain},
         "batched_over_plain": value / plain_value,
         "batched_bf16": {"value": bf16_value, "unit": "particles/s", "over_plain": bf16_value / plain_value,
+                         "scheme": ("BF16 f, h on the matrix cores (FP32 accumulation) for the search and the lower "
+                                    "levels; FP32 assembly for each particle's final level; FP32 march"),
                          "rot_diff_vs_fp32_deg": {"median": float(np.median(d16)), "p99": float(np.percentile(d16, 99)),
                                                   "n_over_0.05": int(np.sum(d16 > 0.05))},
                          "rot_err_vs_truth_deg": {"median": float(np.median(err16)), "p90": float(np.percentile(err16, 90))}},
@@ -337,9 +407,17 @@ def main():
         "rot_err_vs_truth_deg": {"median": float(np.median(err)), "p90": float(np.percentile(err, 90)),
                                  "max": float(err.max())},
     }
+    out["batched_bf16"]["without_fp32_final_level"] = {"value": bf16o_value, "unit": "particles/s"}
     if not args.no_cpu:
         log("cpu baseline ...")
-        out["cpu_baseline"] = cpu_baseline(b, wl)
+        rep, sample, ob, ocand = cpu_baseline(b, wl)
+        out["cpu_baseline"] = rep
+        # the GPU's selected rotations against the FP64 oracle on the particles the oracle ran
+        out["vs_oracle"] = {"fp32": errors_vs_oracle(S, b, sample, ob, ocand, best),
+                            "bf16": errors_vs_oracle(S, b, sample, ob, ocand, b16),
+                            "bf16_without_fp32_final_level": errors_vs_oracle(S, b, sample, ob, ocand, b16o)}
+        out["rot_err_vs_oracle_deg"] = {k: v["rot_err_vs_oracle_deg"] for k, v in out["vs_oracle"].items()}
+        log(f"vs oracle: {json.dumps(out['rot_err_vs_oracle_deg'])}")
     print(json.dumps(out), flush=True)
     ctx.close()
 

@@ -8,6 +8,11 @@
  *   -> frequency-marched Newton refinement and final selection (Sec. 2.2, 2.4, Alg. 1)
  *   and the adjoint of the selected objective value with respect to the inputs.
  *
+ * Problem statement (Sec. 1): given a particle f and a template h, both real functions,
+ * return the rotation g maximising <f, g o h>; the inputs of Alg. 1 are the band schedule
+ * {L_j}, the Newton steps per level M_iter and the number of SOFFT candidates (the paper's P,
+ * Kc here).
+ *
  * Conventions (App. A.3-A.5).  Rotations use the ZYZ chart
  * g(a, b, c) = r_z(a) r_y(b) r_z(c) (eq. Euler), angles in radians, a and c in
  * [0, 2pi), b in [0, pi].  D^l_mn(a, b, c) = e^{-ima} d^l_mn(b) e^{-inc}
@@ -17,20 +22,29 @@
  * i.e. <f, g o h> with (g o h)_l = D^l(g) h_l; the conjugation of D is the
  * "conjugation absorbed into the coefficients" of App. A.5.
  *
- * Memory.  Every pointer is a device pointer unless its comment says (host).
- * The caller allocates every input, output and workspace buffer; the library
- * keeps no pointer after the enqueued work completes.  A context owns read-only
- * tables (recurrence coefficients, SOFFT node data) that it builds on the first call
- * that needs them or in matcha_prepare(), the SOFFT workspace of its eager
- * matcha_soft_search calls (see there) and the particle order of its eager
- * matcha_coeff_assemble calls on batches of mixed L_p (see there).  Every call validates its
- * arguments synchronously on the host and then enqueues its kernels on `stream`
- * (a hipStream_t passed as void*); nothing waits on the device.  A context is not
- * thread-safe.
+ * Memory.  Every pointer is a device pointer unless its comment says (host).  The caller
+ * allocates every input, output and workspace buffer; the library allocates nothing on the
+ * caller's behalf and keeps no pointer after the enqueued work completes.  A context owns only
+ * read-only tables: the Wigner-d recurrence coefficients for every degree up to MATCHA_MAX_L
+ * (built by matcha_create), the SOFFT node tables of each (B, n_grid) passed to matcha_prepare,
+ * and the launch shapes chosen by matcha_autotune.  Tables are freed only by matcha_destroy, so
+ * a captured graph never refers to freed tables while its context lives.
  *
- * Errors.  Invalid arguments return MATCHA_ERR_INVALID_ARG and enqueue nothing.
- * Launch failures return MATCHA_ERR_HIP.  Numerical conditions never fail a call;
- * they set per-particle status bits (MATCHA_ST_*).  No C++ exception crosses the ABI.
+ * Calls.  matcha_create, matcha_prepare, matcha_autotune and the graph calls are synchronous
+ * set-up calls and may allocate.  The enqueue calls (matcha_coeff_assemble, matcha_soft_search,
+ * matcha_march_newton, matcha_evaluate, matcha_grad_template) validate their arguments on the
+ * host and enqueue kernels on `stream` (a hipStream_t passed as void*); they never allocate,
+ * free or wait on the device, so they can be captured into a HIP graph.  A context is not
+ * thread-safe; calls that share a workspace must be ordered (one stream).
+ *
+ * Errors.  Invalid arguments return MATCHA_ERR_INVALID_ARG and enqueue nothing; a workspace
+ * below the call's need returns MATCHA_ERR_WORKSPACE; a SOFFT shape not passed to
+ * matcha_prepare returns MATCHA_ERR_NOT_PREPARED.  The enqueue calls check, in this order, the
+ * batch, the configuration and buffer arguments, the workspace and then the context (a NULL ctx
+ * gives MATCHA_ERR_INVALID_ARG only once everything else has passed; device pointers are checked
+ * for NULL and alignment only, never read on the host).  Launch failures return MATCHA_ERR_HIP.
+ * Numerical conditions never fail a call; they set per-particle status bits (MATCHA_ST_*).
+ * No C++ exception crosses the ABI.
  *
  * Layouts.
  *   complex      : interleaved (re, im), float32 unless stated.
@@ -43,9 +57,13 @@
  *                  (m, n) with 0 <= |n| <= m <= l, in the order q = m*m + m + n,
  *                  two values: C^l_mn and C^l_{m'n'} of its partner
  *                  (m', n') = (n, m) if n >= 0, (-n, -m) if n < 0.
- *                  Row l starts at 2 * l(l+1)(2l+1)/6 complex values.  The wedge and
- *                  its partners cover {m > 0} and {m = 0, n >= 0}; the other half
- *                  follows from C^l_{-m,-n} = (-1)^{m-n} conj(C^l_mn).
+ *                  Row l starts at 2 * l(l+1)(2l+1)/6 complex values, so the rows l <= L' of a
+ *                  band-L_p block are the band-L' block.  The wedge and its partners cover
+ *                  {m > 0} and {m = 0, n >= 0}; the other half follows from
+ *                  C^l_{-m,-n} = (-1)^{m-n} conj(C^l_mn).  matcha_c_unpack converts to the
+ *                  packed-by-l layout.
+ *   C (by l)     : block l at l(4l^2-1)/3 complex values, (2l+1)^2 values row-major in
+ *                  (m, n), m, n = -l..l.
  *   candidates   : float4 (a, b, c, value) per candidate, [P][Kc].
  */
 #ifndef MATCHA_H
@@ -63,7 +81,8 @@ typedef enum {
     MATCHA_ERR_INVALID_ARG = -1,
     MATCHA_ERR_UNSUPPORTED = -2,
     MATCHA_ERR_HIP = -3,
-    MATCHA_ERR_WORKSPACE = -4
+    MATCHA_ERR_WORKSPACE = -4,
+    MATCHA_ERR_NOT_PREPARED = -5
 } matcha_status;
 
 typedef enum {
@@ -96,8 +115,9 @@ typedef struct {
     const int32_t *R_host;      /* (host) [P]                                   */
     const int32_t *L_dev;       /* [P]                                          */
     const int32_t *R_dev;       /* [P]                                          */
-    const int64_t *f_offset;    /* [P] complex-element offsets of particles in f */
-    const int64_t *C_offset;    /* [P] complex-element offsets in C              */
+    const int64_t *f_offset;    /* [P] complex-element offsets of particles in f (any layout
+                                   that keeps particles apart; need not be packed) */
+    const int64_t *C_offset;    /* [P] complex-element offsets in C (even)       */
     int32_t L_h, R_h;           /* template extents: h is [R_h][(L_h+1)^2]       */
     const int32_t *order;       /* [P] nullable: processing order of the particles for the
                                    march (e.g. longest first from matcha_lpt_order); the
@@ -116,7 +136,9 @@ typedef struct {
 /* Frequency march (Alg. 1).  levels (host) is the global schedule; particle p
  * runs every level < L_p and then L_p.  steps = M_iter Newton steps per level.
  * max_step > 0 clips the largest component of a Newton step (0: pure Newton, as
- * in the paper).  early_stop enables the Sec. 2.4 tolerances. */
+ * in the paper).  early_stop enables the Sec. 2.4 tests: a level ends once
+ * |grad| <= tol_grad |F|, |F - F_prev| <= tol_rel |F| (from its second step on) or the last
+ * step's largest component <= tol_step. */
 typedef struct {
     const int32_t *levels; /* (host) strictly increasing, levels[0] >= 1 */
     int32_t n_levels;
@@ -126,6 +148,10 @@ typedef struct {
     double tol_grad, tol_step, tol_rel;
     int32_t fp64_above;    /* levels above this degree run the Wigner-d recurrence in FP64 (FP64
                               coefficient table; the l-sums stay FP32); 0 or >= MATCHA_MAX_L: FP32 only */
+    const float *C_final;  /* nullable: coefficients (same layout and offsets as C) for each
+                              particle's final level L_p and the final values; NULL: C.  The BF16
+                              path marches the lower levels on BF16-assembled C and the final level
+                              on FP32-assembled C_final. */
 } matcha_march_cfg;
 
 /* Launch shapes.  Zero fields mean "library default".  march_nc: candidates per wavefront
@@ -138,13 +164,18 @@ typedef struct {
 } matcha_tuning;
 
 /* ---- context ---------------------------------------------------------- */
-/* Creates a context on HIP device `device`.  out receives the handle. */
-matcha_status matcha_create(int device, matcha_ctx **out);
+/* Creates a context on HIP device `device` and builds its recurrence tables for every degree up
+ * to MATCHA_MAX_L (synchronous).  tune_cache (host, nullable): path of a text file of autotune
+ * results, read now if it exists; matcha_autotune looks results up there before timing anything
+ * and adds what it measures.  out receives the handle. */
+matcha_status matcha_create(int device, const char *tune_cache, matcha_ctx **out);
+/* Waits for the device, then frees the context's tables.  Graphs made on it must be destroyed
+ * first. */
 matcha_status matcha_destroy(matcha_ctx *ctx);
-/* Builds the read-only tables for band limits up to L_max and (if n_grid > 0) the
- * SOFFT band B on an n_grid^3 grid, so that later calls allocate nothing (needed
- * before stream capture).  Synchronous. */
-matcha_status matcha_prepare(matcha_ctx *ctx, int32_t L_max, int32_t B, int32_t n_grid);
+/* Builds the SOFFT node tables of band B on an n_grid^3 grid (1 <= B <= 32, 4 <= n_grid <= 96),
+ * kept until matcha_destroy; searches with a (B, n_grid) not prepared return
+ * MATCHA_ERR_NOT_PREPARED.  Synchronous; repeated calls with a prepared shape do nothing. */
+matcha_status matcha_prepare(matcha_ctx *ctx, int32_t B, int32_t n_grid);
 const char *matcha_status_string(matcha_status s);
 /* Sets / reads the launch shapes used by later calls on this context. */
 matcha_status matcha_set_tuning(matcha_ctx *ctx, const matcha_tuning *t);
@@ -156,13 +187,26 @@ matcha_status matcha_get_tuning(const matcha_ctx *ctx, matcha_tuning *t);
 int64_t matcha_c_elems(int32_t L);
 /* Complex values of one particle's f: R (L+1)^2. */
 int64_t matcha_f_elems(int32_t L, int32_t R);
-/* Bytes of workspace needed by matcha_soft_search / matcha_march_newton /
- * matcha_grad_template for this batch (0 when none). */
-size_t matcha_workspace_size(const matcha_batch *batch, int32_t Kc);
+/* Bytes of workspace with which every enqueue call on this batch runs in one pass: the maximum of
+ *   matcha_coeff_assemble: P int32 (the particle order by L_p) when the L_p differ, else 0;
+ *   matcha_soft_search (soft non-NULL): per particle n^3 floats of grid, n (B+1)(2B+1) complex
+ *     node transforms and 1024 maxima keys (575 KB at B = 12, n_grid = 48), for as many particles
+ *     as fit in 4 GiB;
+ *   matcha_grad_template: P int64 offsets plus one template-gradient term of R_p (L_p+1)^2
+ *     complex float32 per particle;
+ *   matcha_march_newton, matcha_evaluate: none.
+ * Returns 0 for an empty or invalid batch.  ctx and march may be NULL. */
+size_t matcha_workspace_size(const matcha_ctx *ctx, const matcha_batch *batch, const matcha_soft_cfg *soft,
+                             const matcha_march_cfg *march);
 
 /* Longest-processing-time order (host): particle indices sorted by decreasing march cost
  * Kc * steps * sum over the particle's schedule of (L_j+1)(L_j+2)(2L_j+3)/6, ties by index. */
 matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg *cfg, int32_t *order_host);
+
+/* Wedge layout -> packed-by-l layout (host, for callers that want C^l as full matrices):
+ * C_wedge [matcha_c_elems(L)] complex float32 of one particle, C_byl [sum_{l<=L} (2l+1)^2]
+ * complex float32; the half not stored is filled from C^l_{-m,-n} = (-1)^{m-n} conj(C^l_mn). */
+matcha_status matcha_c_unpack(int32_t L, const float *C_wedge_host, float *C_byl_host);
 
 /* ---- the path ------------------------------------------------------------ */
 /* Coefficient assembly, eq. sigmalmm (Sec. 2.1, App. A.5) with shells in place of
@@ -173,12 +217,13 @@ matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg
  * R_max = max_p R_p shells is staged in one workgroup's LDS: MATCHA_ERR_UNSUPPORTED when
  * 8 R_max 16 ceil((2 L_max + 1) / 16) bytes (FP32; BF16: 4 (2 R_max rounded up to 32, + 8)
  * 16 ceil((2 L_max + 1) / 16)) exceed 160 KB, e.g. R_max > 142 at L_max = 64 in FP32.
- * When the L_p differ, a first kernel orders the particles by decreasing L_p into P int32
- * owned by the context (allocated on first need and grown synchronously; a graph from
- * matcha_align_graph_create owns its own), so that the rows of degree l cover only the
- * particles with L_p >= l; results do not depend on that order. */
+ * When the L_p differ, a first kernel orders the particles by decreasing L_p into the head of
+ * ws (P int32; MATCHA_ERR_WORKSPACE if ws_bytes is smaller), so that the rows of degree l cover
+ * only the particles with L_p >= l; results do not depend on that order.  With equal L_p, ws
+ * may be NULL. */
 matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
-                                    const float *w, float *C, matcha_precision prec, void *stream);
+                                    const float *w, float *C, matcha_precision prec, void *ws, size_t ws_bytes,
+                                    void *stream);
 
 /* SOFFT search at band B (Sec. 2.3; the search step of Alg. 1): evaluates C_B on the
  * n_grid^3 grid (Wigner-d transform over l, then a 2-D inverse DFT over (a, c)),
@@ -187,16 +232,14 @@ matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, 
  * ranks them by (value desc, index asc) and writes the first Kc to cand
  * [P][Kc] float4 (a_j, b_i, c_k, value).  With fewer than Kc maxima the list is
  * filled with the best remaining nodes and MATCHA_ST_FEW_MAXIMA is set.
- * status [P] is overwritten.  Requires 1 <= B <= min_p L_p, B <= 32, 4 <= n_grid <= 96,
- * 1 <= Kc <= MATCHA_MAX_KC (MATCHA_ERR_UNSUPPORTED if the shape does not fit a workgroup's LDS).
- * The node transforms, the grid and the maxima lists pass through a workspace owned by the
- * context (n_grid^3 floats of grid, n_grid (B+1)(2B+1) complex values and a key list per
- * particle: 575 KB at B = 12, n_grid = 48; at most 4 GiB, larger batches run in chunks of
- * particles), allocated on first need and
- * grown synchronously; calls on one context must not overlap in time (use one stream per
- * context).  matcha_align_graph_create gives each graph a workspace of its own. */
+ * status [P] is overwritten.  Requires 1 <= B <= min_p L_p, 1 <= Kc <= MATCHA_MAX_KC and
+ * (B, n_grid) prepared (MATCHA_ERR_UNSUPPORTED if the shape does not fit a workgroup's LDS).
+ * The node transforms, the grid and the maxima lists of each particle pass through ws; the
+ * batch runs in chunks of as many particles as ws holds (MATCHA_ERR_WORKSPACE below one
+ * particle's share, see matcha_workspace_size). */
 matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
-                                 const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream);
+                                 const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *ws, size_t ws_bytes,
+                                 void *stream);
 
 /* Frequency-marched Newton refinement and selection (the march and selection steps of
  * Alg. 1, Sec. 2.2):
@@ -206,10 +249,11 @@ matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, con
  * (ties: lowest index; non-finite values never win).
  * cand [P][Kc] float4 in/out: in = start points, out = (final angles, C_{L_p}).
  * best [P] float4 (a, b, c, C_{L_p}) of the selected candidate; best_idx [P];
- * status [P] in/out: the selected candidate's bits are OR-ed into it. */
+ * status [P] in/out: the selected candidate's bits are OR-ed into it.  Uses no workspace
+ * (ws may be NULL). */
 matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
                                   const matcha_march_cfg *cfg, int32_t Kc, float *cand, float *best,
-                                  int32_t *best_idx, uint32_t *status, void *stream);
+                                  int32_t *best_idx, uint32_t *status, void *ws, size_t ws_bytes, void *stream);
 
 /* Objective only: value, gradient and Hessian of C_{L_eval} at one rotation per
  * particle.  theta [P] float4 (a, b, c, unused); out [P][10] float:
@@ -223,35 +267,54 @@ matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const 
  *   grad_h[r][l,n] = sum_p g_p w_r sum_m f_p,lm(r) conj(D^l_mn(R_p*))
  *   grad_f_p[r][l,m] = g_p w_r sum_n D^l_mn(R_p*) h_ln(r)
  * grad_h: complex float32 [R_h][(L_h+1)^2] (entries outside every particle's
- * range are zeroed); grad_f: same layout as f; either may be NULL.  The sum over
- * particles is deterministic (fixed-order tree, no floating-point atomics).
- * ws: workspace of matcha_workspace_size() bytes. */
+ * range are zeroed); grad_f: same layout as f; either may be NULL.  prec: MATCHA_FP32 only
+ * (MATCHA_ERR_UNSUPPORTED otherwise).  The sum over particles is deterministic (particles in
+ * index order, no floating-point atomics); each particle's term passes through ws (packed in the
+ * library's own order, whatever f_offset is; MATCHA_ERR_WORKSPACE if ws_bytes is below
+ * matcha_workspace_size's grad_template share when grad_h is requested). */
 matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, const float *f, const float *h,
                                    const float *w, const float *best, const float *g, float *grad_h, float *grad_f,
-                                   void *ws, size_t ws_bytes, void *stream);
+                                   matcha_precision prec, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- batching: graphs and tuning ------------------------------------------ */
 typedef struct matcha_graph matcha_graph;
 
-/* Records matcha_coeff_assemble + matcha_soft_search + matcha_march_newton for these exact
- * buffers into a HIP graph (captured on a private stream) and instantiates it.  Later replays
- * run the whole path with one launch call and read the buffers' contents at replay time.
- * The context must stay alive; tables are built before capture.  Synchronous. */
-matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
-                                        const float *w, float *C, matcha_precision prec, const matcha_soft_cfg *soft,
-                                        const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
-                                        uint32_t *status, matcha_graph **out);
+/* Buffers of the whole path.  f, h, w, prec: the assembly's inputs, into C.  f32 / h32 (both
+ * or neither; FP32, used with prec = MATCHA_BF16_FP32ACC): inputs of an FP32 assembly into C32
+ * that the march uses for each particle's final level (matcha_march_cfg.C_final). */
+typedef struct {
+    const void *f, *h;
+    const float *w;
+    matcha_precision prec;
+    const float *f32, *h32;
+    float *C, *C32;
+    float *cand, *best;
+    int32_t *best_idx;
+    uint32_t *status;
+} matcha_align_bufs;
+
+/* Records matcha_coeff_assemble (twice with f32 / h32) + matcha_soft_search +
+ * matcha_march_newton for these exact buffers and workspace into a HIP graph (captured on a
+ * private stream) and instantiates it.  Later replays run the whole path with one launch call
+ * and read the buffers' contents at replay time; the buffers and ws must outlive the graph, and
+ * the context must outlive it too.  (soft->B, soft->n_grid) must be prepared.  march->C_final is
+ * ignored (C32 takes its place).  Synchronous. */
+matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *batch, const matcha_align_bufs *bufs,
+                                        const matcha_soft_cfg *soft, const matcha_march_cfg *march, void *ws,
+                                        size_t ws_bytes, matcha_graph **out);
 /* Replays the graph on `stream` (asynchronous). */
 matcha_status matcha_graph_launch(matcha_graph *g, void *stream);
 matcha_status matcha_graph_destroy(matcha_graph *g);
 
-/* Autotuner: times every supported launch shape of the SOFFT search and of the march on this
- * batch (hipEvents, `reps` repetitions each, after one warm-up), keeps the fastest in the
- * context (later calls use it) and returns it in *best_tuning (host).  cand / best / best_idx /
- * status / C are used as scratch and hold the last trial's (valid) results.  Synchronous. */
+/* Autotuner: when the context's tune cache holds a result for this device, batch shape and
+ * configuration, applies it and returns it without timing.  Otherwise times every supported launch
+ * shape of the SOFFT search and of the march on this batch (hipEvents, `reps` repetitions each,
+ * after one warm-up), keeps the fastest in the context (later calls use it), adds it to the tune
+ * cache file and returns it in *best_tuning (host).  cand / best / best_idx / status are used as
+ * scratch and hold the last trial's (valid) results.  Synchronous. */
 matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *soft,
                               const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
-                              uint32_t *status, int32_t reps, matcha_tuning *best_tuning);
+                              uint32_t *status, int32_t reps, void *ws, size_t ws_bytes, matcha_tuning *best_tuning);
 
 #ifdef __cplusplus
 }

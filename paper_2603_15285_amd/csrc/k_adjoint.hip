@@ -14,8 +14,9 @@
 // the grad_h term d^T . Fs^T (v_mfma_f32_16x16x4_f32; lane i supplies A[i%16][i/16] and
 // B[i/16][i%16] of a 16 x 4 x 16 step and holds D rows 4(i/16) .. +3 of column i%16), with the
 // real and imaginary parts of the staged arrays as two B operands.
-// The particle's grad_h term goes to a workspace laid out like f; a second kernel sums the
-// particles in index order (no floating-point atomics, so the result is deterministic).
+// The particle's grad_h term goes to a workspace at packed offsets (computed from L_p and R_p by a
+// first kernel, independent of the caller's f_offset); a last kernel sums the particles in index
+// order (no floating-point atomics, so the result is deterministic).
 #include "matcha_launch.hpp"
 
 namespace matcha {
@@ -58,7 +59,7 @@ __global__ void __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_e
     const int64_t sf = (int64_t)(L + 1) * (L + 1), sh = (int64_t)(a.Lh + 1) * (a.Lh + 1);
     const float2 *fp = a.f + a.f_off[p];
     float2 *gf = a.grad_f ? a.grad_f + a.f_off[p] : nullptr;
-    float2 *gw = a.ws ? a.ws + a.f_off[p] : nullptr;
+    float2 *gw = a.ws ? a.ws + a.ws_off[p] : nullptr;
 
     for (int l = 0; l <= L; ++l) {
         const int w = 2 * l + 1;
@@ -149,6 +150,33 @@ __global__ void __launch_bounds__(kAdjThreads) __attribute__((amdgpu_waves_per_e
     }
 }
 
+// ws_off[p] = sum_{q < p} R_q (L_q+1)^2: the packed offsets of the particles' template terms, in one
+// workgroup (each thread sums a run of particles, the runs' totals are scanned in LDS, then each
+// thread writes its run's offsets).
+constexpr int kScanThreads = 1024;
+__global__ void __launch_bounds__(kScanThreads) k_term_offsets(const int32_t *Lp, const int32_t *Rp, int P, int64_t *off)
+{
+    __shared__ int64_t part[kScanThreads];
+    const int t = threadIdx.x;
+    const int per = (P + kScanThreads - 1) / kScanThreads;
+    const int b = min(t * per, P), e = min(b + per, P);
+    int64_t s = 0;
+    for (int p = b; p < e; ++p) s += (int64_t)Rp[p] * (Lp[p] + 1) * (Lp[p] + 1);
+    part[t] = s;
+    __syncthreads();
+    for (int d = 1; d < kScanThreads; d <<= 1) {
+        const int64_t v = t >= d ? part[t - d] : 0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    int64_t o = t > 0 ? part[t - 1] : 0;
+    for (int p = b; p < e; ++p) {
+        off[p] = o;
+        o += (int64_t)Rp[p] * (Lp[p] + 1) * (Lp[p] + 1);
+    }
+}
+
 // grad_h[r][lm] = sum over particles in index order of their terms (zero outside a particle's
 // shells and degrees).
 __global__ void __launch_bounds__(256) k_grad_reduce(GradArgs a)
@@ -170,7 +198,7 @@ __global__ void __launch_bounds__(256) k_grad_reduce(GradArgs a)
             const int p = min(p0 + u, a.P - 1);
             const int Lp = a.Lp[p], Rp = a.Rp[p];
             const bool ok = p0 + u < a.P && r < Rp && l <= Lp;
-            v[u] = a.ws[ok ? a.f_off[p] + (int64_t)r * (Lp + 1) * (Lp + 1) + lm : 0];
+            v[u] = a.ws[ok ? a.ws_off[p] + (int64_t)r * (Lp + 1) * (Lp + 1) + lm : 0];
             if (!ok) v[u] = make_float2(0.f, 0.f);
         }
 #pragma unroll
@@ -190,6 +218,11 @@ size_t grad_smem_bytes(int Lmax)
 
 hipError_t launch_grad(const GradArgs &a, hipStream_t s)
 {
+    if (a.ws) {
+        hipLaunchKernelGGL(k_term_offsets, dim3(1), dim3(kScanThreads), 0, s, a.Lp, a.Rp, a.P, a.ws_off);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_grad_particle, dim3(a.P), dim3(kAdjThreads), grad_smem_bytes(a.L_max), s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.grad_h) return e;

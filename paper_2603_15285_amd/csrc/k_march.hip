@@ -506,6 +506,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
 
     const int Lp = a.Lp[p];
     const float4 *Cp = a.C + a.C_off[p] / 2;
+    const float4 *Cf = (a.C_fin ? a.C_fin : a.C) + a.C_off[p] / 2;  // the final level's coefficients
     if (lane < NC) {
         const int k = wave * NC + lane;
         float4 c0 = k < a.Kc ? a.cand[(int64_t)p * a.Kc + k] : make_float4(0.f, 1.5707964f, 0.f, 0.f);
@@ -525,10 +526,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
     for (int j = 0; j < a.n_levels; ++j) ns += a.levels[j] < Lp;
     for (int j = 0; j < ns; ++j) {
         const int L = j + 1 < ns ? a.levels[j] : Lp;
+        const float4 *Cl = j + 1 < ns ? Cp : Cf;
         if (lane < NC) st.frozen[lane] = 0;
         for (int s = 0; s < a.steps; ++s) {
             prepare_step<NC, true>(st, ws, L, lane);
-            eval_level_any<NC, true, F64>(Cp, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
+            eval_level_any<NC, true, F64>(Cl, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
             wave_reduce<NC, 10>(acc, st, lane);
             if (lane < NC && !st.frozen[lane]) {
                 double e[10];
@@ -568,7 +570,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
     // value at the final points on the last level, then selection
     prepare_step<NC, true>(st, ws, Lp, lane);
-    eval_level_any<NC, false, F64>(Cp, a.tab, a.tab64, a.pinfo, Lp, a.fp64_above, st.bc, ws, acc, lane);
+    eval_level_any<NC, false, F64>(Cf, a.tab, a.tab64, a.pinfo, Lp, a.fp64_above, st.bc, ws, acc, lane);
     wave_reduce<NC, 1>(acc, st, lane);
     if (lane < NC) {
         const int k = wave * NC + lane;

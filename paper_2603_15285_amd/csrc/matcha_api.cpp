@@ -1,13 +1,18 @@
 // matcha_api.cpp -- the C ABI of libmatcha (include/matcha.h): argument validation,
-// read-only table construction, launch sizing.  Everything numerical runs in the kernels.
+// read-only table construction, workspace layout, launch sizing, the tune cache.  Everything
+// numerical runs in the kernels.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
-#include <utility>
 #include <cmath>
+#include <complex>
 #include <cstdint>
+#include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
+#include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/matcha.h"
@@ -15,20 +20,28 @@
 
 using namespace matcha;
 
+namespace {
+
+// SOFFT node tables of one prepared (B, n) shape.
+struct GridTables {
+    int B = 0, n = 0;
+    float2 *dgrid = nullptr;  // weighted d^l(b_i) per node and wedge pair (build_grid_table)
+    float *dft = nullptr;     // DFT tables of the grid kernel (build_soft_dft)
+};
+
+}  // namespace
+
 struct matcha_ctx {
     int device = 0;
-    int tab_L = -1;  // tables cover l <= tab_L
+    // recurrence tables for every l <= kMaxL, built by matcha_create
     float4 *tab = nullptr;
     double2 *tab64 = nullptr;  // (A, AC) of tab in FP64
     PairInfo *pinfo = nullptr;
+    std::vector<GridTables> grids;  // every prepared (B, n); freed by matcha_destroy only
     matcha_tuning tune{0, 0};
-    int grid_B = -1, grid_n = -1;  // the SOFFT node tables below are for (grid_B, grid_n)
-    float2 *dgrid = nullptr;
-    float *dft = nullptr;           // DFT tables of the SOFFT grid kernel (build_soft_dft)
-    float *soft_ws = nullptr;       // SOFFT grid workspace of the eager calls
-    size_t soft_ws_bytes = 0;
-    int32_t *by_L = nullptr;        // particle order of the eager assembly calls on mixed L_p
-    int by_L_cap = 0;
+    std::string tune_path;  // tune cache file, empty: none
+    std::map<std::string, matcha_tuning> tune_cache;
+    std::string arch;  // device name and compute-unit count, part of every tune cache key
 };
 
 namespace {
@@ -94,49 +107,6 @@ void build_tables(int Lmax, std::vector<float4> &tab, std::vector<double2> &tab6
         }
 }
 
-matcha_status ensure_tables(matcha_ctx *ctx, int L)
-{
-    if (L <= ctx->tab_L) return MATCHA_OK;
-    std::vector<float4> tab;
-    std::vector<double2> tab64;
-    std::vector<PairInfo> pinfo;
-    build_tables(L, tab, tab64, pinfo);
-    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    float4 *dt = nullptr;
-    double2 *dt64 = nullptr;
-    PairInfo *dp = nullptr;
-    if (hipMalloc(&dt, tab.size() * sizeof(float4)) != hipSuccess) return MATCHA_ERR_HIP;
-    if (hipMalloc(&dt64, tab64.size() * sizeof(double2)) != hipSuccess) {
-        (void)hipFree(dt);
-        return MATCHA_ERR_HIP;
-    }
-    if (hipMalloc(&dp, pinfo.size() * sizeof(PairInfo)) != hipSuccess) {
-        (void)hipFree(dt);
-        (void)hipFree(dt64);
-        return MATCHA_ERR_HIP;
-    }
-    if (hipMemcpy(dt, tab.data(), tab.size() * sizeof(float4), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(dt64, tab64.data(), tab64.size() * sizeof(double2), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(dp, pinfo.data(), pinfo.size() * sizeof(PairInfo), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(dt);
-        (void)hipFree(dt64);
-        (void)hipFree(dp);
-        return MATCHA_ERR_HIP;
-    }
-    // the previous (smaller) tables may still be in use by enqueued work
-    if (ctx->tab) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->tab);
-        (void)hipFree(ctx->tab64);
-        (void)hipFree(ctx->pinfo);
-    }
-    ctx->tab = dt;
-    ctx->tab64 = dt64;
-    ctx->pinfo = dp;
-    ctx->tab_L = L;
-    return MATCHA_OK;
-}
-
 // d^l_mn(b_i) at the SOFFT polar nodes b_i = pi (2i+1) / (2n) for every wedge pair and l <= B,
 // in FP64 by the three-term recurrence from the edge value
 //   d^m_mn(b) = (-1)^{m-n} sqrt(binom(2m, m+n)) cos^{m+n}(b/2) sin^{m-n}(b/2),
@@ -168,44 +138,53 @@ void build_grid_table(int B, int n, std::vector<float2> &g)
     }
 }
 
-matcha_status ensure_grid(matcha_ctx *ctx, int B, int n)
+
+const GridTables *find_grid(const matcha_ctx *ctx, int B, int n)
 {
-    if (ctx->dgrid && ctx->grid_B == B && ctx->grid_n == n) return MATCHA_OK;
-    std::vector<float2> g;
-    build_grid_table(B, n, g);
-    std::vector<float> e(soft_dft_floats(n, B));
-    build_soft_dft(B, n, e.data());
-    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    float2 *d = nullptr;
-    float *de = nullptr;
-    if (hipMalloc(&d, g.size() * sizeof(float2)) != hipSuccess) return MATCHA_ERR_HIP;
-    if (hipMalloc(&de, e.size() * sizeof(float)) != hipSuccess) {
-        (void)hipFree(d);
+    for (const GridTables &g : ctx->grids)
+        if (g.B == B && g.n == n) return &g;
+    return nullptr;
+}
+
+template <typename T>
+matcha_status upload(const std::vector<T> &host, T **dev)
+{
+    *dev = nullptr;
+    if (hipMalloc(dev, host.size() * sizeof(T)) != hipSuccess) {
+        *dev = nullptr;
         return MATCHA_ERR_HIP;
     }
-    if (hipMemcpy(d, g.data(), g.size() * sizeof(float2), hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(de, e.data(), e.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-        (void)hipFree(d);
-        (void)hipFree(de);
+    if (hipMemcpy(*dev, host.data(), host.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(*dev);
+        *dev = nullptr;
         return MATCHA_ERR_HIP;
     }
-    if (ctx->dgrid) {
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->dgrid);
-        (void)hipFree(ctx->dft);
-    }
-    ctx->dgrid = d;
-    ctx->dft = de;
-    ctx->grid_B = B;
-    ctx->grid_n = n;
     return MATCHA_OK;
 }
 
-// The SOFFT search of a particle keeps in a workspace, between its kernels: the Wigner
+void free_tables(matcha_ctx *ctx)
+{
+    if (ctx->tab) (void)hipFree(ctx->tab);
+    if (ctx->tab64) (void)hipFree(ctx->tab64);
+    if (ctx->pinfo) (void)hipFree(ctx->pinfo);
+    for (GridTables &g : ctx->grids) {
+        if (g.dgrid) (void)hipFree(g.dgrid);
+        if (g.dft) (void)hipFree(g.dft);
+    }
+    ctx->grids.clear();
+    ctx->tab = nullptr;
+    ctx->tab64 = nullptr;
+    ctx->pinfo = nullptr;
+}
+
+// ---- workspace layouts (every region 256-byte aligned) ----------------------------------
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// The SOFFT search of a particle keeps in the workspace, between its kernels: the Wigner
 // transforms of its n polar nodes ((B+1)(2B+1) complex each), its grid (n^3 floats) and its list
-// of maxima keys with their count.  Batches whose workspace would exceed kSoftWsCap run in chunks
-// of particles.  Layout of a chunk of pc particles (each region 256-byte aligned): the grids, pc
-// lists of kSoftListMax keys, pc counts, the Wigner transforms.
+// of maxima keys with their count.  A chunk of pc particles lays out: the grids, pc lists of
+// kSoftListMax keys, pc counts, the Wigner transforms.  matcha_workspace_size offers one chunk of
+// the whole batch up to kSoftWsCap; a smaller workspace runs the batch in more chunks.
 constexpr size_t kSoftWsCap = (size_t)4 << 30;
 constexpr size_t kSoftListMax = 1024;  // keys per particle: the larger select workgroup's list
 
@@ -215,7 +194,6 @@ size_t soft_particle_bytes(int n, int B)
 {
     return soft_grid_bytes(n) + kSoftListMax * sizeof(unsigned long long) + sizeof(uint32_t) + soft_s_bytes(n, B);
 }
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct SoftChunk {
     size_t grid, list, count, S, total;  // region offsets and total bytes
@@ -238,44 +216,24 @@ size_t soft_ws_need(int P, int n, int B)
     return soft_chunk(pc, n, B).total;
 }
 
-matcha_status ensure_soft_ws(matcha_ctx *ctx, size_t bytes)
-{
-    if (ctx->soft_ws_bytes >= bytes) return MATCHA_OK;
-    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    if (ctx->soft_ws) {
-        (void)hipDeviceSynchronize();  // earlier searches may still read it
-        (void)hipFree(ctx->soft_ws);
-        ctx->soft_ws = nullptr;
-        ctx->soft_ws_bytes = 0;
-    }
-    if (hipMalloc(&ctx->soft_ws, bytes) != hipSuccess) {
-        ctx->soft_ws = nullptr;
-        return MATCHA_ERR_HIP;
-    }
-    ctx->soft_ws_bytes = bytes;
-    return MATCHA_OK;
-}
+// Assembly of mixed L_p: the particle order by decreasing L_p, P int32 at the head of ws.
+size_t assemble_ws_need(int P, bool mixed) { return mixed ? sizeof(int32_t) * (size_t)P : 0; }
 
-matcha_status ensure_by_L(matcha_ctx *ctx, int P)
+// Adjoint: P int64 offsets of the particles' template terms (packed by the library, whatever
+// f_offset is), then the terms, R_p (L_p+1)^2 complex float32 each.
+size_t grad_terms(const matcha_batch *b)
 {
-    if (ctx->by_L_cap >= P) return MATCHA_OK;
-    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    if (ctx->by_L) {
-        (void)hipDeviceSynchronize();  // earlier assemblies may still read it
-        (void)hipFree(ctx->by_L);
-        ctx->by_L = nullptr;
-        ctx->by_L_cap = 0;
-    }
-    if (hipMalloc(&ctx->by_L, sizeof(int32_t) * (size_t)P) != hipSuccess) {
-        ctx->by_L = nullptr;
-        return MATCHA_ERR_HIP;
-    }
-    ctx->by_L_cap = P;
-    return MATCHA_OK;
+    size_t n = 0;
+    for (int p = 0; p < b->n_particles; ++p)
+        n += (size_t)b->R_host[p] * (size_t)(b->L_host[p] + 1) * (size_t)(b->L_host[p] + 1);
+    return n;
+}
+size_t grad_ws_need(const matcha_batch *b)
+{
+    return align256(sizeof(int64_t) * (size_t)b->n_particles) + grad_terms(b) * sizeof(float2);
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
-
 
 // Common batch checks; on success minL / maxL / maxR hold the host-side extents.
 matcha_status check_batch(const matcha_batch *b, int *minL, int *maxL, int *maxR)
@@ -328,8 +286,9 @@ matcha_status assemble_check(const matcha_batch *batch, const void *f, const voi
 // The assembly launches.  With mixed L_p (lo < hi), by_L ([P] int32) receives the particles in
 // the order of decreasing L_p first, so that each degree's rows cover only the particles that
 // have it.
-matcha_status assemble_ws(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h, const float *w,
-                          float *C, matcha_precision prec, int lo, int hi, int rmax, int32_t *by_L, hipStream_t s)
+matcha_status assemble_launch(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
+                              const float *w, float *C, matcha_precision prec, int lo, int hi, int rmax,
+                              int32_t *by_L, hipStream_t s)
 {
     const int P = batch->n_particles;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
@@ -378,11 +337,145 @@ matcha_status assemble_ws(matcha_ctx *ctx, const matcha_batch *batch, const void
     return launched(launch_assemble_f32(a, P, hi, rmax, s));
 }
 
+// The smallest workspace of a search: one particle's share.
+size_t soft_ws_min(int n, int B) { return soft_chunk(1, n, B).total; }
+
+// Checks of a SOFFT search, in the order batch, configuration and buffers, workspace, context (so
+// that the host-side checks need no device); on success *nt is the select kernel's workgroup size
+// and *gt the prepared tables.
+matcha_status soft_check(const matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *cfg,
+                         const float *cand, const uint32_t *status, const void *ws, size_t ws_bytes, int *nt,
+                         const GridTables **gt)
+{
+    int lo, hi, rmax;
+    if (!cfg) return MATCHA_ERR_INVALID_ARG;
+    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
+    if (st != MATCHA_OK) return st;
+    const int B = cfg->B, n = cfg->n_grid, Kc = cfg->Kc;
+    if (B < 1 || B > 32 || n < 4 || n > 96 || Kc < 1 || Kc > MATCHA_MAX_KC) return MATCHA_ERR_INVALID_ARG;
+    if (batch->n_particles == 0) return ctx ? MATCHA_OK : MATCHA_ERR_INVALID_ARG;
+    if (!C || !cand || !status || !aligned16(C) || !aligned16(cand) || B > lo) return MATCHA_ERR_INVALID_ARG;
+    if (!ws || !aligned16(ws) || ws_bytes < soft_ws_min(n, B)) return MATCHA_ERR_WORKSPACE;
+    if (!ctx) return MATCHA_ERR_INVALID_ARG;
+    *nt = ctx->tune.soft_threads ? ctx->tune.soft_threads : 256;
+    if (soft_grid_smem_bytes(n, B) > 160 * 1024 || soft_select_smem_bytes(n, *nt) > 160 * 1024)
+        return MATCHA_ERR_UNSUPPORTED;
+    *gt = find_grid(ctx, B, n);
+    return *gt ? MATCHA_OK : MATCHA_ERR_NOT_PREPARED;
+}
+
+// The search proper over a workspace of ws_bytes (at least one particle's share).
+matcha_status soft_launch(const matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *cfg,
+                          const GridTables *gt, float *cand, uint32_t *status, int nt, void *ws, size_t ws_bytes,
+                          hipStream_t s)
+{
+    const int P = batch->n_particles, n = cfg->n_grid, B = cfg->B;
+    size_t pcs = std::min<size_t>((size_t)P, ws_bytes / soft_particle_bytes(n, B));
+    while (pcs > 1 && soft_chunk(pcs, n, B).total > ws_bytes) --pcs;
+    const int pc = (int)std::max<size_t>(pcs, 1);
+    const SoftChunk ch = soft_chunk((size_t)pc, n, B);
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    char *base = reinterpret_cast<char *>(ws);
+    SoftArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.C = reinterpret_cast<const float4 *>(C);
+    a.C_off = batch->C_offset;
+    a.dgrid = gt->dgrid;
+    a.dft = gt->dft;
+    a.pinfo = ctx->pinfo;
+    a.B = B;
+    a.n = n;
+    a.Kc = cfg->Kc;
+    a.grid = reinterpret_cast<float *>(base + ch.grid);
+    a.mlist = reinterpret_cast<unsigned long long *>(base + ch.list);
+    a.mcount = reinterpret_cast<uint32_t *>(base + ch.count);
+    a.S = reinterpret_cast<float2 *>(base + ch.S);
+    a.cand = reinterpret_cast<float4 *>(cand);
+    a.status = status;
+    for (int p0 = 0; p0 < P; p0 += pc) {
+        const int cnt = std::min(pc, P - p0);
+        a.p0 = p0;
+        if (launch_soft_wigner(a, cnt, s) != hipSuccess) return MATCHA_ERR_HIP;
+        if (launch_soft_grid(a, cnt, s) != hipSuccess) return MATCHA_ERR_HIP;
+        if (launch_soft_select(a, cnt, nt, s) != hipSuccess) return MATCHA_ERR_HIP;
+    }
+    return MATCHA_OK;
+}
+
+// Checks of the march configuration.
+matcha_status march_check(const matcha_batch *batch, const matcha_march_cfg *cfg, int32_t Kc, int lo)
+{
+    if (Kc < 1 || Kc > MATCHA_MAX_KC || cfg->steps < 0 || cfg->n_levels < 1 || cfg->n_levels > MATCHA_MAX_LEVELS ||
+        !cfg->levels || !(cfg->max_step >= 0.0) || lo < 1)
+        return MATCHA_ERR_INVALID_ARG;
+    if (cfg->C_final && !aligned16(cfg->C_final)) return MATCHA_ERR_INVALID_ARG;
+    if (cfg->early_stop && !(cfg->tol_grad >= 0.0 && cfg->tol_step >= 0.0 && cfg->tol_rel >= 0.0))
+        return MATCHA_ERR_INVALID_ARG;
+    for (int j = 0; j < cfg->n_levels; ++j) {
+        if (cfg->levels[j] < 1 || cfg->levels[j] > MATCHA_MAX_L) return MATCHA_ERR_INVALID_ARG;
+        if (j > 0 && cfg->levels[j] <= cfg->levels[j - 1]) return MATCHA_ERR_INVALID_ARG;
+    }
+    (void)batch;
+    return MATCHA_OK;
+}
+
+// ---- tune cache --------------------------------------------------------------------------
+// One line per entry: "<key> <march_nc> <soft_threads>".  The key names the device and every
+// input of the timing: the batch's size and band / shell statistics, the search shape and the
+// march schedule.
+std::string tune_key(const matcha_ctx *ctx, const matcha_batch *b, const matcha_soft_cfg *soft,
+                     const matcha_march_cfg *march)
+{
+    long long sL = 0, sR = 0;
+    int lo = 1 << 30, hi = -1, rlo = 1 << 30, rhi = -1;
+    for (int p = 0; p < b->n_particles; ++p) {
+        sL += b->L_host[p];
+        sR += b->R_host[p];
+        lo = std::min(lo, b->L_host[p]);
+        hi = std::max(hi, b->L_host[p]);
+        rlo = std::min(rlo, b->R_host[p]);
+        rhi = std::max(rhi, b->R_host[p]);
+    }
+    std::string k = ctx->arch + "|P" + std::to_string(b->n_particles) + "|L" + std::to_string(lo) + "," +
+                    std::to_string(hi) + "," + std::to_string(sL) + "|R" + std::to_string(rlo) + "," +
+                    std::to_string(rhi) + "," + std::to_string(sR) + "|ord" + std::to_string(b->order ? 1 : 0) +
+                    "|B" + std::to_string(soft->B) + ",n" + std::to_string(soft->n_grid) + ",K" +
+                    std::to_string(soft->Kc) + "|lv";
+    for (int j = 0; j < march->n_levels; ++j) k += (j ? "," : "") + std::to_string(march->levels[j]);
+    k += "|s" + std::to_string(march->steps) + "|f64_" + std::to_string(march->fp64_above) + "|es" +
+         std::to_string(march->early_stop);
+    for (char &c : k)
+        if (c == ' ' || c == '\t' || c == '\n') c = '_';
+    return k;
+}
+
+void tune_cache_load(matcha_ctx *ctx)
+{
+    FILE *fp = std::fopen(ctx->tune_path.c_str(), "r");
+    if (!fp) return;
+    char line[4096];
+    while (std::fgets(line, sizeof line, fp)) {
+        char key[4000];
+        int nc = 0, st = 0;
+        if (std::sscanf(line, "%3999s %d %d", key, &nc, &st) == 3) ctx->tune_cache[key] = matcha_tuning{nc, st};
+    }
+    std::fclose(fp);
+}
+
+bool tune_cache_store(const matcha_ctx *ctx, const std::string &key, const matcha_tuning &t)
+{
+    if (ctx->tune_path.empty()) return true;
+    FILE *fp = std::fopen(ctx->tune_path.c_str(), "a");
+    if (!fp) return false;
+    std::fprintf(fp, "%s %d %d\n", key.c_str(), t.march_nc, t.soft_threads);
+    return std::fclose(fp) == 0;
+}
+
 }  // namespace
 
 extern "C" {
 
-matcha_status matcha_create(int device, matcha_ctx **out)
+matcha_status matcha_create(int device, const char *tune_cache, matcha_ctx **out)
 {
     if (!out) return MATCHA_ERR_INVALID_ARG;
     int n = 0;
@@ -391,6 +484,26 @@ matcha_status matcha_create(int device, matcha_ctx **out)
     matcha_ctx *c = new (std::nothrow) matcha_ctx();
     if (!c) return MATCHA_ERR_HIP;
     c->device = device;
+    hipDeviceProp_t prop;
+    if (hipSetDevice(device) != hipSuccess || hipGetDeviceProperties(&prop, device) != hipSuccess) {
+        delete c;
+        return MATCHA_ERR_HIP;
+    }
+    c->arch = std::string(prop.gcnArchName) + "_cu" + std::to_string(prop.multiProcessorCount);
+    std::vector<float4> tab;
+    std::vector<double2> tab64;
+    std::vector<PairInfo> pinfo;
+    build_tables(kMaxL, tab, tab64, pinfo);
+    if (upload(tab, &c->tab) != MATCHA_OK || upload(tab64, &c->tab64) != MATCHA_OK ||
+        upload(pinfo, &c->pinfo) != MATCHA_OK) {
+        free_tables(c);
+        delete c;
+        return MATCHA_ERR_HIP;
+    }
+    if (tune_cache && tune_cache[0]) {
+        c->tune_path = tune_cache;
+        tune_cache_load(c);
+    }
     *out = c;
     return MATCHA_OK;
 }
@@ -398,31 +511,32 @@ matcha_status matcha_create(int device, matcha_ctx **out)
 matcha_status matcha_destroy(matcha_ctx *ctx)
 {
     if (!ctx) return MATCHA_ERR_INVALID_ARG;
-    if (ctx->tab) {
-        (void)hipSetDevice(ctx->device);
-        (void)hipDeviceSynchronize();
-        (void)hipFree(ctx->tab);
-        (void)hipFree(ctx->tab64);
-        (void)hipFree(ctx->pinfo);
-    }
-    if (ctx->dgrid || ctx->soft_ws || ctx->by_L) {
-        (void)hipSetDevice(ctx->device);
-        (void)hipDeviceSynchronize();
-        if (ctx->dgrid) (void)hipFree(ctx->dgrid);
-        if (ctx->dft) (void)hipFree(ctx->dft);
-        if (ctx->soft_ws) (void)hipFree(ctx->soft_ws);
-        if (ctx->by_L) (void)hipFree(ctx->by_L);
-    }
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();  // enqueued work may still read the tables
+    free_tables(ctx);
     delete ctx;
     return MATCHA_OK;
 }
 
-matcha_status matcha_prepare(matcha_ctx *ctx, int32_t L_max, int32_t B, int32_t n_grid)
+matcha_status matcha_prepare(matcha_ctx *ctx, int32_t B, int32_t n_grid)
 {
-    if (!ctx || L_max < 0 || L_max > MATCHA_MAX_L || B < 0 || B > L_max || n_grid < 0) return MATCHA_ERR_INVALID_ARG;
-    matcha_status st = ensure_tables(ctx, L_max);
-    if (st != MATCHA_OK || B < 1 || n_grid < 4) return st;
-    return ensure_grid(ctx, B, n_grid);
+    if (!ctx || B < 1 || B > 32 || n_grid < 4 || n_grid > 96) return MATCHA_ERR_INVALID_ARG;
+    if (find_grid(ctx, B, n_grid)) return MATCHA_OK;
+    std::vector<float2> g;
+    build_grid_table(B, n_grid, g);
+    std::vector<float> e(soft_dft_floats(n_grid, B));
+    build_soft_dft(B, n_grid, e.data());
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    GridTables t;
+    t.B = B;
+    t.n = n_grid;
+    if (upload(g, &t.dgrid) != MATCHA_OK) return MATCHA_ERR_HIP;
+    if (upload(e, &t.dft) != MATCHA_OK) {
+        (void)hipFree(t.dgrid);
+        return MATCHA_ERR_HIP;
+    }
+    ctx->grids.push_back(t);
+    return MATCHA_OK;
 }
 
 const char *matcha_status_string(matcha_status s)
@@ -433,6 +547,7 @@ const char *matcha_status_string(matcha_status s)
     case MATCHA_ERR_UNSUPPORTED: return "unsupported configuration";
     case MATCHA_ERR_HIP: return "HIP runtime error";
     case MATCHA_ERR_WORKSPACE: return "workspace too small";
+    case MATCHA_ERR_NOT_PREPARED: return "SOFFT shape not prepared (call matcha_prepare)";
     }
     return "unknown status";
 }
@@ -467,119 +582,105 @@ int64_t matcha_f_elems(int32_t L, int32_t R)
     return (int64_t)R * (L + 1) * (L + 1);
 }
 
-size_t matcha_workspace_size(const matcha_batch *batch, int32_t Kc)
+size_t matcha_workspace_size(const matcha_ctx *ctx, const matcha_batch *batch, const matcha_soft_cfg *soft,
+                             const matcha_march_cfg *march)
 {
-    (void)Kc;
-    if (!batch || batch->n_particles <= 0 || !batch->L_host || !batch->R_host) return 0;
-    // matcha_grad_template: one complex float32 template-gradient term per particle, laid out like f
-    size_t n = 0;
-    for (int p = 0; p < batch->n_particles; ++p) {
-        const int64_t e = matcha_f_elems(batch->L_host[p], batch->R_host[p]);
-        if (e < 0) return 0;
-        n += (size_t)e;
-    }
-    return n * 2 * sizeof(float);
-}
-
-matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
-                                    const float *w, float *C, matcha_precision prec, void *stream)
-{
+    (void)ctx;
+    (void)march;
     int lo, hi, rmax;
-    if (!ctx) return MATCHA_ERR_INVALID_ARG;
-    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
-    if (st != MATCHA_OK) return st;
-    if (batch->n_particles == 0) return MATCHA_OK;
-    st = assemble_check(batch, f, h, w, C, prec, hi, rmax);
-    if (st != MATCHA_OK) return st;
-    if (lo != hi) {
-        st = ensure_by_L(ctx, batch->n_particles);
-        if (st != MATCHA_OK) return st;
-    }
-    return assemble_ws(ctx, batch, f, h, w, C, prec, lo, hi, rmax, ctx->by_L, static_cast<hipStream_t>(stream));
+    if (check_batch(batch, &lo, &hi, &rmax) != MATCHA_OK || batch->n_particles == 0) return 0;
+    size_t need = std::max(assemble_ws_need(batch->n_particles, lo != hi), grad_ws_need(batch));
+    if (soft && soft->B >= 1 && soft->n_grid >= 4)
+        need = std::max(need, soft_ws_need(batch->n_particles, soft->n_grid, soft->B));
+    return need;
 }
 
-}  // extern "C"
-
-namespace {
-
-// Checks of a SOFFT search; on success *nt is the select kernel's workgroup size.
-matcha_status soft_check(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *cfg,
-                         const float *cand, const uint32_t *status, int *nt)
+matcha_status matcha_c_unpack(int32_t L, const float *C_wedge_host, float *C_byl_host)
 {
-    int lo, hi, rmax;
-    if (!ctx || !cfg) return MATCHA_ERR_INVALID_ARG;
-    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
-    if (st != MATCHA_OK) return st;
-    if (batch->n_particles == 0) return MATCHA_OK;
-    if (!C || !cand || !status || !aligned16(C) || !aligned16(cand)) return MATCHA_ERR_INVALID_ARG;
-    const int B = cfg->B, n = cfg->n_grid, Kc = cfg->Kc;
-    if (B < 1 || B > lo || B > 32 || n < 4 || n > 96 || Kc < 1 || Kc > MATCHA_MAX_KC) return MATCHA_ERR_INVALID_ARG;
-    *nt = ctx->tune.soft_threads ? ctx->tune.soft_threads : 256;
-    if (soft_grid_smem_bytes(n, B) > 160 * 1024 || soft_select_smem_bytes(n, *nt) > 160 * 1024)
-        return MATCHA_ERR_UNSUPPORTED;
-    st = ensure_tables(ctx, std::max(hi, B));
-    if (st != MATCHA_OK) return st;
-    return ensure_grid(ctx, B, n);
-}
-
-// The search proper over a grid workspace ws of ws_bytes (at least one particle's grid).
-matcha_status soft_search_ws(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *cfg,
-                             float *cand, uint32_t *status, int nt, float *ws, size_t ws_bytes, hipStream_t s)
-{
-    const int P = batch->n_particles, n = cfg->n_grid, B = cfg->B;
-    if (!ws || ws_bytes < soft_chunk(1, n, B).total) return MATCHA_ERR_INVALID_ARG;
-    size_t pcs = std::min<size_t>((size_t)P, ws_bytes / soft_particle_bytes(n, B));
-    while (pcs > 1 && soft_chunk(pcs, n, B).total > ws_bytes) --pcs;
-    const int pc = (int)std::max<size_t>(pcs, 1);
-    const SoftChunk ch = soft_chunk((size_t)pc, n, B);
-    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    char *base = reinterpret_cast<char *>(ws);
-    SoftArgs a;
-    std::memset(&a, 0, sizeof a);
-    a.C = reinterpret_cast<const float4 *>(C);
-    a.C_off = batch->C_offset;
-    a.dgrid = ctx->dgrid;
-    a.dft = ctx->dft;
-    a.pinfo = ctx->pinfo;
-    a.B = B;
-    a.n = n;
-    a.Kc = cfg->Kc;
-    a.grid = reinterpret_cast<float *>(base + ch.grid);
-    a.mlist = reinterpret_cast<unsigned long long *>(base + ch.list);
-    a.mcount = reinterpret_cast<uint32_t *>(base + ch.count);
-    a.S = reinterpret_cast<float2 *>(base + ch.S);
-    a.cand = reinterpret_cast<float4 *>(cand);
-    a.status = status;
-    for (int p0 = 0; p0 < P; p0 += pc) {
-        const int cnt = std::min(pc, P - p0);
-        a.p0 = p0;
-        if (launch_soft_wigner(a, cnt, s) != hipSuccess) return MATCHA_ERR_HIP;
-        if (launch_soft_grid(a, cnt, s) != hipSuccess) return MATCHA_ERR_HIP;
-        if (launch_soft_select(a, cnt, nt, s) != hipSuccess) return MATCHA_ERR_HIP;
+    if (L < 0 || L > MATCHA_MAX_L || !C_wedge_host || !C_byl_host) return MATCHA_ERR_INVALID_ARG;
+    typedef std::complex<float> cf;
+    const cf *wv = reinterpret_cast<const cf *>(C_wedge_host);
+    cf *out = reinterpret_cast<cf *>(C_byl_host);
+    for (int l = 0; l <= L; ++l) {
+        const int64_t blk = (int64_t)l * (4 * l * l - 1) / 3, w = 2 * l + 1;
+        std::vector<char> set((size_t)(w * w), 0);
+        auto put = [&](int m, int n, cf v) {
+            out[blk + (m + l) * w + (n + l)] = v;
+            set[(size_t)((m + l) * w + (n + l))] = 1;
+        };
+        for (int m = 0; m <= l; ++m)
+            for (int n = -m; n <= m; ++n) {
+                const int64_t q = (int64_t)m * m + m + n, at = 2 * (wedge_row(l) + q);
+                put(m, n, wv[at]);
+                const int pm = n >= 0 ? n : -n, pn = n >= 0 ? m : -m;
+                if (pm != m || pn != n) put(pm, pn, wv[at + 1]);
+            }
+        // the rest by C^l_{-m,-n} = (-1)^{m-n} conj(C^l_mn)
+        for (int m = -l; m <= l; ++m)
+            for (int n = -l; n <= l; ++n)
+                if (!set[(size_t)((m + l) * w + (n + l))]) {
+                    const cf v = std::conj(out[blk + (-m + l) * w + (-n + l)]);
+                    out[blk + (m + l) * w + (n + l)] = ((m - n) & 1) ? -v : v;
+                }
     }
     return MATCHA_OK;
 }
 
-}  // namespace
+matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg *cfg, int32_t *order_host)
+{
+    int lo, hi, rmax;
+    if (!cfg || !order_host || !cfg->levels || cfg->n_levels < 1) return MATCHA_ERR_INVALID_ARG;
+    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
+    if (st != MATCHA_OK) return st;
+    const int P = batch->n_particles;
+    std::vector<std::pair<double, int>> cost((size_t)P);
+    for (int p = 0; p < P; ++p) {
+        const int Lp = batch->L_host[p];
+        double c = 0.0;
+        for (int j = 0; j < cfg->n_levels; ++j)
+            if (cfg->levels[j] < Lp) c += (double)wedge_row(cfg->levels[j] + 1);
+        c += (double)wedge_row(Lp + 1);
+        cost[(size_t)p] = {-c, p};
+    }
+    std::stable_sort(cost.begin(), cost.end());
+    for (int p = 0; p < P; ++p) order_host[p] = cost[(size_t)p].second;
+    return MATCHA_OK;
+}
 
-extern "C" {
+matcha_status matcha_coeff_assemble(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
+                                    const float *w, float *C, matcha_precision prec, void *ws, size_t ws_bytes,
+                                    void *stream)
+{
+    int lo, hi, rmax;
+    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
+    if (st != MATCHA_OK) return st;
+    if (batch->n_particles == 0) return ctx ? MATCHA_OK : MATCHA_ERR_INVALID_ARG;
+    st = assemble_check(batch, f, h, w, C, prec, hi, rmax);
+    if (st != MATCHA_OK) return st;
+    const size_t need = assemble_ws_need(batch->n_particles, lo != hi);
+    if (need && (!ws || ws_bytes < need || !aligned16(ws))) return MATCHA_ERR_WORKSPACE;
+    if (!ctx) return MATCHA_ERR_INVALID_ARG;
+    return assemble_launch(ctx, batch, f, h, w, C, prec, lo, hi, rmax, static_cast<int32_t *>(ws),
+                           static_cast<hipStream_t>(stream));
+}
 
 matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
-                                 const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream)
+                                 const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *ws, size_t ws_bytes,
+                                 void *stream)
 {
     int nt = 0;
-    matcha_status st = soft_check(ctx, batch, C, cfg, cand, status, &nt);
+    const GridTables *gt = nullptr;
+    matcha_status st = soft_check(ctx, batch, C, cfg, cand, status, ws, ws_bytes, &nt, &gt);
     if (st != MATCHA_OK || batch->n_particles == 0) return st;
-    st = ensure_soft_ws(ctx, soft_ws_need(batch->n_particles, cfg->n_grid, cfg->B));
-    if (st != MATCHA_OK) return st;
-    return soft_search_ws(ctx, batch, C, cfg, cand, status, nt, ctx->soft_ws, ctx->soft_ws_bytes,
-                          static_cast<hipStream_t>(stream));
+    return soft_launch(ctx, batch, C, cfg, gt, cand, status, nt, ws, ws_bytes, static_cast<hipStream_t>(stream));
 }
 
 matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
                                   const matcha_march_cfg *cfg, int32_t Kc, float *cand, float *best,
-                                  int32_t *best_idx, uint32_t *status, void *stream)
+                                  int32_t *best_idx, uint32_t *status, void *ws, size_t ws_bytes, void *stream)
 {
+    (void)ws;
+    (void)ws_bytes;
     int lo, hi, rmax;
     if (!ctx || !cfg) return MATCHA_ERR_INVALID_ARG;
     matcha_status st = check_batch(batch, &lo, &hi, &rmax);
@@ -587,19 +688,13 @@ matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, co
     if (batch->n_particles == 0) return MATCHA_OK;
     if (!C || !cand || !best || !best_idx || !status || !aligned16(C) || !aligned16(cand) || !aligned16(best))
         return MATCHA_ERR_INVALID_ARG;
-    if (Kc < 1 || Kc > MATCHA_MAX_KC || cfg->steps < 0 || cfg->n_levels < 1 || cfg->n_levels > MATCHA_MAX_LEVELS ||
-        !cfg->levels || !(cfg->max_step >= 0.0) || lo < 1)
-        return MATCHA_ERR_INVALID_ARG;
-    for (int j = 0; j < cfg->n_levels; ++j) {
-        if (cfg->levels[j] < 1 || cfg->levels[j] > MATCHA_MAX_L) return MATCHA_ERR_INVALID_ARG;
-        if (j > 0 && cfg->levels[j] <= cfg->levels[j - 1]) return MATCHA_ERR_INVALID_ARG;
-    }
-    st = ensure_tables(ctx, hi);
+    st = march_check(batch, cfg, Kc, lo);
     if (st != MATCHA_OK) return st;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     MarchArgs a;
     std::memset(&a, 0, sizeof a);
     a.C = reinterpret_cast<const float4 *>(C);
+    a.C_fin = reinterpret_cast<const float4 *>(cfg->C_final);
     a.C_off = batch->C_offset;
     a.Lp = batch->L_dev;
     a.tab = ctx->tab;
@@ -634,9 +729,7 @@ matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const 
     if (st != MATCHA_OK) return st;
     if (batch->n_particles == 0) return MATCHA_OK;
     if (!C || !theta || !out || !aligned16(C) || !aligned16(theta)) return MATCHA_ERR_INVALID_ARG;
-    if (L_eval < 0 || L_eval > lo) return MATCHA_ERR_INVALID_ARG;  /* 0: each particle's own L_p */
-    st = ensure_tables(ctx, std::max(hi, L_eval));
-    if (st != MATCHA_OK) return st;
+    if (L_eval < 0 || L_eval > lo) return MATCHA_ERR_INVALID_ARG; /* 0: each particle's own L_p */
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     EvalArgs a;
     a.C = reinterpret_cast<const float4 *>(C);
@@ -654,19 +747,18 @@ matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const 
 
 matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, const float *f, const float *h,
                                    const float *w, const float *best, const float *g, float *grad_h, float *grad_f,
-                                   void *ws, size_t ws_bytes, void *stream)
+                                   matcha_precision prec, void *ws, size_t ws_bytes, void *stream)
 {
     int lo, hi, rmax;
-    if (!ctx) return MATCHA_ERR_INVALID_ARG;
     matcha_status st = check_batch(batch, &lo, &hi, &rmax);
     if (st != MATCHA_OK) return st;
-    if (batch->n_particles == 0) return MATCHA_OK;
+    if (prec != MATCHA_FP32) return MATCHA_ERR_UNSUPPORTED;
+    if (batch->n_particles == 0) return ctx ? MATCHA_OK : MATCHA_ERR_INVALID_ARG;
     if (!f || !h || !w || !best || !g || !batch->f_offset || !aligned16(best)) return MATCHA_ERR_INVALID_ARG;
+    if (grad_h && (!ws || !aligned16(ws) || ws_bytes < grad_ws_need(batch))) return MATCHA_ERR_WORKSPACE;
+    if (!ctx) return MATCHA_ERR_INVALID_ARG;
     if (!grad_h && !grad_f) return MATCHA_OK;
-    if (grad_h && (!ws || ws_bytes < matcha_workspace_size(batch, 0))) return MATCHA_ERR_WORKSPACE;
     if (grad_smem_bytes(hi) > 160 * 1024) return MATCHA_ERR_UNSUPPORTED;
-    st = ensure_tables(ctx, hi);
-    if (st != MATCHA_OK) return st;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     GradArgs a;
     std::memset(&a, 0, sizeof a);
@@ -684,96 +776,85 @@ matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, c
     a.g = g;
     a.grad_f = reinterpret_cast<float2 *>(grad_f);
     a.grad_h = reinterpret_cast<float2 *>(grad_h);
-    a.ws = grad_h ? static_cast<float2 *>(ws) : nullptr;
+    if (grad_h) {
+        char *base = static_cast<char *>(ws);
+        a.ws_off = reinterpret_cast<int64_t *>(base);
+        a.ws = reinterpret_cast<float2 *>(base + align256(sizeof(int64_t) * (size_t)a.P));
+    }
     a.pinfo = ctx->pinfo;
     a.tab = ctx->tab;
     return launched(launch_grad(a, static_cast<hipStream_t>(stream)));
 }
 
-matcha_status matcha_lpt_order(const matcha_batch *batch, const matcha_march_cfg *cfg, int32_t *order_host)
-{
-    int lo, hi, rmax;
-    if (!cfg || !order_host || !cfg->levels || cfg->n_levels < 1) return MATCHA_ERR_INVALID_ARG;
-    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
-    if (st != MATCHA_OK) return st;
-    const int P = batch->n_particles;
-    std::vector<std::pair<double, int>> cost((size_t)P);
-    for (int p = 0; p < P; ++p) {
-        const int Lp = batch->L_host[p];
-        double c = 0.0;
-        for (int j = 0; j < cfg->n_levels; ++j)
-            if (cfg->levels[j] < Lp) c += (double)wedge_row(cfg->levels[j] + 1);
-        c += (double)wedge_row(Lp + 1);
-        cost[(size_t)p] = {-c, p};
-    }
-    std::stable_sort(cost.begin(), cost.end());
-    for (int p = 0; p < P; ++p) order_host[p] = cost[(size_t)p].second;
-    return MATCHA_OK;
-}
-
 struct matcha_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    float *soft_ws = nullptr;  // the graph's own SOFFT grid workspace (the context's may be regrown)
-    int32_t *by_L = nullptr;   // the graph's own particle order for the assembly (mixed L_p)
-    int device = 0;
 };
 
-matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *batch, const void *f, const void *h,
-                                        const float *w, float *C, matcha_precision prec, const matcha_soft_cfg *soft,
-                                        const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
-                                        uint32_t *status, matcha_graph **out)
+matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *batch, const matcha_align_bufs *bufs,
+                                        const matcha_soft_cfg *soft, const matcha_march_cfg *march, void *ws,
+                                        size_t ws_bytes, matcha_graph **out)
 {
     int lo, hi, rmax;
-    if (!ctx || !soft || !march || !out) return MATCHA_ERR_INVALID_ARG;
+    if (!ctx || !bufs || !soft || !march || !out) return MATCHA_ERR_INVALID_ARG;
     matcha_status st = check_batch(batch, &lo, &hi, &rmax);
     if (st != MATCHA_OK) return st;
-    // build every table now: nothing may allocate while the stream is being captured
-    st = ensure_tables(ctx, std::max(hi, soft->B));
-    if (st != MATCHA_OK) return st;
+    const bool fin = bufs->f32 || bufs->h32;
+    if (fin && (!bufs->f32 || !bufs->h32 || !bufs->C32)) return MATCHA_ERR_INVALID_ARG;
+    const int P = batch->n_particles;
     int nt = 0;
-    st = soft_check(ctx, batch, C, soft, cand, status, &nt);
+    const GridTables *gt = nullptr;
+    st = soft_check(ctx, batch, bufs->C, soft, bufs->cand, bufs->status, ws, ws_bytes, &nt, &gt);
     if (st != MATCHA_OK) return st;
+    if (P > 0) {
+        st = assemble_check(batch, bufs->f, bufs->h, bufs->w, bufs->C, bufs->prec, hi, rmax);
+        if (st == MATCHA_OK && fin) st = assemble_check(batch, bufs->f32, bufs->h32, bufs->w, bufs->C32, MATCHA_FP32, hi, rmax);
+        if (st != MATCHA_OK) return st;
+        if (ws_bytes < assemble_ws_need(P, lo != hi)) return MATCHA_ERR_WORKSPACE;
+    }
+    matcha_march_cfg mc = *march;
+    mc.C_final = fin ? bufs->C32 : nullptr;
+    if (P > 0) {
+        st = march_check(batch, &mc, soft->Kc, lo);
+        if (st != MATCHA_OK) return st;
+    }
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     matcha_graph *g = new (std::nothrow) matcha_graph();
     if (!g) return MATCHA_ERR_HIP;
-    g->device = ctx->device;
-    const int P = batch->n_particles;
-    const size_t ws_bytes = P > 0 ? soft_ws_need(P, soft->n_grid, soft->B) : 0;
-    if (P > 0 && hipMalloc(&g->soft_ws, ws_bytes) != hipSuccess) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
         delete g;
         return MATCHA_ERR_HIP;
     }
-    auto fail = [&](matcha_status e) {
-        if (g->soft_ws) (void)hipFree(g->soft_ws);
-        if (g->by_L) (void)hipFree(g->by_L);
-        delete g;
-        return e;
-    };
-    if (P > 0 && lo != hi && hipMalloc(&g->by_L, sizeof(int32_t) * (size_t)P) != hipSuccess) return fail(MATCHA_ERR_HIP);
-    if (P > 0) {
-        st = assemble_check(batch, f, h, w, C, prec, hi, rmax);
-        if (st != MATCHA_OK) return fail(st);
-    }
-    hipStream_t cs = nullptr;
-    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) return fail(MATCHA_ERR_HIP);
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
         (void)hipStreamDestroy(cs);
-        return fail(MATCHA_ERR_HIP);
+        delete g;
+        return MATCHA_ERR_HIP;
     }
-    if (P > 0) st = assemble_ws(ctx, batch, f, h, w, C, prec, lo, hi, rmax, g->by_L, cs);
-    if (st == MATCHA_OK && P > 0) st = soft_search_ws(ctx, batch, C, soft, cand, status, nt, g->soft_ws, ws_bytes, cs);
-    if (st == MATCHA_OK) st = matcha_march_newton(ctx, batch, C, march, soft->Kc, cand, best, best_idx, status, cs);
+    if (P > 0) {
+        st = assemble_launch(ctx, batch, bufs->f, bufs->h, bufs->w, bufs->C, bufs->prec, lo, hi, rmax,
+                             static_cast<int32_t *>(ws), cs);
+        if (st == MATCHA_OK && fin)
+            st = assemble_launch(ctx, batch, bufs->f32, bufs->h32, bufs->w, bufs->C32, MATCHA_FP32, lo, hi, rmax,
+                                 static_cast<int32_t *>(ws), cs);
+        if (st == MATCHA_OK)
+            st = soft_launch(ctx, batch, bufs->C, soft, gt, bufs->cand, bufs->status, nt, ws, ws_bytes, cs);
+        if (st == MATCHA_OK)
+            st = matcha_march_newton(ctx, batch, bufs->C, &mc, soft->Kc, bufs->cand, bufs->best, bufs->best_idx,
+                                     bufs->status, nullptr, 0, cs);
+    }
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &graph);
     (void)hipStreamDestroy(cs);
     if (st != MATCHA_OK || ec != hipSuccess) {
         if (graph) (void)hipGraphDestroy(graph);
-        return fail(st != MATCHA_OK ? st : MATCHA_ERR_HIP);
+        delete g;
+        return st != MATCHA_OK ? st : MATCHA_ERR_HIP;
     }
     if (hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess) {
         (void)hipGraphDestroy(graph);
-        return fail(MATCHA_ERR_HIP);
+        delete g;
+        return MATCHA_ERR_HIP;
     }
     g->graph = graph;
     *out = g;
@@ -791,21 +872,25 @@ matcha_status matcha_graph_destroy(matcha_graph *g)
     if (!g) return MATCHA_ERR_INVALID_ARG;
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    if (g->soft_ws || g->by_L) {
-        (void)hipSetDevice(g->device);
-        (void)hipDeviceSynchronize();  // replays may still read them
-        if (g->soft_ws) (void)hipFree(g->soft_ws);
-        if (g->by_L) (void)hipFree(g->by_L);
-    }
     delete g;
     return MATCHA_OK;
 }
 
 matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *soft,
                               const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
-                              uint32_t *status, int32_t reps, matcha_tuning *best_tuning)
+                              uint32_t *status, int32_t reps, void *ws, size_t ws_bytes, matcha_tuning *best_tuning)
 {
+    int lo, hi, rmax;
     if (!ctx || !soft || !march || !best_tuning || reps < 1) return MATCHA_ERR_INVALID_ARG;
+    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
+    if (st != MATCHA_OK) return st;
+    const std::string key = tune_key(ctx, batch, soft, march);
+    const auto hit = ctx->tune_cache.find(key);
+    if (hit != ctx->tune_cache.end()) {
+        st = matcha_set_tuning(ctx, &hit->second);
+        if (st == MATCHA_OK) *best_tuning = ctx->tune;
+        return st;
+    }
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     hipStream_t s = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return MATCHA_ERR_HIP;
@@ -815,7 +900,6 @@ matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const 
         return MATCHA_ERR_HIP;
     }
     const matcha_tuning saved = ctx->tune;
-    matcha_status st = MATCHA_OK;
     auto time_it = [&](auto &&run, float *ms) -> matcha_status {
         matcha_status r = run();  // warm-up
         if (r != MATCHA_OK) return r;
@@ -831,7 +915,7 @@ matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const 
     for (int nt : {256, 512}) {
         ctx->tune.soft_threads = nt;
         float ms = 0.f;
-        st = time_it([&] { return matcha_soft_search(ctx, batch, C, soft, cand, status, s); }, &ms);
+        st = time_it([&] { return matcha_soft_search(ctx, batch, C, soft, cand, status, ws, ws_bytes, s); }, &ms);
         if (st == MATCHA_ERR_UNSUPPORTED) {  // this shape does not fit the workgroup's LDS
             st = MATCHA_OK;
             continue;
@@ -852,8 +936,9 @@ matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const 
         float ms = 0.f;
         st = time_it(
             [&] {
-                matcha_status r = matcha_soft_search(ctx, batch, C, soft, cand, status, s);
-                return r == MATCHA_OK ? matcha_march_newton(ctx, batch, C, march, soft->Kc, cand, best, best_idx, status, s)
+                matcha_status r = matcha_soft_search(ctx, batch, C, soft, cand, status, ws, ws_bytes, s);
+                return r == MATCHA_OK ? matcha_march_newton(ctx, batch, C, march, soft->Kc, cand, best, best_idx,
+                                                            status, nullptr, 0, s)
                                       : r;
             },
             &ms);
@@ -867,6 +952,10 @@ matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const 
     (void)hipStreamSynchronize(s);
     (void)hipStreamDestroy(s);
     ctx->tune = st == MATCHA_OK ? best_t : saved;
+    if (st == MATCHA_OK) {
+        ctx->tune_cache[key] = ctx->tune;
+        (void)tune_cache_store(ctx, key, ctx->tune);  // best effort: the context keeps the result either way
+    }
     *best_tuning = ctx->tune;
     return st;
 }

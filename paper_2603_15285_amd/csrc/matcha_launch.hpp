@@ -57,6 +57,7 @@ struct SoftArgs {
 
 struct MarchArgs {
     const float4 *C;          // wedge layout, float4 = (C^l_mn, C^l_partner)
+    const float4 *C_fin;      // nullable: coefficients of each particle's final level (same offsets as C)
     const int64_t *C_off;     // complex offsets (even)
     const int32_t *Lp;
     const float4 *tab;        // per (l, q): A = abar_{l-1}, AC = abar_{l-1} c_{l-1}, PW = w P_l, PWT = w~ s P_l
@@ -101,7 +102,8 @@ struct GradArgs {
     const float4 *best;
     const float *g;
     float2 *grad_f;           // may be null
-    float2 *ws;               // per-particle grad_h terms, laid out like f (null if grad_h is null)
+    float2 *ws;               // per-particle grad_h terms at ws_off[p] (null if grad_h is null)
+    int64_t *ws_off;          // [P] packed offsets of the terms, written by the first kernel
     float2 *grad_h;           // may be null
     const PairInfo *pinfo;
     const float4 *tab;

@@ -17,7 +17,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmatcha.so")
 
-OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_WORKSPACE = 0, -1, -2, -3, -4
+OK, ERR_INVALID_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_WORKSPACE, ERR_NOT_PREPARED = 0, -1, -2, -3, -4, -5
 FP32, BF16_FP32ACC = 0, 1
 ST_NONFINITE, ST_INDEFINITE, ST_SINGULAR, ST_NEAR_POLE, ST_FEW_MAXIMA, ST_EARLY_STOP = 1, 2, 4, 8, 16, 32
 MAX_L, MAX_KC, MAX_LEVELS = 64, 64, 16
@@ -26,7 +26,7 @@ EXPORTED = ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_status_
             "matcha_get_tuning", "matcha_c_elems", "matcha_f_elems", "matcha_workspace_size", "matcha_lpt_order",
             "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton", "matcha_evaluate",
             "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch", "matcha_graph_destroy",
-            "matcha_autotune"]
+            "matcha_autotune", "matcha_c_unpack"]
 
 
 class MatchaError(RuntimeError):
@@ -52,7 +52,13 @@ class _MarchCfg(ct.Structure):
     _fields_ = [("levels", ct.POINTER(ct.c_int32)), ("n_levels", ct.c_int32), ("steps", ct.c_int32),
                 ("max_step", ct.c_double), ("early_stop", ct.c_int32),
                 ("tol_grad", ct.c_double), ("tol_step", ct.c_double), ("tol_rel", ct.c_double),
-                ("fp64_above", ct.c_int32)]
+                ("fp64_above", ct.c_int32), ("C_final", ct.c_void_p)]
+
+
+class _AlignBufs(ct.Structure):
+    _fields_ = [("f", ct.c_void_p), ("h", ct.c_void_p), ("w", ct.c_void_p), ("prec", ct.c_int),
+                ("f32", ct.c_void_p), ("h32", ct.c_void_p), ("C", ct.c_void_p), ("C32", ct.c_void_p),
+                ("cand", ct.c_void_p), ("best", ct.c_void_p), ("best_idx", ct.c_void_p), ("status", ct.c_void_p)]
 
 
 _lib = None
@@ -67,9 +73,9 @@ def lib():
         L = ct.CDLL(LIB_PATH)
         vp, i32, i64, sz = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_size_t
         bp = ct.POINTER(_Batch)
-        L.matcha_create.argtypes = [ct.c_int, ct.POINTER(vp)]
+        L.matcha_create.argtypes = [ct.c_int, ct.c_char_p, ct.POINTER(vp)]
         L.matcha_destroy.argtypes = [vp]
-        L.matcha_prepare.argtypes = [vp, i32, i32, i32]
+        L.matcha_prepare.argtypes = [vp, i32, i32]
         L.matcha_status_string.argtypes = [ct.c_int]
         L.matcha_status_string.restype = ct.c_char_p
         L.matcha_set_tuning.argtypes = [vp, ct.POINTER(_Tuning)]
@@ -78,24 +84,25 @@ def lib():
         L.matcha_c_elems.restype = i64
         L.matcha_f_elems.argtypes = [i32, i32]
         L.matcha_f_elems.restype = i64
-        L.matcha_workspace_size.argtypes = [bp, i32]
+        L.matcha_workspace_size.argtypes = [vp, bp, ct.POINTER(_SoftCfg), ct.POINTER(_MarchCfg)]
         L.matcha_workspace_size.restype = sz
-        L.matcha_coeff_assemble.argtypes = [vp, bp, vp, vp, vp, vp, ct.c_int, vp]
-        L.matcha_soft_search.argtypes = [vp, bp, vp, ct.POINTER(_SoftCfg), vp, vp, vp]
-        L.matcha_march_newton.argtypes = [vp, bp, vp, ct.POINTER(_MarchCfg), i32, vp, vp, vp, vp, vp]
+        L.matcha_coeff_assemble.argtypes = [vp, bp, vp, vp, vp, vp, ct.c_int, vp, sz, vp]
+        L.matcha_soft_search.argtypes = [vp, bp, vp, ct.POINTER(_SoftCfg), vp, vp, vp, sz, vp]
+        L.matcha_march_newton.argtypes = [vp, bp, vp, ct.POINTER(_MarchCfg), i32, vp, vp, vp, vp, vp, sz, vp]
         L.matcha_evaluate.argtypes = [vp, bp, vp, i32, i32, vp, vp, vp]
-        L.matcha_grad_template.argtypes = [vp, bp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+        L.matcha_grad_template.argtypes = [vp, bp, vp, vp, vp, vp, vp, vp, vp, ct.c_int, vp, sz, vp]
         L.matcha_lpt_order.argtypes = [bp, ct.POINTER(_MarchCfg), ct.POINTER(ct.c_int32)]
-        L.matcha_align_graph_create.argtypes = [vp, bp, vp, vp, vp, vp, ct.c_int, ct.POINTER(_SoftCfg),
-                                                ct.POINTER(_MarchCfg), vp, vp, vp, vp, ct.POINTER(vp)]
+        L.matcha_c_unpack.argtypes = [i32, vp, vp]
+        L.matcha_align_graph_create.argtypes = [vp, bp, ct.POINTER(_AlignBufs), ct.POINTER(_SoftCfg),
+                                                ct.POINTER(_MarchCfg), vp, sz, ct.POINTER(vp)]
         L.matcha_graph_launch.argtypes = [vp, vp]
         L.matcha_graph_destroy.argtypes = [vp]
         L.matcha_autotune.argtypes = [vp, bp, vp, ct.POINTER(_SoftCfg), ct.POINTER(_MarchCfg), vp, vp, vp, vp, i32,
-                                      ct.POINTER(_Tuning)]
+                                      vp, sz, ct.POINTER(_Tuning)]
         for name in ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_set_tuning", "matcha_get_tuning",
                      "matcha_lpt_order", "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton",
                      "matcha_evaluate", "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch",
-                     "matcha_graph_destroy", "matcha_autotune"]:
+                     "matcha_graph_destroy", "matcha_autotune", "matcha_c_unpack"]:
             getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -130,17 +137,33 @@ def _need(t: torch.Tensor, dtype, name: str):
 
 
 class Context:
-    """A libmatcha context on one device (owns the read-only recurrence tables)."""
+    """A libmatcha context on one device (owns the read-only tables and the tuning).
 
-    def __init__(self, device: int | None = None):
+    As the caller of the C ABI, this object also owns a workspace tensor that the eager calls
+    share (grown on demand; torch orders its reuse on the current stream)."""
+
+    def __init__(self, device: int | None = None, tune_cache: str | None = None):
         dev = torch.cuda.current_device() if device is None else int(device)
         h = ct.c_void_p()
-        _check(lib().matcha_create(dev, ct.byref(h)), "matcha_create")
+        _check(lib().matcha_create(dev, tune_cache.encode() if tune_cache else None, ct.byref(h)), "matcha_create")
         self.handle = h
         self.device = dev
+        self._prepared = set()
+        self._ws = None
 
-    def prepare(self, L_max: int, B: int = 0, n_grid: int = 0):
-        _check(lib().matcha_prepare(self.handle, L_max, B, n_grid), "matcha_prepare")
+    def prepare(self, B: int, n_grid: int):
+        """SOFFT node tables for band B on an n_grid^3 grid (synchronous; needed before capture)."""
+        if (B, n_grid) not in self._prepared:
+            _check(lib().matcha_prepare(self.handle, int(B), int(n_grid)), "matcha_prepare")
+            self._prepared.add((B, n_grid))
+
+    def workspace(self, nbytes: int) -> torch.Tensor | None:
+        """A device buffer of at least nbytes (None for 0), reused by later eager calls."""
+        if nbytes <= 0:
+            return None
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
+        return self._ws
 
     def set_tuning(self, march_nc: int = 0, soft_threads: int = 0):
         t = _Tuning(int(march_nc), int(soft_threads))
@@ -225,13 +248,28 @@ class Batch:
         return order
 
 
-def _march_cfg(levels, steps, max_step=0.0, early_stop=False, tol_grad=1e-6, tol_step=1e-7, tol_rel=1e-7,
-               fp64_above=0):
+# Early-stopping tolerances (Sec. 2.4): the oracle's defaults, so that both sides stop at the same
+# tests unless a caller chooses otherwise.
+TOL_GRAD, TOL_STEP, TOL_REL = 1e-9, 1e-10, 1e-13
+
+
+def _march_cfg(levels, steps, max_step=0.0, early_stop=False, tol_grad=TOL_GRAD, tol_step=TOL_STEP, tol_rel=TOL_REL,
+               fp64_above=0, C_final=None):
     lv = np.ascontiguousarray(levels, dtype=np.int32)
     cfg = _MarchCfg(lv.ctypes.data_as(ct.POINTER(ct.c_int32)), len(lv), int(steps), float(max_step),
-                    int(early_stop), float(tol_grad), float(tol_step), float(tol_rel), int(fp64_above))
+                    int(early_stop), float(tol_grad), float(tol_step), float(tol_rel), int(fp64_above),
+                    None if C_final is None else C_final.data_ptr())
     cfg._keep = lv  # the levels array must outlive the struct
     return cfg
+
+
+def workspace_bytes(batch: "Batch", B: int = 0, n_grid: int = 0, ctx: "Context | None" = None) -> int:
+    """matcha_workspace_size: bytes with which every call on this batch runs in one pass (the SOFFT
+    share only when B and n_grid are given)."""
+    bs = batch.c_struct()
+    soft = _SoftCfg(int(B), int(n_grid), 1) if B and n_grid else None
+    return int(lib().matcha_workspace_size(ctx.handle if ctx else None, ct.byref(bs),
+                                           ct.byref(soft) if soft is not None else None, None))
 
 
 def coeff_assemble(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch.Tensor,
@@ -242,7 +280,9 @@ def coeff_assemble(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor,
         C = torch.empty(2 * batch.c_total, dtype=torch.float32, device=f.device)
     _need(C, torch.float32, "C")
     bs = batch.c_struct()
-    _check(lib().matcha_coeff_assemble(ctx.handle, ct.byref(bs), _ptr(f), _ptr(h), _ptr(w), _ptr(C), prec,
+    nb = workspace_bytes(batch) if int(batch.L.min(initial=0)) != int(batch.L.max(initial=0)) else 0
+    ws = ctx.workspace(nb)
+    _check(lib().matcha_coeff_assemble(ctx.handle, ct.byref(bs), _ptr(f), _ptr(h), _ptr(w), _ptr(C), prec, _ptr(ws), nb,
                                        ct.c_void_p(_stream(stream))), "matcha_coeff_assemble")
     return C
 
@@ -254,27 +294,33 @@ def soft_search(ctx: Context, batch: Batch, C: torch.Tensor, B: int, n_grid: int
     if status is None:
         status = torch.empty(batch.n, dtype=torch.int32, device=C.device)
     _need(cand, torch.float32, "cand")
+    ctx.prepare(B, n_grid)
     bs = batch.c_struct()
     cfg = _SoftCfg(B, n_grid, Kc)
+    nb = workspace_bytes(batch, B, n_grid)
+    ws = ctx.workspace(nb)
     _check(lib().matcha_soft_search(ctx.handle, ct.byref(bs), _ptr(C), ct.byref(cfg), _ptr(cand), _ptr(status),
-                                    ct.c_void_p(_stream(stream))), "matcha_soft_search")
+                                    _ptr(ws), nb, ct.c_void_p(_stream(stream))), "matcha_soft_search")
     return cand, status
 
 
 def march_newton(ctx: Context, batch: Batch, C: torch.Tensor, levels: Sequence[int], steps: int,
                  cand: torch.Tensor, status: torch.Tensor, best: torch.Tensor | None = None,
                  best_idx: torch.Tensor | None = None, max_step: float = 0.0, early_stop: bool = False,
-                 tol_grad: float = 1e-6, tol_step: float = 1e-7, tol_rel: float = 1e-7, fp64_above: int = 0,
-                 stream=None):
+                 tol_grad: float = TOL_GRAD, tol_step: float = TOL_STEP, tol_rel: float = TOL_REL, fp64_above: int = 0,
+                 C_final: torch.Tensor | None = None, stream=None):
+    """C_final (same layout as C): coefficients for each particle's final level (None: C)."""
     Kc = int(cand.shape[1])
     if best is None:
         best = torch.empty((batch.n, 4), dtype=torch.float32, device=C.device)
     if best_idx is None:
         best_idx = torch.empty(batch.n, dtype=torch.int32, device=C.device)
-    cfg = _march_cfg(levels, steps, max_step, early_stop, tol_grad, tol_step, tol_rel, fp64_above)
+    if C_final is not None:
+        _need(C_final, torch.float32, "C_final")
+    cfg = _march_cfg(levels, steps, max_step, early_stop, tol_grad, tol_step, tol_rel, fp64_above, C_final)
     bs = batch.c_struct()
     _check(lib().matcha_march_newton(ctx.handle, ct.byref(bs), _ptr(C), ct.byref(cfg), Kc, _ptr(cand), _ptr(best),
-                                     _ptr(best_idx), _ptr(status), ct.c_void_p(_stream(stream))),
+                                     _ptr(best_idx), _ptr(status), None, 0, ct.c_void_p(_stream(stream))),
            "matcha_march_newton")
     return best, best_idx, status
 
@@ -290,11 +336,6 @@ def evaluate(ctx: Context, batch: Batch, C: torch.Tensor, L_eval: int, theta: to
     return out
 
 
-def workspace_bytes(batch: Batch, Kc: int = 0) -> int:
-    bs = batch.c_struct()
-    return int(lib().matcha_workspace_size(ct.byref(bs), int(Kc)))
-
-
 def grad_template(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch.Tensor,
                   best: torch.Tensor, g: torch.Tensor, want_h: bool = True, want_f: bool = True, stream=None):
     """Adjoint of sum_p g_p C_{L_p}(R_p*) at fixed rotations: (grad_h, grad_f), each None if not wanted.
@@ -303,14 +344,11 @@ def grad_template(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, 
     _need(g, torch.float32, "g")
     gh = torch.empty_like(h) if want_h else None
     gf = torch.empty_like(f) if want_f else None
-    ws = None
-    nbytes = 0
-    if want_h:
-        nbytes = workspace_bytes(batch)
-        ws = torch.empty(max(nbytes // 4, 1), dtype=torch.float32, device=f.device)
+    nbytes = workspace_bytes(batch) if want_h else 0
+    ws = ctx.workspace(nbytes)
     bs = batch.c_struct()
     _check(lib().matcha_grad_template(ctx.handle, ct.byref(bs), _ptr(f), _ptr(h), _ptr(w), _ptr(best), _ptr(g),
-                                      _ptr(gh), _ptr(gf), _ptr(ws), nbytes, ct.c_void_p(_stream(stream))),
+                                      _ptr(gh), _ptr(gf), FP32, _ptr(ws), nbytes, ct.c_void_p(_stream(stream))),
            "matcha_grad_template")
     return gh, gf
 
@@ -338,41 +376,62 @@ class Objective(torch.autograd.Function):
 
 def align(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch.Tensor, B: int, n_grid: int,
           Kc: int, levels: Sequence[int], steps: int, max_step: float = 0.0, fp64_above: int = 0,
+          prec: int = FP32, f32: torch.Tensor | None = None, h32: torch.Tensor | None = None,
+          early_stop: bool = False, tol_grad: float = TOL_GRAD, tol_step: float = TOL_STEP, tol_rel: float = TOL_REL,
           bufs: dict | None = None, stream=None):
-    """The whole path: assembly, SOFFT search, march and selection.  Returns (best, best_idx, status)."""
+    """The whole path: assembly, SOFFT search, march and selection.  Returns (best, best_idx, status).
+
+    prec = BF16_FP32ACC with f32 / h32 given: the final level marches on FP32-assembled coefficients."""
     b = {} if bufs is None else bufs
-    C = coeff_assemble(ctx, batch, f, h, w, C=b.get("C"), stream=stream)
+    C = coeff_assemble(ctx, batch, f, h, w, C=b.get("C"), prec=prec, stream=stream)
+    C32 = None
+    if f32 is not None or h32 is not None:
+        C32 = coeff_assemble(ctx, batch, f32, h32, w, C=b.get("C32"), prec=FP32, stream=stream)
     cand, status = soft_search(ctx, batch, C, B, n_grid, Kc, cand=b.get("cand"), status=b.get("status"),
                                stream=stream)
     best, best_idx, status = march_newton(ctx, batch, C, levels, steps, cand, status, best=b.get("best"),
-                                          best_idx=b.get("best_idx"), max_step=max_step, fp64_above=fp64_above,
-                                          stream=stream)
+                                          best_idx=b.get("best_idx"), max_step=max_step, early_stop=early_stop,
+                                          tol_grad=tol_grad, tol_step=tol_step, tol_rel=tol_rel,
+                                          fp64_above=fp64_above, C_final=C32, stream=stream)
     if bufs is not None:
         bufs.update(C=C, cand=cand, status=status, best=best, best_idx=best_idx)
+        if C32 is not None:
+            bufs.update(C32=C32)
     return best, best_idx, status
 
 
 class AlignGraph:
-    """The whole path (assembly, SOFFT search, march) for fixed buffers, captured once into a HIP
-    graph and replayed with one launch."""
+    """The whole path (assembly, SOFFT search, march) for fixed buffers and a workspace of its own,
+    captured once into a HIP graph (matcha_align_graph_create) and replayed with one launch.
+
+    prec = BF16_FP32ACC with f32 / h32: the graph also assembles FP32 coefficients from f32 / h32
+    and marches each particle's final level on them."""
 
     def __init__(self, ctx: Context, batch: Batch, f, h, w, B: int, n_grid: int, Kc: int, levels, steps: int,
-                 prec: int = FP32, fp64_above: int = 0):
+                 prec: int = FP32, fp64_above: int = 0, f32=None, h32=None):
         dev = f.device
+        ctx.prepare(B, n_grid)
+        fin = f32 is not None
         self.bufs = dict(C=torch.empty(2 * batch.c_total, dtype=torch.float32, device=dev),
+                         C32=torch.empty(2 * batch.c_total, dtype=torch.float32, device=dev) if fin else None,
                          cand=torch.empty((batch.n, Kc, 4), dtype=torch.float32, device=dev),
                          status=torch.empty(batch.n, dtype=torch.int32, device=dev),
                          best=torch.empty((batch.n, 4), dtype=torch.float32, device=dev),
                          best_idx=torch.empty(batch.n, dtype=torch.int32, device=dev))
-        self._keep = (ctx, batch, f, h, w)
+        nb = workspace_bytes(batch, B, n_grid)
+        self.ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=dev)
+        self._keep = (ctx, batch, f, h, w, f32, h32)
         self._bs = batch.c_struct()
         self._soft = _SoftCfg(B, n_grid, Kc)
         self._march = _march_cfg(levels, steps, fp64_above=fp64_above)
-        g = ct.c_void_p()
         b = self.bufs
-        _check(lib().matcha_align_graph_create(ctx.handle, ct.byref(self._bs), _ptr(f), _ptr(h), _ptr(w), _ptr(b["C"]),
-                                               prec, ct.byref(self._soft), ct.byref(self._march), _ptr(b["cand"]),
-                                               _ptr(b["best"]), _ptr(b["best_idx"]), _ptr(b["status"]), ct.byref(g)),
+        self._io = _AlignBufs(f.data_ptr(), h.data_ptr(), w.data_ptr(), int(prec),
+                              f32.data_ptr() if fin else None, h32.data_ptr() if fin else None,
+                              b["C"].data_ptr(), b["C32"].data_ptr() if fin else None, b["cand"].data_ptr(),
+                              b["best"].data_ptr(), b["best_idx"].data_ptr(), b["status"].data_ptr())
+        g = ct.c_void_p()
+        _check(lib().matcha_align_graph_create(ctx.handle, ct.byref(self._bs), ct.byref(self._io), ct.byref(self._soft),
+                                               ct.byref(self._march), _ptr(self.ws), nb, ct.byref(g)),
                "matcha_align_graph_create")
         self.handle = g
 
@@ -394,19 +453,35 @@ class AlignGraph:
 
 def autotune(ctx: Context, batch: Batch, C: torch.Tensor, B: int, n_grid: int, Kc: int, levels, steps: int,
              reps: int = 2, fp64_above: int = 0) -> dict:
-    """Times the supported launch shapes on this batch and keeps the fastest in the context."""
+    """Times the supported launch shapes on this batch and keeps the fastest in the context (or
+    applies the context's tune cache entry for this batch and configuration)."""
     dev = C.device
+    ctx.prepare(B, n_grid)
     cand = torch.empty((batch.n, Kc, 4), dtype=torch.float32, device=dev)
     status = torch.empty(batch.n, dtype=torch.int32, device=dev)
     best = torch.empty((batch.n, 4), dtype=torch.float32, device=dev)
     best_idx = torch.empty(batch.n, dtype=torch.int32, device=dev)
     soft = _SoftCfg(B, n_grid, Kc)
     march = _march_cfg(levels, steps, fp64_above=fp64_above)
+    nb = workspace_bytes(batch, B, n_grid)
+    ws = ctx.workspace(nb)
     t = _Tuning()
     bs = batch.c_struct()
     _check(lib().matcha_autotune(ctx.handle, ct.byref(bs), _ptr(C), ct.byref(soft), ct.byref(march), _ptr(cand),
-                                 _ptr(best), _ptr(best_idx), _ptr(status), int(reps), ct.byref(t)), "matcha_autotune")
+                                 _ptr(best), _ptr(best_idx), _ptr(status), int(reps), _ptr(ws), nb, ct.byref(t)),
+           "matcha_autotune")
     return {"march_nc": int(t.march_nc), "soft_threads": int(t.soft_threads)}
+
+
+def c_unpack(L: int, C_wedge: np.ndarray) -> np.ndarray:
+    """One particle's wedge-layout C (host complex64 [matcha_c_elems(L)]) in the packed-by-l
+    layout (complex64 [sum_{l<=L} (2l+1)^2]), through matcha_c_unpack."""
+    cw = np.ascontiguousarray(C_wedge, dtype=np.complex64)
+    if cw.size != c_elems(L):
+        raise MatchaError(f"C_wedge has {cw.size} values, band {L} needs {c_elems(L)}")
+    out = np.zeros((L + 1) * (2 * L + 1) * (2 * L + 3) // 3, dtype=np.complex64)
+    _check(lib().matcha_c_unpack(int(L), cw.ctypes.data, out.ctypes.data), "matcha_c_unpack")
+    return out
 
 
 # ------------------------------------------------------------ layout helpers

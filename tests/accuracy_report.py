@@ -1,5 +1,6 @@
-"""Accuracy report: the batched path (FP32 and BF16 assembly) against the FP64 oracle on evenly
-spaced sampled particles of three workloads, and the adjoint's time and error.  Needs a GPU:
+"""Accuracy report: the batched path (FP32; BF16 assembly with the final level on FP32 coefficients;
+BF16 throughout) against the FP64 oracle on evenly spaced sampled particles of three workloads,
+and the adjoint's time and error.  Needs a GPU:
 
     python tests/accuracy_report.py
 
@@ -35,14 +36,16 @@ for name, npart, nsamp in [("L32_R32_B12_K16", 4096, 64), ("uneven_L24to48", 102
     batch, f, h, w = upload(b)
     fp64 = 40 if int(b.L.max()) > 40 else 0
     res = {}
-    for tag, ff, hh, prec in [("fp32", f, h, M.FP32), ("bf16", f.to(torch.bfloat16), h.to(torch.bfloat16), M.BF16_FP32ACC)]:
-        C = M.coeff_assemble(ctx, batch, ff, hh, w, prec=prec)
-        cand, st = M.soft_search(ctx, batch, C, wl.B, wl.n_grid, wl.Kc)
-        best, bi, st = M.march_newton(ctx, batch, C, wl.levels, wl.steps, cand, st, fp64_above=fp64)
+    f16, h16 = f.to(torch.bfloat16), h.to(torch.bfloat16)
+    for tag, ff, hh, prec, fin in [("fp32", f, h, M.FP32, False), ("bf16", f16, h16, M.BF16_FP32ACC, True),
+                                   ("bf16 throughout", f16, h16, M.BF16_FP32ACC, False)]:
+        kw = dict(f32=f, h32=h) if fin else {}
+        best, bi, st = M.align(ctx, batch, ff, hh, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, prec=prec,
+                               fp64_above=fp64, **kw)
         res[tag] = best.cpu().numpy().astype(np.float64)
     sample = np.linspace(0, npart - 1, nsamp).astype(int)
     ob, obi, ost, ocand = O.align_batch(b, wl.B, wl.n_grid, wl.Kc, list(wl.levels), wl.steps, particles=sample)
-    for tag in ("fp32", "bf16"):
+    for tag in res:
         e_rot, e_obj, ties = [], [], 0
         for t, p in enumerate(sample):
             Sc = scale(b, p, int(b.L[p]))

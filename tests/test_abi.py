@@ -49,13 +49,38 @@ def test_sizes_are_closed_forms():
 
 def test_status_strings_and_null_context_rejected():
     M, L = _lib()
-    for code in (0, -1, -2, -3, -4):
+    for code in (0, -1, -2, -3, -4, -5):
         assert len(L.matcha_status_string(code)) > 0
-    assert L.matcha_create(0, None) == M.ERR_INVALID_ARG
+    assert L.matcha_status_string(-5).decode().startswith("SOFFT shape not prepared")
+    assert L.matcha_create(0, None, None) == M.ERR_INVALID_ARG
     assert L.matcha_destroy(None) == M.ERR_INVALID_ARG
-    assert L.matcha_prepare(None, 8, 4, 16) == M.ERR_INVALID_ARG
-    assert L.matcha_soft_search(None, None, None, None, None, None, None) == M.ERR_INVALID_ARG
-    assert L.matcha_march_newton(None, None, None, None, 4, None, None, None, None, None) == M.ERR_INVALID_ARG
+    assert L.matcha_prepare(None, 8, 32) == M.ERR_INVALID_ARG
+    assert L.matcha_soft_search(None, None, None, None, None, None, None, 0, None) == M.ERR_INVALID_ARG
+    assert L.matcha_march_newton(None, None, None, None, 4, None, None, None, None, None, 0, None) == M.ERR_INVALID_ARG
+    assert L.matcha_grad_template(None, None, None, None, None, None, None, None, None, 0, None, 0, None) == \
+        M.ERR_INVALID_ARG
+
+
+def test_c_unpack_fills_the_packed_by_l_layout():
+    """matcha_c_unpack: a Hermitian-symmetric C^l (C^l_{-m,-n} = (-1)^{m-n} conj(C^l_mn)) written in
+    the wedge layout comes back whole in the packed-by-l layout, bit for bit."""
+    M, L = _lib()
+    rng = np.random.default_rng(8)
+    for Lb in (0, 1, 4, 9):
+        full = []
+        for l in range(Lb + 1):
+            w = 2 * l + 1
+            X = (rng.standard_normal((w, w)) + 1j * rng.standard_normal((w, w))).astype(np.complex64)
+            mm = np.arange(-l, l + 1)
+            sgn = (-1.0) ** (mm[:, None] - mm[None, :])
+            X = (0.5 * (X + sgn * np.conj(X[::-1, ::-1]))).astype(np.complex64)  # the symmetry, exactly
+            assert np.array_equal(X, (sgn.astype(np.float32) * np.conj(X[::-1, ::-1])))
+            full.append(X.reshape(-1))
+        full = np.concatenate(full)
+        l, m, n, pm, pn = M.wedge_index(Lb)
+        wedge = np.stack([full[M.canonical_at(l, m, n)], full[M.canonical_at(l, pm, pn)]], -1).reshape(-1)
+        got = M.c_unpack(Lb, wedge)
+        assert np.array_equal(got, full), Lb
 
 
 def test_wedge_layout_covers_the_half_plane_once():

@@ -88,6 +88,58 @@ def test_adjoint_uneven_and_deterministic(M, ctx):
     assert np.abs(gh - ref_h).max() <= 2e-5 * np.abs(ref_h).max()
 
 
+def test_adjoint_padded_and_permuted_f_offsets(M, ctx):
+    """f_offset need not be packed: particles stored out of order with gaps between them (the
+    library packs its own workspace).  grad_f lands at each particle's own offset, nothing is
+    written into the gaps, and grad_h matches the oracle."""
+    b = S.make_batch(16, 12, 4, seed=12, snr=0.2, L_per=[16, 9, 16, 5], R_per=[12, 6, 3, 12])
+    rng = np.random.default_rng(13)
+    eul = S.haar_euler(rng, 4)
+    g = rng.standard_normal(4).astype(np.float32)
+    sizes = [b.f(p).size for p in range(4)]
+    order = [2, 0, 3, 1]  # storage order in f
+    gap = 1000
+    offs = np.zeros(4, dtype=np.int64)
+    o = gap
+    for p in order:
+        offs[p] = o
+        o += sizes[p] + gap
+    flat = np.zeros(o, dtype=np.complex64)
+    for p in range(4):
+        flat[offs[p]: offs[p] + sizes[p]] = b.f(p).reshape(-1)
+    batch = M.Batch.make(b.L, b.R, b.L_h, b.R_h, f_offset=offs)
+    f = torch.from_numpy(flat.view(np.float32).copy()).cuda()
+    h = torch.from_numpy(b.h.astype(np.complex64).view(np.float32).reshape(-1).copy()).cuda()
+    w = torch.from_numpy(b.w.astype(np.float32)).cuda()
+    best = torch.from_numpy(np.c_[eul, np.zeros(4)].astype(np.float32)).cuda()
+    gh, gf = M.grad_template(ctx, batch, f, h, w, best, torch.from_numpy(g).cuda())
+    assert M.workspace_bytes(batch) < 8 * o  # packed, not sized by the padded f
+    gh = gh.cpu().numpy().view(np.complex64).reshape(b.R_h, -1)
+    gfa = gf.cpu().numpy().view(np.complex64)
+    e32 = best.cpu().numpy().astype(np.float64)
+    ref_h = np.zeros_like(b.h)
+    used = np.zeros(o, dtype=bool)
+    for p in range(4):
+        Lp, Rp = int(b.L[p]), int(b.R[p])
+        ref_h, ref_f = O.grad_one(Lp, Rp, b.f(p), b.h, 16, b.w, e32[p, :3], float(g[p]), grad_h=ref_h)
+        got = gfa[offs[p]: offs[p] + sizes[p]].reshape(ref_f.shape)
+        assert np.abs(got - ref_f).max() <= 2e-5 * np.abs(ref_f).max(), p
+        used[offs[p]: offs[p] + sizes[p]] = True
+    assert np.abs(gh - ref_h).max() <= 2e-5 * np.abs(ref_h).max()
+    # grad_f only, through the C ABI into a pre-filled buffer: the gaps keep their contents
+    gf2 = torch.full_like(f, 3.0)
+    bs = batch.c_struct()
+    nb = M.workspace_bytes(batch)
+    ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
+    rc = M.lib().matcha_grad_template(ctx.handle, M.ct.byref(bs), M._ptr(f), M._ptr(h), M._ptr(w), M._ptr(best),
+                                      M._ptr(torch.from_numpy(g).cuda()), None, M._ptr(gf2), M.FP32, M._ptr(ws), nb,
+                                      M.ct.c_void_p(M._stream()))
+    assert rc == M.OK
+    gf2 = gf2.cpu().numpy().view(np.complex64)
+    assert np.all(gf2[~used] == 3.0 + 3.0j)  # the gaps are untouched
+    assert np.array_equal(gf2[used], gfa[used])
+
+
 def test_adjoint_central_differences(M, ctx):
     b = S.make_workload("adjoint_L32", n_particles=4)
     rng = np.random.default_rng(6)

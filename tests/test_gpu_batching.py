@@ -164,3 +164,124 @@ def test_uneven_graph_and_assembly_order(M, ctx, prec):
         n = 2 * M.c_elems(int(b.L[q]))
         o, orv = 2 * int(batch.C_offset[q]), 2 * int(batch_r.C_offset[i])
         assert np.array_equal(C[o: o + n], Cr[orv: orv + n]), q
+
+
+def test_bf16_graph_with_fp32_final_level_matches_eager(M, ctx):
+    """The BF16 path whose final level marches on FP32-assembled coefficients, as one graph (two
+    assemblies, search, march) against the same calls made eagerly: bit for bit."""
+    wl = S.WORKLOADS["L32_R32_B12_K16"]
+    b = S.make_workload("L32_R32_B12_K16", n_particles=32)
+    batch, f, h, w = upload(M, b)
+    f16, h16 = f.to(torch.bfloat16), h.to(torch.bfloat16)
+    best, bi, st = M.align(ctx, batch, f16, h16, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps,
+                           prec=M.BF16_FP32ACC, f32=f, h32=h)
+    torch.cuda.synchronize()
+    ref = (best.clone(), bi.clone(), st.clone())
+    g = M.AlignGraph(ctx, batch, f16, h16, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, prec=M.BF16_FP32ACC,
+                     f32=f, h32=h)
+    for rep in range(3):
+        eager(M, ctx, batch, f, h, w, wl)  # unrelated eager work between replays
+        got = g.launch()
+        torch.cuda.synchronize()
+        for x, y in zip(got, ref):
+            assert torch.equal(x, y), rep
+    g.close()
+
+
+def test_caller_captures_the_path_with_its_own_workspace(M):
+    """Every enqueue call allocates nothing and never synchronises, so a caller can capture the whole
+    path (assembly of mixed band limits, search, march) into a graph of its own with a workspace it
+    owns (torch.cuda.CUDAGraph here).  Each replay, with eager work and synchronisations between
+    replays, matches the eager result bit for bit."""
+    c = M.Context(0)
+    wl = S.WORKLOADS["uneven_L24to48"]
+    b = S.make_workload("uneven_L24to48", n_particles=24)
+    batch, f, h, w = upload(M, b)
+    c.prepare(wl.B, wl.n_grid)
+    nb = M.workspace_bytes(batch, wl.B, wl.n_grid)
+    ws = c.workspace(nb)
+    bufs = dict(C=torch.empty(2 * batch.c_total, dtype=torch.float32, device="cuda"),
+                cand=torch.empty((batch.n, wl.Kc, 4), dtype=torch.float32, device="cuda"),
+                status=torch.empty(batch.n, dtype=torch.int32, device="cuda"),
+                best=torch.empty((batch.n, 4), dtype=torch.float32, device="cuda"),
+                best_idx=torch.empty(batch.n, dtype=torch.int32, device="cuda"))
+
+    def run():
+        return M.align(c, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, fp64_above=40, bufs=bufs)
+
+    run()
+    torch.cuda.synchronize()
+    ref = tuple(x.clone() for x in (bufs["best"], bufs["best_idx"], bufs["status"]))
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        run()
+    assert c.workspace(nb) is ws  # no workspace was allocated during capture
+    for rep in range(3):
+        for t in bufs.values():
+            t.fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        got = (bufs["best"], bufs["best_idx"], bufs["status"])
+        for x, y in zip(got, ref):
+            assert torch.equal(x, y), rep
+        M.soft_search(c, batch, bufs["C"], 8, 24, 8)  # eager work between replays
+        torch.cuda.synchronize()
+    del graph
+    c.close()
+
+
+def test_tune_cache_persists_results(M, tmp_path):
+    """matcha_create(tune_cache): autotune stores its choice in the file; a new context on the same
+    file applies the stored choice for the same batch and configuration without timing again (no
+    new line), and a different configuration is timed and added."""
+    path = str(tmp_path / "tune.txt")
+    wl = S.WORKLOADS["L32_R32_B12_K16"]
+    b = S.make_workload("L32_R32_B12_K16", n_particles=64)
+    batch, f, h, w = upload(M, b)
+    c1 = M.Context(0, tune_cache=path)
+    C = M.coeff_assemble(c1, batch, f, h, w)
+    t1 = M.autotune(c1, batch, C, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
+    c1.close()
+    lines = open(path).read().splitlines()
+    assert len(lines) == 1 and lines[0].split()[1:] == [str(t1["march_nc"]), str(t1["soft_threads"])]
+    c2 = M.Context(0, tune_cache=path)
+    assert c2.get_tuning() == {"march_nc": 0, "soft_threads": 0}
+    t2 = M.autotune(c2, batch, C, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
+    assert t2 == t1 and c2.get_tuning() == t1
+    assert len(open(path).read().splitlines()) == 1
+    M.autotune(c2, batch, C, wl.B, wl.n_grid, wl.Kc, wl.levels, 2, reps=1)  # another schedule
+    assert len(open(path).read().splitlines()) == 2
+    c2.close()
+
+
+def test_graph_survives_other_shapes_on_its_context(M):
+    """A graph keeps pointing at the context's tables: searches at another (B, n) and evaluations at
+    a larger band on the same context between replays must not disturb it (tables are freed only
+    with the context)."""
+    c = M.Context(0)
+    wl = S.WORKLOADS["L32_R32_B12_K16"]
+    b = S.make_workload("L32_R32_B12_K16", n_particles=16)
+    batch, f, h, w = upload(M, b)
+    ref = eager(M, c, batch, f, h, w, wl)
+    g = M.AlignGraph(c, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps)
+    bb = S.make_batch(48, 8, 2, seed=5, snr=0.1)
+    batch2, f2, h2, w2 = upload(M, bb)
+    for rep in range(2):
+        C = M.coeff_assemble(c, batch, f, h, w)
+        M.soft_search(c, batch, C, 8, 24, 8)
+        C2 = M.coeff_assemble(c, batch2, f2, h2, w2)
+        M.evaluate(c, batch2, C2, 48, torch.zeros((2, 4), dtype=torch.float32, device="cuda"), fp64_above=40)
+        M.soft_search(c, batch2, C2, 16, 40, 8)
+        got = g.launch()
+        torch.cuda.synchronize()
+        for x, y in zip(got, ref):
+            assert torch.equal(x, y), rep
+    g.close()
+    c.close()

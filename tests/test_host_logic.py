@@ -12,7 +12,7 @@ def host_batch(L, R, L_h, R_h):
     R = np.ascontiguousarray(R, dtype=np.int32)
     b = M._Batch()
     b.n_particles = L.size
-    b.L_max = int(L.max())
+    b.L_max = int(L.max()) if L.size else 0
     b.L_host = L.ctypes.data_as(ct.POINTER(ct.c_int32))
     b.R_host = R.ctypes.data_as(ct.POINTER(ct.c_int32))
     # device arrays are only checked for presence on the host; never dereferenced here
@@ -56,11 +56,80 @@ def test_lpt_order_rejects_bad_arguments():
     assert rc == M.ERR_INVALID_ARG
 
 
-def test_workspace_is_one_template_term_per_particle():
+def align256(x):
+    return (x + 255) // 256 * 256
+
+
+def soft_particle(n, B):
+    """Per particle: n^3 floats of grid, 1024 maxima keys, a count, n (B+1)(2B+1) complex node transforms."""
+    return n ** 3 * 4, 1024 * 8, 4, n * (B + 1) * (2 * B + 1) * 8
+
+
+def soft_chunk(pc, n, B):
+    g, l, c, s = soft_particle(n, B)
+    return align256(pc * g) + align256(pc * l) + align256(pc * c) + align256(pc * s)
+
+
+def test_workspace_size_is_the_largest_call_need():
+    """matcha_workspace_size = max(assembly order buffer, SOFFT chunk of the whole batch, adjoint
+    offsets and per-particle template terms)."""
     L, R = [32, 10, 3], [32, 5, 2]
     b, keep = host_batch(L, R, 32, 32)
-    n = M.lib().matcha_workspace_size(ct.byref(b), 16)
-    assert n == 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
+    grad = align256(8 * 3) + 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
+    assert M.lib().matcha_workspace_size(None, ct.byref(b), None, None) == grad
+    soft = M._SoftCfg(3, 12, 4)
+    want = max(grad, soft_chunk(3, 12, 3), 4 * 3)
+    assert M.lib().matcha_workspace_size(None, ct.byref(b), ct.byref(soft), None) == want
+    soft = M._SoftCfg(12, 48, 16)
+    assert M.lib().matcha_workspace_size(None, ct.byref(b), ct.byref(soft), None) == soft_chunk(3, 48, 12)
+    # empty or invalid batches need nothing
+    e, keep2 = host_batch([], [], 32, 32)
+    e.n_particles = 0
+    assert M.lib().matcha_workspace_size(None, ct.byref(e), ct.byref(soft), None) == 0
+    bad, keep3 = host_batch([40], [4], 32, 32)  # L_p above the template's band
+    assert M.lib().matcha_workspace_size(None, ct.byref(bad), None, None) == 0
+
+
+def test_workspace_too_small_is_reported_before_the_context():
+    """Every enqueue call checks its workspace on the host, before it needs a context or a device: a
+    short workspace gives MATCHA_ERR_WORKSPACE, an adequate one then fails only on the NULL context."""
+    lib = M.lib()
+    dev = ct.c_void_p(1 << 20)  # aligned stand-in for device buffers: never dereferenced by these checks
+    L, R = [8, 6, 8], [4, 4, 3]
+    b, keep = host_batch(L, R, 8, 4)
+    b.f_offset = dev
+    # assembly of mixed band limits needs P int32
+    rc = lib.matcha_coeff_assemble(None, ct.byref(b), dev, dev, dev, dev, M.FP32, dev, 11, None)
+    assert rc == M.ERR_WORKSPACE
+    rc = lib.matcha_coeff_assemble(None, ct.byref(b), dev, dev, dev, dev, M.FP32, None, 0, None)
+    assert rc == M.ERR_WORKSPACE
+    rc = lib.matcha_coeff_assemble(None, ct.byref(b), dev, dev, dev, dev, M.FP32, dev, 12, None)
+    assert rc == M.ERR_INVALID_ARG
+    # equal band limits need no workspace
+    bu, keepu = host_batch([8, 8], [4, 4], 8, 4)
+    bu.f_offset = dev
+    assert lib.matcha_coeff_assemble(None, ct.byref(bu), dev, dev, dev, dev, M.FP32, None, 0, None) == M.ERR_INVALID_ARG
+    # search: one particle's share at least
+    soft = M._SoftCfg(4, 16, 8)
+    one = soft_chunk(1, 16, 4)
+    rc = lib.matcha_soft_search(None, ct.byref(b), dev, ct.byref(soft), dev, dev, dev, one - 1, None)
+    assert rc == M.ERR_WORKSPACE
+    rc = lib.matcha_soft_search(None, ct.byref(b), dev, ct.byref(soft), dev, dev, dev, one, None)
+    assert rc == M.ERR_INVALID_ARG
+    rc = lib.matcha_soft_search(None, ct.byref(b), dev, ct.byref(soft), dev, dev, ct.c_void_p((1 << 20) + 8), one,
+                                None)
+    assert rc == M.ERR_WORKSPACE  # misaligned
+    # adjoint with grad_h: offsets and terms
+    need = align256(8 * 3) + 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
+    args = (None, ct.byref(b), dev, dev, dev, dev, dev, dev, None, M.FP32)
+    assert lib.matcha_grad_template(*args, dev, need - 1, None) == M.ERR_WORKSPACE
+    assert lib.matcha_grad_template(*args, dev, need, None) == M.ERR_INVALID_ARG
+    # grad_f only: no workspace
+    args_f = (None, ct.byref(b), dev, dev, dev, dev, dev, None, dev, M.FP32)
+    assert lib.matcha_grad_template(*args_f, None, 0, None) == M.ERR_INVALID_ARG
+    # only FP32 is offered
+    args_b = (None, ct.byref(b), dev, dev, dev, dev, dev, dev, None, M.BF16_FP32ACC)
+    assert lib.matcha_grad_template(*args_b, dev, need, None) == M.ERR_UNSUPPORTED
 
 
 def test_march_traffic_reported_only_for_its_workload_and_sources(tmp_path, monkeypatch):

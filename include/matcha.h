@@ -276,6 +276,21 @@ matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, c
                                    const float *w, const float *best, const float *g, float *grad_h, float *grad_f,
                                    matcha_precision prec, void *ws, size_t ws_bytes, void *stream);
 
+/* SOFFT search for callers that cannot allocate (code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the kernels and results of matcha_soft_search, with its
+ * workspace taken from a static device array of MATCHA_NOALLOC_SCRATCH_BYTES that each device the
+ * library runs on holds from library load until the process ends (its address is looked up once per
+ * device by matcha_create).  The caller still passes C, cand and status.  The batch runs in chunks
+ * of as many particles as the array holds; a shape whose one-particle share exceeds it returns
+ * MATCHA_ERR_WORKSPACE (the largest shape the search accepts, B = 32 on a 96^3 grid, needs
+ * 5.2 MB).  Every call on a device shares that device's array and leaves its contents behind
+ * (each call writes what it reads before reading it): calls that overlap in time on one device
+ * (other streams, other contexts, other threads) race, so the caller must order them.  Calls
+ * no hipMalloc, hipFree or allocating routine. */
+#define MATCHA_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+matcha_status matcha_soft_search_noalloc(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
+                                         const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream);
+
 /* ---- batching: graphs and tuning ------------------------------------------ */
 typedef struct matcha_graph matcha_graph;
 

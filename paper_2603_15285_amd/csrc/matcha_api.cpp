@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <utility>
@@ -31,8 +32,14 @@ struct GridTables {
 
 }  // namespace
 
+// The workspace of matcha_soft_search_noalloc: one array per device, held until the process ends.
+// Host code never uses this name as an address; it uses the per-device pointer from
+// hipGetSymbolAddress (noalloc_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[MATCHA_NOALLOC_SCRATCH_BYTES];
+
 struct matcha_ctx {
     int device = 0;
+    void *scratch = nullptr;  // this device's address of `scratch`
     // recurrence tables for every l <= kMaxL, built by matcha_create
     float4 *tab = nullptr;
     double2 *tab64 = nullptr;  // (A, AC) of tab in FP64
@@ -234,6 +241,23 @@ size_t grad_ws_need(const matcha_batch *b)
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+// Device address of `scratch` on `device` (current), looked up once per device.
+matcha_status noalloc_scratch_ptr(int device, void **out)
+{
+    constexpr int kDevices = 64;
+    static std::mutex mu;
+    static void *ptr[kDevices] = {};
+    if (device < 0 || device >= kDevices) return MATCHA_ERR_UNSUPPORTED;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return MATCHA_ERR_HIP;
+        ptr[device] = p;
+    }
+    *out = ptr[device];
+    return MATCHA_OK;
+}
 
 // Common batch checks; on success minL / maxL / maxR hold the host-side extents.
 matcha_status check_batch(const matcha_batch *b, int *minL, int *maxL, int *maxR)
@@ -490,6 +514,10 @@ matcha_status matcha_create(int device, const char *tune_cache, matcha_ctx **out
         return MATCHA_ERR_HIP;
     }
     c->arch = std::string(prop.gcnArchName) + "_cu" + std::to_string(prop.multiProcessorCount);
+    if (noalloc_scratch_ptr(device, &c->scratch) != MATCHA_OK) {
+        delete c;
+        return MATCHA_ERR_HIP;
+    }
     std::vector<float4> tab;
     std::vector<double2> tab64;
     std::vector<PairInfo> pinfo;
@@ -673,6 +701,19 @@ matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, con
     matcha_status st = soft_check(ctx, batch, C, cfg, cand, status, ws, ws_bytes, &nt, &gt);
     if (st != MATCHA_OK || batch->n_particles == 0) return st;
     return soft_launch(ctx, batch, C, cfg, gt, cand, status, nt, ws, ws_bytes, static_cast<hipStream_t>(stream));
+}
+
+matcha_status matcha_soft_search_noalloc(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
+                                         const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream)
+{
+    if (!ctx || !ctx->scratch) return MATCHA_ERR_INVALID_ARG;
+    int nt = 0;
+    const GridTables *gt = nullptr;
+    matcha_status st = soft_check(ctx, batch, C, cfg, cand, status, ctx->scratch, MATCHA_NOALLOC_SCRATCH_BYTES, &nt,
+                                  &gt);
+    if (st != MATCHA_OK || batch->n_particles == 0) return st;
+    return soft_launch(ctx, batch, C, cfg, gt, cand, status, nt, ctx->scratch, MATCHA_NOALLOC_SCRATCH_BYTES,
+                       static_cast<hipStream_t>(stream));
 }
 
 matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, const float *C,

@@ -26,7 +26,8 @@ EXPORTED = ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_status_
             "matcha_get_tuning", "matcha_c_elems", "matcha_f_elems", "matcha_workspace_size", "matcha_lpt_order",
             "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton", "matcha_evaluate",
             "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch", "matcha_graph_destroy",
-            "matcha_autotune", "matcha_c_unpack"]
+            "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc"]
+NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class MatchaError(RuntimeError):
@@ -93,6 +94,7 @@ def lib():
         L.matcha_grad_template.argtypes = [vp, bp, vp, vp, vp, vp, vp, vp, vp, ct.c_int, vp, sz, vp]
         L.matcha_lpt_order.argtypes = [bp, ct.POINTER(_MarchCfg), ct.POINTER(ct.c_int32)]
         L.matcha_c_unpack.argtypes = [i32, vp, vp]
+        L.matcha_soft_search_noalloc.argtypes = [vp, bp, vp, ct.POINTER(_SoftCfg), vp, vp, vp]
         L.matcha_align_graph_create.argtypes = [vp, bp, ct.POINTER(_AlignBufs), ct.POINTER(_SoftCfg),
                                                 ct.POINTER(_MarchCfg), vp, sz, ct.POINTER(vp)]
         L.matcha_graph_launch.argtypes = [vp, vp]
@@ -102,7 +104,7 @@ def lib():
         for name in ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_set_tuning", "matcha_get_tuning",
                      "matcha_lpt_order", "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton",
                      "matcha_evaluate", "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch",
-                     "matcha_graph_destroy", "matcha_autotune", "matcha_c_unpack"]:
+                     "matcha_graph_destroy", "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc"]:
             getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -301,6 +303,18 @@ def soft_search(ctx: Context, batch: Batch, C: torch.Tensor, B: int, n_grid: int
     ws = ctx.workspace(nb)
     _check(lib().matcha_soft_search(ctx.handle, ct.byref(bs), _ptr(C), ct.byref(cfg), _ptr(cand), _ptr(status),
                                     _ptr(ws), nb, ct.c_void_p(_stream(stream))), "matcha_soft_search")
+    return cand, status
+
+
+def soft_search_noalloc(ctx: Context, batch: Batch, C: torch.Tensor, B: int, n_grid: int, Kc: int,
+                        cand: torch.Tensor, status: torch.Tensor, stream=None):
+    """matcha_soft_search_noalloc: the search with the library's static device scratch as workspace
+    ((B, n_grid) must be prepared; nothing is allocated)."""
+    _need(cand, torch.float32, "cand")
+    bs = batch.c_struct()
+    cfg = _SoftCfg(B, n_grid, Kc)
+    _check(lib().matcha_soft_search_noalloc(ctx.handle, ct.byref(bs), _ptr(C), ct.byref(cfg), _ptr(cand),
+                                            _ptr(status), ct.c_void_p(_stream(stream))), "matcha_soft_search_noalloc")
     return cand, status
 
 

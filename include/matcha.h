@@ -187,17 +187,20 @@ matcha_status matcha_get_tuning(const matcha_ctx *ctx, matcha_tuning *t);
 int64_t matcha_c_elems(int32_t L);
 /* Complex values of one particle's f: R (L+1)^2. */
 int64_t matcha_f_elems(int32_t L, int32_t R);
-/* Bytes of workspace with which every enqueue call on this batch runs in one pass: the maximum of
+/* Bytes of workspace with which the forward path's calls on this batch run in one pass: the
+ * maximum of
  *   matcha_coeff_assemble: P int32 (the particle order by L_p) when the L_p differ, else 0;
  *   matcha_soft_search (soft non-NULL): per particle n^3 floats of grid, n (B+1)(2B+1) complex
  *     node transforms and 1024 maxima keys (575 KB at B = 12, n_grid = 48), for as many particles
  *     as fit in 4 GiB;
- *   matcha_grad_template: P int64 offsets plus one template-gradient term of R_p (L_p+1)^2
- *     complex float32 per particle;
  *   matcha_march_newton, matcha_evaluate: none.
  * Returns 0 for an empty or invalid batch.  ctx and march may be NULL. */
 size_t matcha_workspace_size(const matcha_ctx *ctx, const matcha_batch *batch, const matcha_soft_cfg *soft,
                              const matcha_march_cfg *march);
+/* Bytes of workspace of matcha_grad_template with grad_h requested: P int64 offsets (256-byte
+ * aligned) plus one template-gradient term of R_p (L_p+1)^2 complex float32 per particle.  0 for
+ * an empty or invalid batch. */
+size_t matcha_grad_workspace_size(const matcha_batch *batch);
 
 /* Longest-processing-time order (host): particle indices sorted by decreasing march cost
  * Kc * steps * sum over the particle's schedule of (L_j+1)(L_j+2)(2L_j+3)/6, ties by index. */
@@ -271,7 +274,7 @@ matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const 
  * (MATCHA_ERR_UNSUPPORTED otherwise).  The sum over particles is deterministic (particles in
  * index order, no floating-point atomics); each particle's term passes through ws (packed in the
  * library's own order, whatever f_offset is; MATCHA_ERR_WORKSPACE if ws_bytes is below
- * matcha_workspace_size's grad_template share when grad_h is requested). */
+ * matcha_grad_workspace_size when grad_h is requested). */
 matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, const float *f, const float *h,
                                    const float *w, const float *best, const float *g, float *grad_h, float *grad_f,
                                    matcha_precision prec, void *ws, size_t ws_bytes, void *stream);

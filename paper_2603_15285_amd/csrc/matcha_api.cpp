@@ -617,10 +617,17 @@ size_t matcha_workspace_size(const matcha_ctx *ctx, const matcha_batch *batch, c
     (void)march;
     int lo, hi, rmax;
     if (check_batch(batch, &lo, &hi, &rmax) != MATCHA_OK || batch->n_particles == 0) return 0;
-    size_t need = std::max(assemble_ws_need(batch->n_particles, lo != hi), grad_ws_need(batch));
+    size_t need = assemble_ws_need(batch->n_particles, lo != hi);
     if (soft && soft->B >= 1 && soft->n_grid >= 4)
         need = std::max(need, soft_ws_need(batch->n_particles, soft->n_grid, soft->B));
     return need;
+}
+
+size_t matcha_grad_workspace_size(const matcha_batch *batch)
+{
+    int lo, hi, rmax;
+    if (check_batch(batch, &lo, &hi, &rmax) != MATCHA_OK || batch->n_particles == 0) return 0;
+    return grad_ws_need(batch);
 }
 
 matcha_status matcha_c_unpack(int32_t L, const float *C_wedge_host, float *C_byl_host)

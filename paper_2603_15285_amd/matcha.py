@@ -26,7 +26,7 @@ EXPORTED = ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_status_
             "matcha_get_tuning", "matcha_c_elems", "matcha_f_elems", "matcha_workspace_size", "matcha_lpt_order",
             "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton", "matcha_evaluate",
             "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch", "matcha_graph_destroy",
-            "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc"]
+            "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc", "matcha_grad_workspace_size"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
@@ -87,6 +87,8 @@ def lib():
         L.matcha_f_elems.restype = i64
         L.matcha_workspace_size.argtypes = [vp, bp, ct.POINTER(_SoftCfg), ct.POINTER(_MarchCfg)]
         L.matcha_workspace_size.restype = sz
+        L.matcha_grad_workspace_size.argtypes = [bp]
+        L.matcha_grad_workspace_size.restype = sz
         L.matcha_coeff_assemble.argtypes = [vp, bp, vp, vp, vp, vp, ct.c_int, vp, sz, vp]
         L.matcha_soft_search.argtypes = [vp, bp, vp, ct.POINTER(_SoftCfg), vp, vp, vp, sz, vp]
         L.matcha_march_newton.argtypes = [vp, bp, vp, ct.POINTER(_MarchCfg), i32, vp, vp, vp, vp, vp, sz, vp]
@@ -265,9 +267,15 @@ def _march_cfg(levels, steps, max_step=0.0, early_stop=False, tol_grad=TOL_GRAD,
     return cfg
 
 
+def grad_workspace_bytes(batch: "Batch") -> int:
+    """matcha_grad_workspace_size: the adjoint's workspace for this batch."""
+    bs = batch.c_struct()
+    return int(lib().matcha_grad_workspace_size(ct.byref(bs)))
+
+
 def workspace_bytes(batch: "Batch", B: int = 0, n_grid: int = 0, ctx: "Context | None" = None) -> int:
-    """matcha_workspace_size: bytes with which every call on this batch runs in one pass (the SOFFT
-    share only when B and n_grid are given)."""
+    """matcha_workspace_size: bytes with which the forward calls on this batch run in one pass (the
+    SOFFT share only when B and n_grid are given)."""
     bs = batch.c_struct()
     soft = _SoftCfg(int(B), int(n_grid), 1) if B and n_grid else None
     return int(lib().matcha_workspace_size(ctx.handle if ctx else None, ct.byref(bs),
@@ -358,7 +366,7 @@ def grad_template(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, 
     _need(g, torch.float32, "g")
     gh = torch.empty_like(h) if want_h else None
     gf = torch.empty_like(f) if want_f else None
-    nbytes = workspace_bytes(batch) if want_h else 0
+    nbytes = grad_workspace_bytes(batch) if want_h else 0
     ws = ctx.workspace(nbytes)
     bs = batch.c_struct()
     _check(lib().matcha_grad_template(ctx.handle, ct.byref(bs), _ptr(f), _ptr(h), _ptr(w), _ptr(best), _ptr(g),

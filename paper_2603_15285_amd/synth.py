@@ -134,21 +134,39 @@ def wigner_d_expm(l: int, beta: np.ndarray) -> np.ndarray:
     return d.real.reshape(beta.shape + (2 * l + 1, 2 * l + 1))
 
 
-def rotate_coeffs(h: np.ndarray, L: int, euler: np.ndarray) -> np.ndarray:
+def rotate_coeffs(h: np.ndarray, L: int, euler: np.ndarray, hermitian: bool = False) -> np.ndarray:
     """(g o h)_l = D^l(g) h_l for a batch of rotations.
 
     h: [R, (L+1)^2] complex; euler: [P, 3].  Returns [P, R, (L+1)^2] complex128.
-    """
-    euler = np.atleast_2d(euler)
-    P = euler.shape[0]
-    out = np.empty((P,) + h.shape, dtype=np.complex128)
+
+    d^l(b) = V e^{-i b Lambda} V^H with J_y = V Lambda V^H, applied to the vectors rather than
+    formed: for all particles and shells at once, X = (e^{-inc} h_l) conj(V) and
+    Z = (e^{-i b lambda_k} X) V^T are two GEMMs per degree with the shared V; then e^{-ima}.
+    hermitian: h is Hermitian-symmetric, c_{l,-m} = (-1)^m conj(c_lm), which D^l of a real rotation
+    preserves; the m < 0 half is then written from the m > 0 half so that the output is
+    Hermitian-symmetric exactly."""
+    euler = np.atleast_2d(np.asarray(euler, dtype=np.float64))
+    P, R = euler.shape[0], h.shape[0]
+    out = np.empty((P, R, n_lm(L)), dtype=np.complex128)
     a, b, c = euler[:, 0], euler[:, 1], euler[:, 2]
     for l in range(L + 1):
+        lam, V = _jy_eig(l)
         m = np.arange(-l, l + 1)
-        d = wigner_d_expm(l, b)  # [P, 2l+1, 2l+1]
-        D = np.exp(-1j * a[:, None, None] * m[None, :, None]) * d * np.exp(-1j * c[:, None, None] * m[None, None, :])
         hl = h[:, l * l: (l + 1) * (l + 1)]  # [R, 2l+1]
-        out[:, :, l * l: (l + 1) * (l + 1)] = np.einsum("pmn,rn->prm", D, hl)
+        U = np.exp(-1j * c[:, None, None] * m[None, None, :]) * hl[None]  # [P, R, 2l+1]
+        X = (U.reshape(P * R, 2 * l + 1) @ V.conj()).reshape(P, R, 2 * l + 1)
+        X *= np.exp(-1j * b[:, None, None] * lam[None, None, :])
+        Z = (X.reshape(P * R, 2 * l + 1) @ V.T).reshape(P, R, 2 * l + 1)
+        Z *= np.exp(-1j * a[:, None, None] * m[None, None, :])
+        if not hermitian:
+            out[:, :, l * l: (l + 1) * (l + 1)] = Z
+            continue
+        c0 = l * l + l
+        out[:, :, c0] = Z[:, :, l].real
+        if l > 0:
+            mpos = np.arange(1, l + 1)
+            out[:, :, c0 + mpos] = Z[:, :, l + mpos]
+            out[:, :, c0 - mpos] = ((-1.0) ** mpos) * np.conj(Z[:, :, l + mpos])
     return out
 
 
@@ -157,19 +175,26 @@ def hermitian_gaussian(rng: np.random.Generator, shape_r: int, L: int, var_l: np
     """Random coefficients with c_{l,-m} = (-1)^m conj(c_lm) exactly.
 
     var_l[l]: variance of each coefficient (complex CN for m > 0, real for m = 0);
-    scale_r[r]: optional per-shell multiplier of the variance.
+    scale_r[r]: optional per-shell multiplier of the variance.  The normals are drawn in one call
+    and used degree by degree: for each l, R values for m = 0, then R*l real and R*l imaginary
+    parts (shell-major) for m = 1..l.
     """
     out = np.zeros((shape_r, n_lm(L)), dtype=np.complex128)
     sr = np.ones(shape_r) if scale_r is None else np.asarray(scale_r, dtype=np.float64)
+    z = rng.standard_normal(shape_r * n_lm(L))
+    k = 0
     for l in range(L + 1):
         sd = np.sqrt(var_l[l] * sr)  # [R]
         c0 = l * l + l
-        out[:, c0] = rng.standard_normal(shape_r) * sd
+        out[:, c0] = z[k: k + shape_r] * sd
+        k += shape_r
         if l > 0:
-            z = (rng.standard_normal((shape_r, l)) + 1j * rng.standard_normal((shape_r, l))) * (sd[:, None] / math.sqrt(2.0))
+            n = shape_r * l
+            zc = (z[k: k + n] + 1j * z[k + n: k + 2 * n]).reshape(shape_r, l) * (sd[:, None] / math.sqrt(2.0))
+            k += 2 * n
             mpos = np.arange(1, l + 1)
-            out[:, c0 + mpos] = z
-            out[:, c0 - mpos] = ((-1.0) ** mpos) * np.conj(z)
+            out[:, c0 + mpos] = zc
+            out[:, c0 - mpos] = ((-1.0) ** mpos) * np.conj(zc)
     return out
 
 
@@ -216,14 +241,55 @@ def make_template(L: int, R: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     return h, w
 
 
+_WORKER_TEMPLATE: dict = {}
+
+
+def _worker_init(h, w):
+    _WORKER_TEMPLATE.update(h=h, w=w)
+
+
+def _particles_chunk(task):
+    """Rotated noisy copies of the template for one chunk of particles with equal (L_p, R_p):
+    [chunk, R_p (L_p+1)^2] in f_dtype."""
+    Lp, Rp, chunk, eul, snrs, rngs, noiseless, f_dtype = task
+    h, w = _WORKER_TEMPLATE["h"], _WORKER_TEMPLATE["w"]
+    rot = rotate_coeffs(h[:Rp, : n_lm(Lp)], Lp, eul, hermitian=True)
+    if not noiseless:
+        e_sig = np.einsum("prk,r->p", rot.real ** 2 + rot.imag ** 2, w[:Rp])
+        for j in range(len(chunk)):
+            s2 = float(e_sig[j]) / (snrs[j] * Rp * n_lm(Lp))
+            rot[j] += hermitian_gaussian(rngs[j], Rp, Lp, np.full(Lp + 1, s2), scale_r=1.0 / w[:Rp])
+    return rot.reshape(len(chunk), -1).astype(f_dtype)
+
+
+def _place(f_flat, f_offset, chunk, block):
+    for j, p in enumerate(chunk):
+        o = f_offset[p]
+        f_flat[o: o + block.shape[1]] = block[j]
+
+
+def _workers(n_values: int, n_tasks: int, workers) -> int:
+    """Processes for generating a batch: one unless the caller asks for more (the processes are
+    started with the spawn method, which re-imports the caller's main module: only a main module
+    guarded by `if __name__ == "__main__"` may ask)."""
+    if workers is None or n_values < (1 << 22):
+        return 1
+    return max(1, min(int(workers), n_tasks))
+
+
 def make_batch(L_h: int, R_h: int, n_particles: int, *, seed: int, snr=(0.05, 0.2),
                L_per: Sequence[int] | None = None, R_per: Sequence[int] | None = None,
-               noiseless: bool = False, euler: np.ndarray | None = None) -> Batch:
+               noiseless: bool = False, euler: np.ndarray | None = None, f_dtype=np.complex128,
+               workers: int | None = None) -> Batch:
     """Template h (l <= L_h, R_h shells) and n_particles rotated noisy copies.
 
     snr: a float (fixed linear SNR) or a (lo, hi) pair drawn uniformly per particle.
     L_per / R_per: per-particle band limit and shell count (default L_h / R_h); a
     particle uses template shells 1..R_p and degrees l <= L_p.
+    f_dtype: storage of f (complex64 halves the host memory of the large workloads; both the oracle
+    and the GPU then read the same rounded values).
+    workers: processes sharing the chunks of particles (default one; see _workers); the result does
+    not depend on it.
     """
     h, w = make_template(L_h, R_h, seed)
     ss = np.random.SeedSequence(seed + 1)
@@ -233,7 +299,7 @@ def make_batch(L_h: int, R_h: int, n_particles: int, *, seed: int, snr=(0.05, 0.
     assert L.max() <= L_h and R.max() <= R_h
     sizes = R.astype(np.int64) * (L.astype(np.int64) + 1) ** 2
     f_offset = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-    f_flat = np.empty(int(sizes.sum()), dtype=np.complex128)
+    f_flat = np.empty(int(sizes.sum()), dtype=f_dtype)
     eul = np.empty((n_particles, 3))
     snrs = np.empty(n_particles)
     rngs = [np.random.default_rng(k) for k in kids]
@@ -243,23 +309,40 @@ def make_batch(L_h: int, R_h: int, n_particles: int, *, seed: int, snr=(0.05, 0.
         else:
             eul[p] = euler[p]
         snrs[p] = snr if np.isscalar(snr) else rngs[p].uniform(snr[0], snr[1])
-    # rotate grouped by (L_p, R_p) so the uniform case is one vectorised call
+    # Rotate grouped by (L_p, R_p), in chunks of particles whose size depends only on (L_p, R_p), so
+    # that the GEMMs stay large, the temporaries bounded and the result independent of how many
+    # processes share the chunks; each particle's noise comes from its own generator.
     keys = np.stack([L, R], 1)
-    for (Lp, Rp) in {tuple(k) for k in keys.tolist()}:
+    tasks = []
+    for (Lp, Rp) in sorted({tuple(k) for k in keys.tolist()}):
         idx = np.nonzero((L == Lp) & (R == Rp))[0]
-        hp = h[:Rp, : n_lm(Lp)]
-        for s in range(0, idx.size, 256):
-            chunk = idx[s: s + 256]
-            rot = rotate_coeffs(hp, Lp, eul[chunk])
-            for j, p in enumerate(chunk):
-                fp = rot[j]
-                if not noiseless:
-                    e_sig = float(np.sum(w[:Rp, None] * np.abs(fp) ** 2))
-                    s2 = e_sig / (snrs[p] * Rp * n_lm(Lp))
-                    eta = hermitian_gaussian(rngs[p], Rp, Lp, np.full(Lp + 1, s2), scale_r=1.0 / w[:Rp])
-                    fp = fp + eta
-                o = f_offset[p]
-                f_flat[o: o + fp.size] = fp.reshape(-1)
+        step = max(1, (1 << 22) // (Rp * n_lm(Lp)))
+        for s in range(0, idx.size, step):
+            chunk = idx[s: s + step]
+            tasks.append((int(Lp), int(Rp), chunk, eul[chunk], snrs[chunk], [rngs[p] for p in chunk], noiseless,
+                          f_dtype))
+    nproc = _workers(int(sizes.sum()), len(tasks), workers)
+    if nproc <= 1:
+        _WORKER_TEMPLATE.update(h=h, w=w)
+        for t, block in zip(tasks, map(_particles_chunk, tasks)):
+            _place(f_flat, f_offset, t[2], block)
+    else:
+        import concurrent.futures as cf
+        import multiprocessing as mp
+        import os
+        # one BLAS thread per worker: the workers start at the first submission and read this then
+        saved = os.environ.get("OPENBLAS_NUM_THREADS")
+        os.environ["OPENBLAS_NUM_THREADS"] = "1"
+        try:
+            with cf.ProcessPoolExecutor(nproc, mp_context=mp.get_context("spawn"), initializer=_worker_init,
+                                        initargs=(h, w)) as ex:
+                for t, block in zip(tasks, ex.map(_particles_chunk, tasks)):
+                    _place(f_flat, f_offset, t[2], block)
+        finally:
+            if saved is None:
+                del os.environ["OPENBLAS_NUM_THREADS"]
+            else:
+                os.environ["OPENBLAS_NUM_THREADS"] = saved
     return Batch(L_h=L_h, R_h=R_h, h=h, w=w, L=L, R=R, f_offset=f_offset, f_flat=f_flat,
                  euler_true=eul, snr=snrs)
 
@@ -293,12 +376,14 @@ WORKLOADS = {
 WORKLOAD_INDEX = {k: i for i, k in enumerate(WORKLOADS)}
 
 
-def make_workload(name: str, n_particles: int | None = None, seed_offset: int = 0) -> Batch:
+def make_workload(name: str, n_particles: int | None = None, seed_offset: int = 0, f_dtype=np.complex128,
+                  workers: int | None = None) -> Batch:
     wl = WORKLOADS[name]
     n = wl.n_particles if n_particles is None else n_particles
     seed = SEED_BASE + WORKLOAD_INDEX[name] + 1000 * seed_offset
     if wl.uneven:
         rng = np.random.default_rng(seed + 7)
         Lp = rng.integers(24, 49, size=n)
-        return make_batch(wl.L, wl.R, n, seed=seed, snr=wl.snr, L_per=Lp, R_per=Lp)
-    return make_batch(wl.L, wl.R, n, seed=seed, snr=wl.snr)
+        return make_batch(wl.L, wl.R, n, seed=seed, snr=wl.snr, L_per=Lp, R_per=Lp, f_dtype=f_dtype,
+                          workers=workers)
+    return make_batch(wl.L, wl.R, n, seed=seed, snr=wl.snr, f_dtype=f_dtype, workers=workers)

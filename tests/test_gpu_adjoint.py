@@ -113,7 +113,7 @@ def test_adjoint_padded_and_permuted_f_offsets(M, ctx):
     w = torch.from_numpy(b.w.astype(np.float32)).cuda()
     best = torch.from_numpy(np.c_[eul, np.zeros(4)].astype(np.float32)).cuda()
     gh, gf = M.grad_template(ctx, batch, f, h, w, best, torch.from_numpy(g).cuda())
-    assert M.workspace_bytes(batch) < 8 * o  # packed, not sized by the padded f
+    assert M.grad_workspace_bytes(batch) < 8 * o  # packed, not sized by the padded f
     gh = gh.cpu().numpy().view(np.complex64).reshape(b.R_h, -1)
     gfa = gf.cpu().numpy().view(np.complex64)
     e32 = best.cpu().numpy().astype(np.float64)
@@ -129,7 +129,7 @@ def test_adjoint_padded_and_permuted_f_offsets(M, ctx):
     # grad_f only, through the C ABI into a pre-filled buffer: the gaps keep their contents
     gf2 = torch.full_like(f, 3.0)
     bs = batch.c_struct()
-    nb = M.workspace_bytes(batch)
+    nb = M.grad_workspace_bytes(batch)
     ws = torch.empty(nb, dtype=torch.uint8, device="cuda")
     rc = M.lib().matcha_grad_template(ctx.handle, M.ct.byref(bs), M._ptr(f), M._ptr(h), M._ptr(w), M._ptr(best),
                                       M._ptr(torch.from_numpy(g).cuda()), None, M._ptr(gf2), M.FP32, M._ptr(ws), nb,

@@ -71,14 +71,15 @@ def soft_chunk(pc, n, B):
 
 
 def test_workspace_size_is_the_largest_call_need():
-    """matcha_workspace_size = max(assembly order buffer, SOFFT chunk of the whole batch, adjoint
-    offsets and per-particle template terms)."""
+    """matcha_workspace_size = max(assembly order buffer, SOFFT chunk of the whole batch);
+    matcha_grad_workspace_size = the adjoint's offsets and per-particle template terms."""
     L, R = [32, 10, 3], [32, 5, 2]
     b, keep = host_batch(L, R, 32, 32)
     grad = align256(8 * 3) + 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
-    assert M.lib().matcha_workspace_size(None, ct.byref(b), None, None) == grad
+    assert M.lib().matcha_grad_workspace_size(ct.byref(b)) == grad
+    assert M.lib().matcha_workspace_size(None, ct.byref(b), None, None) == 4 * 3
     soft = M._SoftCfg(3, 12, 4)
-    want = max(grad, soft_chunk(3, 12, 3), 4 * 3)
+    want = max(soft_chunk(3, 12, 3), 4 * 3)
     assert M.lib().matcha_workspace_size(None, ct.byref(b), ct.byref(soft), None) == want
     soft = M._SoftCfg(12, 48, 16)
     assert M.lib().matcha_workspace_size(None, ct.byref(b), ct.byref(soft), None) == soft_chunk(3, 48, 12)
@@ -88,6 +89,8 @@ def test_workspace_size_is_the_largest_call_need():
     assert M.lib().matcha_workspace_size(None, ct.byref(e), ct.byref(soft), None) == 0
     bad, keep3 = host_batch([40], [4], 32, 32)  # L_p above the template's band
     assert M.lib().matcha_workspace_size(None, ct.byref(bad), None, None) == 0
+    assert M.lib().matcha_grad_workspace_size(ct.byref(bad)) == 0
+    assert M.lib().matcha_grad_workspace_size(ct.byref(e)) == 0
 
 
 def test_workspace_too_small_is_reported_before_the_context():

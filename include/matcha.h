@@ -154,13 +154,25 @@ typedef struct {
                               on FP32-assembled C_final. */
 } matcha_march_cfg;
 
-/* Launch shapes.  Zero fields mean "library default".  march_nc: candidates per wavefront
- * of the march kernel (1, 2, 4 or 8; a workgroup holds ceil(Kc / march_nc) <= 8 waves).
- * soft_threads: threads per workgroup of the SOFFT ranking kernel (256 or 512; each
- * particle's maxima list holds twice as many keys). */
+/* Launch shapes and tile shapes.  Zero fields mean "library default".  Results never depend on
+ * them (every output is computed by the same arithmetic in the same order).
+ *   march_nc: candidates per wavefront of the march kernel (1, 2, 4 or 8; a workgroup holds
+ *     ceil(Kc / march_nc) <= 8 waves).
+ *   soft_threads: threads per workgroup of the SOFFT ranking kernel (256 or 512; each particle's
+ *     maxima list holds twice as many keys).
+ *   asm_tiles: 16-row output tiles per wave and workgroup of the assembly (1, 2, 4 or 8;
+ *     default 4).
+ *   grid_nodes: polar nodes per wave of the register-resident SOFFT grid kernel (8, 16 or 32;
+ *     default 16).
+ *   march_persistent: 1 launches the march as a persistent grid (as many workgroups as are resident
+ *     at once, each taking the next particle from a counter in the workspace); 0 (default): one
+ *     workgroup per particle, started by the hardware in batch order. */
 typedef struct {
     int32_t march_nc;
     int32_t soft_threads;
+    int32_t asm_tiles;
+    int32_t grid_nodes;
+    int32_t march_persistent;
 } matcha_tuning;
 
 /* ---- context ---------------------------------------------------------- */
@@ -193,7 +205,8 @@ int64_t matcha_f_elems(int32_t L, int32_t R);
  *   matcha_soft_search (soft non-NULL): per particle n^3 floats of grid, n (B+1)(2B+1) complex
  *     node transforms and 1024 maxima keys (575 KB at B = 12, n_grid = 48), for as many particles
  *     as fit in 4 GiB;
- *   matcha_march_newton, matcha_evaluate: none.
+ *   matcha_march_newton: 256 bytes (the work counter of the persistent launch);
+ *   matcha_evaluate: none.
  * Returns 0 for an empty or invalid batch.  ctx and march may be NULL. */
 size_t matcha_workspace_size(const matcha_ctx *ctx, const matcha_batch *batch, const matcha_soft_cfg *soft,
                              const matcha_march_cfg *march);
@@ -252,8 +265,9 @@ matcha_status matcha_soft_search(matcha_ctx *ctx, const matcha_batch *batch, con
  * (ties: lowest index; non-finite values never win).
  * cand [P][Kc] float4 in/out: in = start points, out = (final angles, C_{L_p}).
  * best [P] float4 (a, b, c, C_{L_p}) of the selected candidate; best_idx [P];
- * status [P] in/out: the selected candidate's bits are OR-ed into it.  Uses no workspace
- * (ws may be NULL). */
+ * status [P] in/out: the selected candidate's bits are OR-ed into it.  The persistent launch
+ * (matcha_tuning.march_persistent) keeps its work counter in the first 4 bytes of ws
+ * (MATCHA_ERR_WORKSPACE below 256 bytes); otherwise ws may be NULL. */
 matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
                                   const matcha_march_cfg *cfg, int32_t Kc, float *cand, float *best,
                                   int32_t *best_idx, uint32_t *status, void *ws, size_t ws_bytes, void *stream);
@@ -325,14 +339,17 @@ matcha_status matcha_graph_launch(matcha_graph *g, void *stream);
 matcha_status matcha_graph_destroy(matcha_graph *g);
 
 /* Autotuner: when the context's tune cache holds a result for this device, batch shape and
- * configuration, applies it and returns it without timing.  Otherwise times every supported launch
- * shape of the SOFFT search and of the march on this batch (hipEvents, `reps` repetitions each,
- * after one warm-up), keeps the fastest in the context (later calls use it), adds it to the tune
- * cache file and returns it in *best_tuning (host).  cand / best / best_idx / status are used as
- * scratch and hold the last trial's (valid) results.  Synchronous. */
-matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *soft,
-                              const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
-                              uint32_t *status, int32_t reps, void *ws, size_t ws_bytes, matcha_tuning *best_tuning);
+ * configuration, applies it and returns it without timing.  Otherwise times, on this batch
+ * (hipEvents, `reps` repetitions each after one warm-up), one field of matcha_tuning at a time with
+ * the others at their best so far: the assembly's row tiles per wave (bufs->f, h, w, prec into
+ * bufs->C), the SOFFT ranking workgroup and grid-kernel nodes per wave, then the march's candidates
+ * per wave and launch form (each march trial re-runs the search so that it starts from fresh
+ * candidates); keeps the fastest in the context (later calls use it), adds it to the tune cache
+ * file and returns it in *best_tuning (host).  bufs->C, cand, best, best_idx and status hold the
+ * last trial's (valid) results; bufs->f32 / h32 / C32 are not used.  Synchronous. */
+matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const matcha_align_bufs *bufs,
+                              const matcha_soft_cfg *soft, const matcha_march_cfg *march, int32_t reps, void *ws,
+                              size_t ws_bytes, matcha_tuning *best_tuning);
 
 #ifdef __cplusplus
 }

@@ -30,8 +30,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kAsmThreads = 256;
 constexpr int kAsmWaves = kAsmThreads / kWave;
-constexpr int kAsmTilesPerWave = 4;  // row tiles per wave and workgroup
-constexpr int kAsmTilesPerBlock = kAsmWaves * kAsmTilesPerWave;
+constexpr int kAsmTilesPerWave = 4;  // default row tiles per wave and workgroup (a.tiles_per_wave)
 
 __device__ inline void store_half_plane(float2 *Cp2, int l, int m, int n, float2 v)
 {
@@ -78,8 +77,9 @@ __global__ void __launch_bounds__(kAsmThreads) k_assemble_f32(AsmArgs a)
     const int col = lane % 16, kq = lane / 16;
     const int par = kq & 1, rsub = kq >> 1;  // K index 4 s + kq = 2 (2 s + rsub) + par
     const int nsteps = (R + 1) / 2;
-    for (int it = 0; it < kAsmTilesPerWave; ++it) {
-        const int rt = blk * kAsmTilesPerBlock + it * kAsmWaves + wave;
+    const int tpb = kAsmWaves * a.tiles_per_wave;
+    for (int it = 0; it < a.tiles_per_wave; ++it) {
+        const int rt = blk * tpb + it * kAsmWaves + wave;
         if (rt >= RT) break;
         // the lane's A row
         const int rho = min(16 * rt + col, rows - 1);
@@ -181,13 +181,15 @@ hipError_t launch_assemble_f32(const AsmArgs &a0, int P, int Lmax, int Rmax, hip
     a.P = P;
     a.Lmax = Lmax;
     a.Rmax = Rmax;
+    if (a.tiles_per_wave < 1) a.tiles_per_wave = kAsmTilesPerWave;
+    const int tpb = kAsmWaves * a.tiles_per_wave;
     int nb = 0;
     for (int d = 0; d <= Lmax; ++d) {
         const int l = Lmax - d;
         if (!a.by_L) a.np_l[l] = P;
         const int64_t rt = ((int64_t)a.np_l[l] * (l + 1) + 15) / 16;
         a.blk_lo[d] = nb;
-        nb += (int)((rt + kAsmTilesPerBlock - 1) / kAsmTilesPerBlock);
+        nb += (int)((rt + tpb - 1) / tpb);
     }
     a.blk_lo[Lmax + 1] = nb;
     if (nb == 0) return hipSuccess;

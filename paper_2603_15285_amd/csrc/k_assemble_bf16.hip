@@ -30,8 +30,7 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 constexpr int kAsmBThreads = 256;
 constexpr int kAsmBWaves = kAsmBThreads / kWave;
 constexpr int kAsmBMaxSteps = 4;      // 32-wide K steps (16 shells each) held in registers at a time
-constexpr int kAsmBTilesPerWave = 4;  // row tiles per wave and workgroup
-constexpr int kAsmBTilesPerBlock = kAsmBWaves * kAsmBTilesPerWave;
+constexpr int kAsmBTilesPerWave = 4;  // default row tiles per wave and workgroup (a.tiles_per_wave)
 
 __device__ inline void store_half_plane_b(float2 *Cp2, int l, int m, int n, float2 v)
 {
@@ -83,8 +82,9 @@ __global__ void __launch_bounds__(kAsmBThreads) k_assemble_bf16(AsmBArgs a)
     const int col = lane % 16, kg = lane / 16;  // K elements 8 kg .. +7: shells 4 kg .. +3 of a step
     const int nk = K / 32;
     const uint32_t *f32 = reinterpret_cast<const uint32_t *>(a.f);  // one complex BF16 value per word
-    for (int it = 0; it < kAsmBTilesPerWave; ++it) {
-        const int rt = blk * kAsmBTilesPerBlock + it * kAsmBWaves + wave;
+    const int tpb = kAsmBWaves * a.tiles_per_wave;
+    for (int it = 0; it < a.tiles_per_wave; ++it) {
+        const int rt = blk * tpb + it * kAsmBWaves + wave;
         if (rt >= RT) break;
         const int rho = min(16 * rt + col, rows - 1);
         const int pi = rho / (l + 1), m = rho - pi * (l + 1);
@@ -158,13 +158,15 @@ hipError_t launch_assemble_bf16(const AsmBArgs &a0, int P, int Lmax, int Rmax, h
     a.P = P;
     a.Lmax = Lmax;
     a.Rmax = Rmax;
+    if (a.tiles_per_wave < 1) a.tiles_per_wave = kAsmBTilesPerWave;
+    const int tpb = kAsmBWaves * a.tiles_per_wave;
     int nb = 0;
     for (int d = 0; d <= Lmax; ++d) {
         const int l = Lmax - d;
         if (!a.by_L) a.np_l[l] = P;
         const int64_t rt = ((int64_t)a.np_l[l] * (l + 1) + 15) / 16;
         a.blk_lo[d] = nb;
-        nb += (int)((rt + kAsmBTilesPerBlock - 1) / kAsmBTilesPerBlock);
+        nb += (int)((rt + tpb - 1) / tpb);
     }
     a.blk_lo[Lmax + 1] = nb;
     if (nb == 0) return hipSuccess;

@@ -14,6 +14,8 @@
 // is applied once per pair afterwards, together with the m and n weights of the
 // a / c derivatives.  D^l = d^l / P_l is the recurrence normalised so that its
 // three-term relation has unit coefficient on D^{l-2} (P_l is tabulated per pair).
+#include <algorithm>
+
 #include "matcha_launch.hpp"
 
 namespace matcha {
@@ -492,11 +494,15 @@ __device__ __forceinline__ void prepare_step(WaveState<NC> &st, WaveScratch<NC> 
     wave_sync();
 }
 
+// One workgroup per particle (the hardware starts workgroups in index order as slots free up), or,
+// with a.queue, a persistent grid that fills the chip once: each workgroup takes the next particle
+// index from the counter until the batch is done (every workgroup then sees an index >= P and
+// leaves).  Either way particle b of the order is processed the same way.
 template <int NC, bool F64>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) k_march(MarchArgs a)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    const int p = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
+    __shared__ int next_b;
     const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
     const int G = blockDim.x / kWave;
     WaveScratch<NC> &ws = reinterpret_cast<WaveScratch<NC> *>(smem)[wave];
@@ -504,6 +510,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
     float *fin = reinterpret_cast<float *>(smem + G * (sizeof(WaveScratch<NC>) + sizeof(WaveState<NC>)));
     uint32_t *fst = reinterpret_cast<uint32_t *>(fin + G * NC);
 
+    int b = (int)blockIdx.x;
+    if (a.queue) {
+        if (threadIdx.x == 0) next_b = atomicAdd(a.queue, 1);
+        __syncthreads();
+        b = next_b;
+    }
+    while (b < a.P) {
+    const int p = a.order ? a.order[b] : b;
     const int Lp = a.Lp[p];
     const float4 *Cp = a.C + a.C_off[p] / 2;
     const float4 *Cf = (a.C_fin ? a.C_fin : a.C) + a.C_off[p] / 2;  // the final level's coefficients
@@ -585,16 +599,24 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        int b = 0;
+        int bi = 0;
         for (int k = 1; k < a.Kc; ++k) {
-            const float F = fin[k], Fb = fin[b];
-            if (isfinite(F) && (!isfinite(Fb) || F > Fb)) b = k;
+            const float F = fin[k], Fb = fin[bi];
+            if (isfinite(F) && (!isfinite(Fb) || F > Fb)) bi = k;
         }
-        a.best[p] = a.cand[(int64_t)p * a.Kc + b];
-        a.best_idx[p] = b;
-        a.status[p] |= fst[b];
+        a.best[p] = a.cand[(int64_t)p * a.Kc + bi];
+        a.best_idx[p] = bi;
+        a.status[p] |= fst[bi];
+    }
+    if (!a.queue) break;
+    __syncthreads();  // the selection has read fin / fst and every wave is done with its LDS state
+    if (threadIdx.x == 0) next_b = atomicAdd(a.queue, 1);
+    __syncthreads();
+    b = next_b;
     }
 }
+
+__global__ void k_zero_counter(int *q) { *q = 0; }
 
 // Objective, gradient and Hessian at one rotation per particle (one wave per particle).
 __global__ void __launch_bounds__(64) k_evaluate(EvalArgs a)
@@ -628,15 +650,35 @@ size_t march_smem_bytes(int G)
     return (size_t)G * (sizeof(WaveScratch<NC>) + sizeof(WaveState<NC>)) + (size_t)G * NC * 8;
 }
 
-template <int NC>
-hipError_t launch_march(const MarchArgs &a, int P, bool f64, hipStream_t s)
+// Workgroups of a persistent launch: as many as are resident at once (at most one per particle).
+template <typename K>
+int persistent_grid(K kernel, int threads, size_t smem, int P)
 {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, smem) != hipSuccess)
+        return -1;
+    return std::max(1, std::min(P, std::max(1, per_cu) * cus));
+}
+
+template <int NC>
+hipError_t launch_march(const MarchArgs &a0, int P, bool f64, hipStream_t s)
+{
+    MarchArgs a = a0;
+    a.P = P;
     const int G = (a.Kc + NC - 1) / NC;
     const size_t sm = march_smem_bytes<NC>(G);
-    if (f64)
-        hipLaunchKernelGGL((k_march<NC, true>), dim3(P), dim3(G * kWave), sm, s, a);
-    else
-        hipLaunchKernelGGL((k_march<NC, false>), dim3(P), dim3(G * kWave), sm, s, a);
+    auto kern = f64 ? k_march<NC, true> : k_march<NC, false>;
+    int grid = P;
+    if (a.queue) {
+        grid = persistent_grid(kern, G * kWave, sm, P);
+        if (grid < 1) return hipErrorInvalidValue;
+        hipLaunchKernelGGL(k_zero_counter, dim3(1), dim3(1), 0, s, a.queue);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(G * kWave), sm, s, a);
     return hipGetLastError();
 }
 

@@ -335,8 +335,9 @@ __global__ void __launch_bounds__(256) k_soft_grid(SoftArgs a)
 //     transpose between the four 16-lane rows, done with two rounds of lane-row swaps
 //     (v_permlane32_swap exchanges rows 2-3 of one register with rows 0-1 of another,
 //     v_permlane16_swap rows 1 and 3 of one with rows 0 and 2 of another).
-// A wave takes kGridRegNodes consecutive nodes (in a particle-major order) on its own.
-constexpr int kGridRegNodes = 16;  // even: the node loop is unrolled by two
+// A wave takes a.grid_nodes consecutive nodes (in a particle-major order) on its own; an even count
+// (the node loop is unrolled by two), kGridRegNodes by default.
+constexpr int kGridRegNodes = 16;
 
 // In-register 4 x 4 transpose across lane rows: x[j] of row r becomes x[r] of row j.
 __device__ __forceinline__ void transpose_rows(float (&x)[4])
@@ -429,9 +430,9 @@ __global__ void __launch_bounds__(256) k_soft_grid_reg(SoftArgs a)
     constexpr int KS1 = BB + 1, KS2 = (BB + 2) / 2, KP = 4 * KS1, NP = 16 * NT, A2W = 4 * KS2;
     const int lane = threadIdx.x % kWave, col = lane % 16, kq = lane / 16;
     const int nodes = a.np * a.n;
-    const int nd0 = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * kGridRegNodes;
+    const int nd0 = (blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave) * a.grid_nodes;
     if (nd0 >= nodes) return;  // no barrier in this kernel
-    const int nd1 = min(nd0 + kGridRegNodes, nodes);
+    const int nd1 = min(nd0 + a.grid_nodes, nodes);
     const float *B1r = a.dft, *A2 = a.dft + 2 * KP * NP;
     float br[NT][KS1], a2[NT][KS2];
 #pragma unroll
@@ -1033,7 +1034,8 @@ hipError_t launch_soft_grid(const SoftArgs &a0, int P, hipStream_t s)
     SoftArgs a = a0;
     a.np = P;
     if (soft_grid_reg_shape(a.n, a.B)) {
-        const int waves = (P * a.n + kGridRegNodes - 1) / kGridRegNodes;
+        if (a.grid_nodes < 2 || (a.grid_nodes & 1)) a.grid_nodes = kGridRegNodes;
+        const int waves = (P * a.n + a.grid_nodes - 1) / a.grid_nodes;
         if (a.B == 12)
             hipLaunchKernelGGL((k_soft_grid_reg<12, 3>), dim3((waves + 3) / 4), dim3(256), 0, s, a);
         else

@@ -45,7 +45,7 @@ struct matcha_ctx {
     double2 *tab64 = nullptr;  // (A, AC) of tab in FP64
     PairInfo *pinfo = nullptr;
     std::vector<GridTables> grids;  // every prepared (B, n); freed by matcha_destroy only
-    matcha_tuning tune{0, 0};
+    matcha_tuning tune{0, 0, 0, 0, 0};
     std::string tune_path;  // tune cache file, empty: none
     std::map<std::string, matcha_tuning> tune_cache;
     std::string arch;  // device name and compute-unit count, part of every tune cache key
@@ -226,6 +226,9 @@ size_t soft_ws_need(int P, int n, int B)
 // Assembly of mixed L_p: the particle order by decreasing L_p, P int32 at the head of ws.
 size_t assemble_ws_need(int P, bool mixed) { return mixed ? sizeof(int32_t) * (size_t)P : 0; }
 
+// The persistent march's work counter at the head of ws.
+constexpr size_t kMarchWs = 256;
+
 // Adjoint: P int64 offsets of the particles' template terms (packed by the library, whatever
 // f_offset is), then the terms, R_p (L_p+1)^2 complex float32 each.
 size_t grad_terms(const matcha_batch *b)
@@ -337,6 +340,7 @@ matcha_status assemble_launch(matcha_ctx *ctx, const matcha_batch *batch, const 
         b.Lh = batch->L_h;
         b.C = reinterpret_cast<float4 *>(C);
         b.C_off = batch->C_offset;
+        b.tiles_per_wave = ctx->tune.asm_tiles;
         if (mixed) {
             b.by_L = by_L;
             std::memcpy(b.np_l, np_l, sizeof(int) * (size_t)(hi + 1));
@@ -354,6 +358,7 @@ matcha_status assemble_launch(matcha_ctx *ctx, const matcha_batch *batch, const 
     a.Lh = batch->L_h;
     a.C = reinterpret_cast<float4 *>(C);
     a.C_off = batch->C_offset;
+    a.tiles_per_wave = ctx->tune.asm_tiles;
     if (mixed) {
         a.by_L = by_L;
         std::memcpy(a.np_l, np_l, sizeof(int) * (size_t)(hi + 1));
@@ -410,6 +415,7 @@ matcha_status soft_launch(const matcha_ctx *ctx, const matcha_batch *batch, cons
     a.B = B;
     a.n = n;
     a.Kc = cfg->Kc;
+    a.grid_nodes = ctx->tune.grid_nodes;
     a.grid = reinterpret_cast<float *>(base + ch.grid);
     a.mlist = reinterpret_cast<unsigned long long *>(base + ch.list);
     a.mcount = reinterpret_cast<uint32_t *>(base + ch.count);
@@ -448,7 +454,7 @@ matcha_status march_check(const matcha_batch *batch, const matcha_march_cfg *cfg
 // input of the timing: the batch's size and band / shell statistics, the search shape and the
 // march schedule.
 std::string tune_key(const matcha_ctx *ctx, const matcha_batch *b, const matcha_soft_cfg *soft,
-                     const matcha_march_cfg *march)
+                     const matcha_march_cfg *march, matcha_precision prec)
 {
     long long sL = 0, sR = 0;
     int lo = 1 << 30, hi = -1, rlo = 1 << 30, rhi = -1;
@@ -467,7 +473,7 @@ std::string tune_key(const matcha_ctx *ctx, const matcha_batch *b, const matcha_
                     std::to_string(soft->Kc) + "|lv";
     for (int j = 0; j < march->n_levels; ++j) k += (j ? "," : "") + std::to_string(march->levels[j]);
     k += "|s" + std::to_string(march->steps) + "|f64_" + std::to_string(march->fp64_above) + "|es" +
-         std::to_string(march->early_stop);
+         std::to_string(march->early_stop) + "|pr" + std::to_string((int)prec);
     for (char &c : k)
         if (c == ' ' || c == '\t' || c == '\n') c = '_';
     return k;
@@ -480,8 +486,10 @@ void tune_cache_load(matcha_ctx *ctx)
     char line[4096];
     while (std::fgets(line, sizeof line, fp)) {
         char key[4000];
-        int nc = 0, st = 0;
-        if (std::sscanf(line, "%3999s %d %d", key, &nc, &st) == 3) ctx->tune_cache[key] = matcha_tuning{nc, st};
+        matcha_tuning t{0, 0, 0, 0, 0};
+        if (std::sscanf(line, "%3999s %d %d %d %d %d", key, &t.march_nc, &t.soft_threads, &t.asm_tiles, &t.grid_nodes,
+                        &t.march_persistent) == 6)
+            ctx->tune_cache[key] = t;
     }
     std::fclose(fp);
 }
@@ -491,7 +499,8 @@ bool tune_cache_store(const matcha_ctx *ctx, const std::string &key, const match
     if (ctx->tune_path.empty()) return true;
     FILE *fp = std::fopen(ctx->tune_path.c_str(), "a");
     if (!fp) return false;
-    std::fprintf(fp, "%s %d %d\n", key.c_str(), t.march_nc, t.soft_threads);
+    std::fprintf(fp, "%s %d %d %d %d %d\n", key.c_str(), t.march_nc, t.soft_threads, t.asm_tiles, t.grid_nodes,
+                 t.march_persistent);
     return std::fclose(fp) == 0;
 }
 
@@ -587,6 +596,11 @@ matcha_status matcha_set_tuning(matcha_ctx *ctx, const matcha_tuning *t)
     if (nc != 0 && nc != 1 && nc != 2 && nc != 4 && nc != 8) return MATCHA_ERR_INVALID_ARG;
     const int st = t->soft_threads;
     if (st != 0 && st != 256 && st != 512) return MATCHA_ERR_INVALID_ARG;
+    const int at = t->asm_tiles;
+    if (at != 0 && at != 1 && at != 2 && at != 4 && at != 8) return MATCHA_ERR_INVALID_ARG;
+    const int gn = t->grid_nodes;
+    if (gn != 0 && gn != 8 && gn != 16 && gn != 32) return MATCHA_ERR_INVALID_ARG;
+    if (t->march_persistent != 0 && t->march_persistent != 1) return MATCHA_ERR_INVALID_ARG;
     ctx->tune = *t;
     return MATCHA_OK;
 }
@@ -617,7 +631,7 @@ size_t matcha_workspace_size(const matcha_ctx *ctx, const matcha_batch *batch, c
     (void)march;
     int lo, hi, rmax;
     if (check_batch(batch, &lo, &hi, &rmax) != MATCHA_OK || batch->n_particles == 0) return 0;
-    size_t need = assemble_ws_need(batch->n_particles, lo != hi);
+    size_t need = std::max(assemble_ws_need(batch->n_particles, lo != hi), kMarchWs);
     if (soft && soft->B >= 1 && soft->n_grid >= 4)
         need = std::max(need, soft_ws_need(batch->n_particles, soft->n_grid, soft->B));
     return need;
@@ -727,17 +741,18 @@ matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, co
                                   const matcha_march_cfg *cfg, int32_t Kc, float *cand, float *best,
                                   int32_t *best_idx, uint32_t *status, void *ws, size_t ws_bytes, void *stream)
 {
-    (void)ws;
-    (void)ws_bytes;
     int lo, hi, rmax;
-    if (!ctx || !cfg) return MATCHA_ERR_INVALID_ARG;
+    if (!cfg) return MATCHA_ERR_INVALID_ARG;
     matcha_status st = check_batch(batch, &lo, &hi, &rmax);
     if (st != MATCHA_OK) return st;
-    if (batch->n_particles == 0) return MATCHA_OK;
+    if (batch->n_particles == 0) return ctx ? MATCHA_OK : MATCHA_ERR_INVALID_ARG;
     if (!C || !cand || !best || !best_idx || !status || !aligned16(C) || !aligned16(cand) || !aligned16(best))
         return MATCHA_ERR_INVALID_ARG;
     st = march_check(batch, cfg, Kc, lo);
     if (st != MATCHA_OK) return st;
+    if (!ctx) return MATCHA_ERR_INVALID_ARG;
+    const bool persist = ctx->tune.march_persistent != 0;
+    if (persist && (!ws || !aligned16(ws) || ws_bytes < kMarchWs)) return MATCHA_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
     MarchArgs a;
     std::memset(&a, 0, sizeof a);
@@ -763,6 +778,7 @@ matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, co
     a.best_idx = best_idx;
     a.status = status;
     a.order = batch->order;
+    a.queue = persist ? static_cast<int *>(ws) : nullptr;
     const int nc = march_nc(ctx, Kc);
     const bool f64 = a.fp64_above < hi;  // a level above the threshold: some particle's L_p
     return launched(launch_march_any(a, batch->n_particles, nc, f64, static_cast<hipStream_t>(stream)));
@@ -858,7 +874,7 @@ matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *bat
         st = assemble_check(batch, bufs->f, bufs->h, bufs->w, bufs->C, bufs->prec, hi, rmax);
         if (st == MATCHA_OK && fin) st = assemble_check(batch, bufs->f32, bufs->h32, bufs->w, bufs->C32, MATCHA_FP32, hi, rmax);
         if (st != MATCHA_OK) return st;
-        if (ws_bytes < assemble_ws_need(P, lo != hi)) return MATCHA_ERR_WORKSPACE;
+        if (ws_bytes < std::max(assemble_ws_need(P, lo != hi), kMarchWs)) return MATCHA_ERR_WORKSPACE;
     }
     matcha_march_cfg mc = *march;
     mc.C_final = fin ? bufs->C32 : nullptr;
@@ -889,7 +905,7 @@ matcha_status matcha_align_graph_create(matcha_ctx *ctx, const matcha_batch *bat
             st = soft_launch(ctx, batch, bufs->C, soft, gt, bufs->cand, bufs->status, nt, ws, ws_bytes, cs);
         if (st == MATCHA_OK)
             st = matcha_march_newton(ctx, batch, bufs->C, &mc, soft->Kc, bufs->cand, bufs->best, bufs->best_idx,
-                                     bufs->status, nullptr, 0, cs);
+                                     bufs->status, ws, ws_bytes, cs);
     }
     hipGraph_t graph = nullptr;
     const hipError_t ec = hipStreamEndCapture(cs, &graph);
@@ -924,15 +940,15 @@ matcha_status matcha_graph_destroy(matcha_graph *g)
     return MATCHA_OK;
 }
 
-matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const float *C, const matcha_soft_cfg *soft,
-                              const matcha_march_cfg *march, float *cand, float *best, int32_t *best_idx,
-                              uint32_t *status, int32_t reps, void *ws, size_t ws_bytes, matcha_tuning *best_tuning)
+matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const matcha_align_bufs *bufs,
+                              const matcha_soft_cfg *soft, const matcha_march_cfg *march, int32_t reps, void *ws,
+                              size_t ws_bytes, matcha_tuning *best_tuning)
 {
     int lo, hi, rmax;
-    if (!ctx || !soft || !march || !best_tuning || reps < 1) return MATCHA_ERR_INVALID_ARG;
+    if (!ctx || !bufs || !soft || !march || !best_tuning || reps < 1) return MATCHA_ERR_INVALID_ARG;
     matcha_status st = check_batch(batch, &lo, &hi, &rmax);
     if (st != MATCHA_OK) return st;
-    const std::string key = tune_key(ctx, batch, soft, march);
+    const std::string key = tune_key(ctx, batch, soft, march, bufs->prec);
     const auto hit = ctx->tune_cache.find(key);
     if (hit != ctx->tune_cache.end()) {
         st = matcha_set_tuning(ctx, &hit->second);
@@ -957,43 +973,62 @@ matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const 
         if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) return MATCHA_ERR_HIP;
         return hipEventElapsedTime(ms, e0, e1) == hipSuccess ? MATCHA_OK : MATCHA_ERR_HIP;
     };
+    // one field at a time: try each value with the others at their best so far; shapes a call
+    // cannot take (MATCHA_ERR_UNSUPPORTED) are skipped
     matcha_tuning best_t = saved;
-    // SOFFT workgroup size
-    float best_ms = 1e30f;
-    for (int nt : {256, 512}) {
-        ctx->tune.soft_threads = nt;
-        float ms = 0.f;
-        st = time_it([&] { return matcha_soft_search(ctx, batch, C, soft, cand, status, ws, ws_bytes, s); }, &ms);
-        if (st == MATCHA_ERR_UNSUPPORTED) {  // this shape does not fit the workgroup's LDS
-            st = MATCHA_OK;
-            continue;
+    auto tune_field = [&](int32_t matcha_tuning::*field, std::initializer_list<int32_t> values, auto &&run) {
+        float best_ms = 1e30f;
+        for (int32_t v : values) {
+            if (st != MATCHA_OK) return;
+            ctx->tune = best_t;
+            ctx->tune.*field = v;
+            float ms = 0.f;
+            st = time_it(run, &ms);
+            if (st == MATCHA_ERR_UNSUPPORTED) {
+                st = MATCHA_OK;
+                continue;
+            }
+            if (st == MATCHA_OK && ms < best_ms) {
+                best_ms = ms;
+                best_t.*field = v;
+            }
         }
-        if (st != MATCHA_OK) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best_t.soft_threads = nt;
-        }
-    }
-    // march candidates per wave (each trial re-runs the search so that it starts from fresh candidates)
-    ctx->tune.soft_threads = best_t.soft_threads;
-    best_ms = 1e30f;
-    for (int nc : {2, 4, 8}) {
-        if (st != MATCHA_OK) break;
-        if ((soft->Kc + nc - 1) / nc > 8) continue;
-        ctx->tune.march_nc = nc;
-        float ms = 0.f;
-        st = time_it(
-            [&] {
-                matcha_status r = matcha_soft_search(ctx, batch, C, soft, cand, status, ws, ws_bytes, s);
-                return r == MATCHA_OK ? matcha_march_newton(ctx, batch, C, march, soft->Kc, cand, best, best_idx,
-                                                            status, nullptr, 0, s)
-                                      : r;
-            },
-            &ms);
-        if (st == MATCHA_OK && ms < best_ms) {
-            best_ms = ms;
-            best_t.march_nc = nc;
-        }
+    };
+    auto assemble = [&] {
+        return matcha_coeff_assemble(ctx, batch, bufs->f, bufs->h, bufs->w, bufs->C, bufs->prec, ws, ws_bytes, s);
+    };
+    auto search = [&] {
+        return matcha_soft_search(ctx, batch, bufs->C, soft, bufs->cand, bufs->status, ws, ws_bytes, s);
+    };
+    auto search_march = [&] {
+        matcha_status r = search();
+        return r == MATCHA_OK ? matcha_march_newton(ctx, batch, bufs->C, march, soft->Kc, bufs->cand, bufs->best,
+                                                    bufs->best_idx, bufs->status, ws, ws_bytes, s)
+                              : r;
+    };
+    tune_field(&matcha_tuning::asm_tiles, {1, 2, 4, 8}, assemble);
+    tune_field(&matcha_tuning::soft_threads, {256, 512}, search);
+    tune_field(&matcha_tuning::grid_nodes, {8, 16, 32}, search);
+    std::vector<int32_t> ncs;
+    for (int nc : {2, 4, 8})
+        if ((soft->Kc + nc - 1) / nc <= 8) ncs.push_back(nc);
+    // candidates per wave and launch form together (the persistent grid's size depends on both)
+    {
+        float best_ms = 1e30f;
+        for (int32_t nc : ncs)
+            for (int32_t pers : {0, 1}) {
+                if (st != MATCHA_OK) break;
+                ctx->tune = best_t;
+                ctx->tune.march_nc = nc;
+                ctx->tune.march_persistent = pers;
+                float ms = 0.f;
+                st = time_it(search_march, &ms);
+                if (st == MATCHA_OK && ms < best_ms) {
+                    best_ms = ms;
+                    best_t.march_nc = nc;
+                    best_t.march_persistent = pers;
+                }
+            }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);

@@ -16,6 +16,7 @@ struct AsmArgs {
     const int64_t *C_off;
     const int32_t *by_L;      // nullable: particle indices by decreasing L_p (k_order_by_L); null: all L_p equal
     int P, Lmax, Rmax;        // set by the launcher
+    int tiles_per_wave;       // 16-row tiles per wave and workgroup (0: default)
     int blk_lo[kMaxL + 2];    // first workgroup of degree Lmax - d, d = 0 .. Lmax; [Lmax+1]: total
     int np_l[kMaxL + 1];      // particles with L_p >= l: the first np_l[l] entries of by_L (or all P)
 };
@@ -32,6 +33,7 @@ struct AsmBArgs {
     const int64_t *C_off;
     const int32_t *by_L;      // nullable: particle indices by decreasing L_p (k_order_by_L); null: all L_p equal
     int P, Lmax, Rmax;        // set by the launcher
+    int tiles_per_wave;       // 16-row tiles per wave and workgroup (0: default)
     int blk_lo[kMaxL + 2];    // first workgroup of degree Lmax - d, d = 0 .. Lmax; [Lmax+1]: total
     int np_l[kMaxL + 1];      // particles with L_p >= l: the first np_l[l] entries of by_L (or all P)
 };
@@ -44,6 +46,7 @@ struct SoftArgs {
     const PairInfo *pinfo;
     int B, n, Kc;
     int gslices;              // waves per workgroup of the grid kernel (set by its launcher)
+    int grid_nodes;           // polar nodes per wave of the register-resident grid kernel (even; 0: default)
     int p0;                   // first particle of this launch
     int np;                   // particles in this launch (set by the grid launcher)
     float *grid;              // [launch particles][n][n][n] workspace: C_B on the grid
@@ -75,7 +78,9 @@ struct MarchArgs {
     float4 *best;
     int32_t *best_idx;
     uint32_t *status;
-    const int32_t *order;     // nullable processing order (workgroup b takes particle order[b])
+    const int32_t *order;     // nullable processing order (the b-th particle taken is order[b])
+    int P;                    // particles
+    int *queue;               // nullable: work counter of the persistent kernel (zeroed by its launcher)
 };
 
 struct EvalArgs {

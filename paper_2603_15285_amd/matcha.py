@@ -41,8 +41,11 @@ class _Batch(ct.Structure):
                 ("L_h", ct.c_int32), ("R_h", ct.c_int32), ("order", ct.c_void_p)]
 
 
+TUNING_FIELDS = ("march_nc", "soft_threads", "asm_tiles", "grid_nodes", "march_persistent")
+
+
 class _Tuning(ct.Structure):
-    _fields_ = [("march_nc", ct.c_int32), ("soft_threads", ct.c_int32)]
+    _fields_ = [(name, ct.c_int32) for name in TUNING_FIELDS]
 
 
 class _SoftCfg(ct.Structure):
@@ -101,7 +104,7 @@ def lib():
                                                 ct.POINTER(_MarchCfg), vp, sz, ct.POINTER(vp)]
         L.matcha_graph_launch.argtypes = [vp, vp]
         L.matcha_graph_destroy.argtypes = [vp]
-        L.matcha_autotune.argtypes = [vp, bp, vp, ct.POINTER(_SoftCfg), ct.POINTER(_MarchCfg), vp, vp, vp, vp, i32,
+        L.matcha_autotune.argtypes = [vp, bp, ct.POINTER(_AlignBufs), ct.POINTER(_SoftCfg), ct.POINTER(_MarchCfg), i32,
                                       vp, sz, ct.POINTER(_Tuning)]
         for name in ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_set_tuning", "matcha_get_tuning",
                      "matcha_lpt_order", "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton",
@@ -169,14 +172,15 @@ class Context:
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=f"cuda:{self.device}")
         return self._ws
 
-    def set_tuning(self, march_nc: int = 0, soft_threads: int = 0):
-        t = _Tuning(int(march_nc), int(soft_threads))
+    def set_tuning(self, march_nc: int = 0, soft_threads: int = 0, asm_tiles: int = 0, grid_nodes: int = 0,
+                   march_persistent: int = 0):
+        t = _Tuning(int(march_nc), int(soft_threads), int(asm_tiles), int(grid_nodes), int(march_persistent))
         _check(lib().matcha_set_tuning(self.handle, ct.byref(t)), "matcha_set_tuning")
 
     def get_tuning(self) -> dict:
         t = _Tuning()
         _check(lib().matcha_get_tuning(self.handle, ct.byref(t)), "matcha_get_tuning")
-        return {"march_nc": int(t.march_nc), "soft_threads": int(t.soft_threads)}
+        return {name: int(getattr(t, name)) for name in TUNING_FIELDS}
 
     def close(self):
         if self.handle:
@@ -341,8 +345,10 @@ def march_newton(ctx: Context, batch: Batch, C: torch.Tensor, levels: Sequence[i
         _need(C_final, torch.float32, "C_final")
     cfg = _march_cfg(levels, steps, max_step, early_stop, tol_grad, tol_step, tol_rel, fp64_above, C_final)
     bs = batch.c_struct()
+    nb = workspace_bytes(batch)
+    ws = ctx.workspace(nb)
     _check(lib().matcha_march_newton(ctx.handle, ct.byref(bs), _ptr(C), ct.byref(cfg), Kc, _ptr(cand), _ptr(best),
-                                     _ptr(best_idx), _ptr(status), None, 0, ct.c_void_p(_stream(stream))),
+                                     _ptr(best_idx), _ptr(status), _ptr(ws), nb, ct.c_void_p(_stream(stream))),
            "matcha_march_newton")
     return best, best_idx, status
 
@@ -473,26 +479,29 @@ class AlignGraph:
             pass
 
 
-def autotune(ctx: Context, batch: Batch, C: torch.Tensor, B: int, n_grid: int, Kc: int, levels, steps: int,
-             reps: int = 2, fp64_above: int = 0) -> dict:
-    """Times the supported launch shapes on this batch and keeps the fastest in the context (or
-    applies the context's tune cache entry for this batch and configuration)."""
-    dev = C.device
+def autotune(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch.Tensor, B: int, n_grid: int,
+             Kc: int, levels, steps: int, reps: int = 2, fp64_above: int = 0, prec: int = FP32) -> dict:
+    """Times the supported launch and tile shapes on this batch (assembly of f, h, w; search; march)
+    and keeps the fastest in the context, or applies the context's tune cache entry for this batch
+    and configuration."""
+    dev = f.device
     ctx.prepare(B, n_grid)
+    C = torch.empty(2 * batch.c_total, dtype=torch.float32, device=dev)
     cand = torch.empty((batch.n, Kc, 4), dtype=torch.float32, device=dev)
     status = torch.empty(batch.n, dtype=torch.int32, device=dev)
     best = torch.empty((batch.n, 4), dtype=torch.float32, device=dev)
     best_idx = torch.empty(batch.n, dtype=torch.int32, device=dev)
+    io = _AlignBufs(f.data_ptr(), h.data_ptr(), w.data_ptr(), int(prec), None, None, C.data_ptr(), None,
+                    cand.data_ptr(), best.data_ptr(), best_idx.data_ptr(), status.data_ptr())
     soft = _SoftCfg(B, n_grid, Kc)
     march = _march_cfg(levels, steps, fp64_above=fp64_above)
     nb = workspace_bytes(batch, B, n_grid)
     ws = ctx.workspace(nb)
     t = _Tuning()
     bs = batch.c_struct()
-    _check(lib().matcha_autotune(ctx.handle, ct.byref(bs), _ptr(C), ct.byref(soft), ct.byref(march), _ptr(cand),
-                                 _ptr(best), _ptr(best_idx), _ptr(status), int(reps), _ptr(ws), nb, ct.byref(t)),
-           "matcha_autotune")
-    return {"march_nc": int(t.march_nc), "soft_threads": int(t.soft_threads)}
+    _check(lib().matcha_autotune(ctx.handle, ct.byref(bs), ct.byref(io), ct.byref(soft), ct.byref(march), int(reps),
+                                 _ptr(ws), nb, ct.byref(t)), "matcha_autotune")
+    return {name: int(getattr(t, name)) for name in TUNING_FIELDS}
 
 
 def c_unpack(L: int, C_wedge: np.ndarray) -> np.ndarray:

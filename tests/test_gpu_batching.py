@@ -63,23 +63,55 @@ def test_graph_replays_match_eager(M, ctx):
 
 
 def test_autotune_keeps_results(M):
+    """The tuner's choice and every other launch or tile shape (assembly row tiles per wave, grid
+    nodes per wave, ranking workgroup, march candidates per wave, persistent march) give the same
+    C, candidates and selections, bit for bit."""
     c = M.Context(0)
     wl = S.WORKLOADS["L32_R32_B12_K16"]
     b = S.make_workload("L32_R32_B12_K16", n_particles=128)
     batch, f, h, w = upload(M, b)
     ref = eager(M, c, batch, f, h, w, wl)
-    C = M.coeff_assemble(c, batch, f, h, w)
-    t = M.autotune(c, batch, C, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
-    assert t["march_nc"] in (2, 4, 8) and t["soft_threads"] in (256, 512)
+    refC = M.coeff_assemble(c, batch, f, h, w).clone()
+    t = M.autotune(c, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
+    assert t["march_nc"] in (2, 4, 8) and t["soft_threads"] in (256, 512) and t["asm_tiles"] in (1, 2, 4, 8)
+    assert t["grid_nodes"] in (8, 16, 32) and t["march_persistent"] in (0, 1)
     assert c.get_tuning() == t
     got = eager(M, c, batch, f, h, w, wl)
     for x, y in zip(got, ref):
         assert torch.equal(x, y)
-    for nc in (2, 8):
-        c.set_tuning(nc, 256)
+    for shape in [(2, 256, 1, 8, 1), (8, 512, 8, 32, 0), (4, 256, 2, 16, 1), (1, 0, 0, 0, 1)]:
+        c.set_tuning(*shape)
+        assert torch.equal(M.coeff_assemble(c, batch, f, h, w), refC), shape
         got = eager(M, c, batch, f, h, w, wl)
         for x, y in zip(got, ref):
-            assert torch.equal(x, y)
+            assert torch.equal(x, y), shape
+    with pytest.raises(M.MatchaError):
+        c.set_tuning(0, 0, 3, 0, 0)  # not a supported tile count
+    with pytest.raises(M.MatchaError):
+        c.set_tuning(0, 0, 0, 12, 0)
+    c.close()
+
+
+def test_persistent_march_uneven_longest_first(M):
+    """The persistent march (workgroups taking particles from a counter) on the uneven workload in
+    longest-first order, with more particles than resident workgroups: the same results, bit for
+    bit, as one workgroup per particle."""
+    c = M.Context(0)
+    wl = S.WORKLOADS["uneven_L24to48"]
+    b = S.make_workload("uneven_L24to48", n_particles=600)
+    batch, f, h, w = upload(M, b)
+    batch.set_lpt_order(wl.levels, wl.steps)
+    C = M.coeff_assemble(c, batch, f, h, w)
+    cand0, st0 = M.soft_search(c, batch, C, wl.B, wl.n_grid, wl.Kc)
+    out = {}
+    for pers in (0, 1):
+        c.set_tuning(4, 0, 0, 0, pers)
+        cand, st = cand0.clone(), st0.clone()
+        best, bi, st = M.march_newton(c, batch, C, wl.levels, wl.steps, cand, st, fp64_above=40)
+        torch.cuda.synchronize()
+        out[pers] = (cand, best, bi, st)
+    for x, y in zip(out[0], out[1]):
+        assert torch.equal(x, y)
     c.close()
 
 
@@ -112,7 +144,7 @@ def test_march_near_pole_candidates_independent_of_grouping(M):
     cand0[1::2, 13, 1] = 0.0
     out = {}
     for nc in (1, 2, 4, 8):
-        c.set_tuning(nc, 0)
+        c.set_tuning(nc, 0, 0, 0, nc % 2 == 0)
         cand, st = cand0.clone(), st0.clone()
         best, bi, st = M.march_newton(c, batch, C, wl.levels, wl.steps, cand, st)
         torch.cuda.synchronize()
@@ -246,17 +278,16 @@ def test_tune_cache_persists_results(M, tmp_path):
     b = S.make_workload("L32_R32_B12_K16", n_particles=64)
     batch, f, h, w = upload(M, b)
     c1 = M.Context(0, tune_cache=path)
-    C = M.coeff_assemble(c1, batch, f, h, w)
-    t1 = M.autotune(c1, batch, C, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
+    t1 = M.autotune(c1, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
     c1.close()
     lines = open(path).read().splitlines()
-    assert len(lines) == 1 and lines[0].split()[1:] == [str(t1["march_nc"]), str(t1["soft_threads"])]
+    assert len(lines) == 1 and lines[0].split()[1:] == [str(t1[k]) for k in M.TUNING_FIELDS]
     c2 = M.Context(0, tune_cache=path)
-    assert c2.get_tuning() == {"march_nc": 0, "soft_threads": 0}
-    t2 = M.autotune(c2, batch, C, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
+    assert c2.get_tuning() == {k: 0 for k in M.TUNING_FIELDS}
+    t2 = M.autotune(c2, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
     assert t2 == t1 and c2.get_tuning() == t1
     assert len(open(path).read().splitlines()) == 1
-    M.autotune(c2, batch, C, wl.B, wl.n_grid, wl.Kc, wl.levels, 2, reps=1)  # another schedule
+    M.autotune(c2, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, 2, reps=1)  # another schedule
     assert len(open(path).read().splitlines()) == 2
     c2.close()
 

@@ -71,15 +71,16 @@ def soft_chunk(pc, n, B):
 
 
 def test_workspace_size_is_the_largest_call_need():
-    """matcha_workspace_size = max(assembly order buffer, SOFFT chunk of the whole batch);
+    """matcha_workspace_size = max(assembly order buffer, SOFFT chunk of the whole batch, the
+    persistent march's 256-byte counter);
     matcha_grad_workspace_size = the adjoint's offsets and per-particle template terms."""
     L, R = [32, 10, 3], [32, 5, 2]
     b, keep = host_batch(L, R, 32, 32)
     grad = align256(8 * 3) + 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
     assert M.lib().matcha_grad_workspace_size(ct.byref(b)) == grad
-    assert M.lib().matcha_workspace_size(None, ct.byref(b), None, None) == 4 * 3
+    assert M.lib().matcha_workspace_size(None, ct.byref(b), None, None) == 256  # the march's work counter
     soft = M._SoftCfg(3, 12, 4)
-    want = max(soft_chunk(3, 12, 3), 4 * 3)
+    want = max(soft_chunk(3, 12, 3), 4 * 3, 256)
     assert M.lib().matcha_workspace_size(None, ct.byref(b), ct.byref(soft), None) == want
     soft = M._SoftCfg(12, 48, 16)
     assert M.lib().matcha_workspace_size(None, ct.byref(b), ct.byref(soft), None) == soft_chunk(3, 48, 12)

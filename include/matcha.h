@@ -211,8 +211,10 @@ int64_t matcha_f_elems(int32_t L, int32_t R);
 size_t matcha_workspace_size(const matcha_ctx *ctx, const matcha_batch *batch, const matcha_soft_cfg *soft,
                              const matcha_march_cfg *march);
 /* Bytes of workspace of matcha_grad_template with grad_h requested: P int64 offsets (256-byte
- * aligned) plus one template-gradient term of R_p (L_p+1)^2 complex float32 per particle.  0 for
- * an empty or invalid batch. */
+ * aligned), S partial template gradients of R_h (L_h+1)^2 complex float32 (256-byte aligned; the
+ * particles are summed in S consecutive segments, S = min(64, P, ceil(2048 / ceil(R_h (L_h+1)^2 /
+ * 256)))), and one template-gradient term of R_p (L_p+1)^2 complex float32 per particle.  0 for an
+ * empty or invalid batch. */
 size_t matcha_grad_workspace_size(const matcha_batch *batch);
 
 /* Longest-processing-time order (host): particle indices sorted by decreasing march cost
@@ -285,8 +287,9 @@ matcha_status matcha_evaluate(matcha_ctx *ctx, const matcha_batch *batch, const 
  *   grad_f_p[r][l,m] = g_p w_r sum_n D^l_mn(R_p*) h_ln(r)
  * grad_h: complex float32 [R_h][(L_h+1)^2] (entries outside every particle's
  * range are zeroed); grad_f: same layout as f; either may be NULL.  prec: MATCHA_FP32 only
- * (MATCHA_ERR_UNSUPPORTED otherwise).  The sum over particles is deterministic (particles in
- * index order, no floating-point atomics); each particle's term passes through ws (packed in the
+ * (MATCHA_ERR_UNSUPPORTED otherwise).  The sum over particles is deterministic (within each of S
+ * consecutive segments of particles in index order, then the segments in order; no floating-point
+ * atomics); each particle's term passes through ws (packed in the
  * library's own order, whatever f_offset is; MATCHA_ERR_WORKSPACE if ws_bytes is below
  * matcha_grad_workspace_size when grad_h is requested). */
 matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, const float *f, const float *h,

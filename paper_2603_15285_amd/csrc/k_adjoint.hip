@@ -17,6 +17,8 @@
 // The particle's grad_h term goes to a workspace at packed offsets (computed from L_p and R_p by a
 // first kernel, independent of the caller's f_offset); a last kernel sums the particles in index
 // order (no floating-point atomics, so the result is deterministic).
+#include <algorithm>
+
 #include "matcha_launch.hpp"
 
 namespace matcha {
@@ -177,27 +179,29 @@ __global__ void __launch_bounds__(kScanThreads) k_term_offsets(const int32_t *Lp
     }
 }
 
-// grad_h[r][lm] = sum over particles in index order of their terms (zero outside a particle's
-// shells and degrees).
+// Partial template gradients: segment sg (blockIdx.y) sums the terms of particles
+// [sg * seg_len, (sg + 1) * seg_len) in index order into part[sg][r][lm] (zero outside a particle's
+// shells and degrees).  Segments give the sum enough workgroups to fill the chip.
 __global__ void __launch_bounds__(256) k_grad_reduce(GradArgs a)
 {
-    const int64_t nl = (int64_t)(a.Lh + 1) * (a.Lh + 1);
+    const int64_t nl = (int64_t)(a.Lh + 1) * (a.Lh + 1), E = nl * a.Rh;
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= nl * a.Rh) return;
+    if (e >= E) return;
     const int r = (int)(e / nl);
     const int lm = (int)(e - (int64_t)r * nl);
     const int l = (int)sqrtf((float)lm + 0.5f);
+    const int pb = blockIdx.y * a.seg_len, pe = min(pb + a.seg_len, a.P);
     float2 s = make_float2(0.f, 0.f);
     // 16 particles' loads in flight at a time (clamped to a valid address where the particle has
     // no such term), then added in index order
     constexpr int U = 16;
-    for (int p0 = 0; p0 < a.P; p0 += U) {
+    for (int p0 = pb; p0 < pe; p0 += U) {
         float2 v[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int p = min(p0 + u, a.P - 1);
+            const int p = min(p0 + u, pe - 1);
             const int Lp = a.Lp[p], Rp = a.Rp[p];
-            const bool ok = p0 + u < a.P && r < Rp && l <= Lp;
+            const bool ok = p0 + u < pe && r < Rp && l <= Lp;
             v[u] = a.ws[ok ? a.ws_off[p] + (int64_t)r * (Lp + 1) * (Lp + 1) + lm : 0];
             if (!ok) v[u] = make_float2(0.f, 0.f);
         }
@@ -207,7 +211,29 @@ __global__ void __launch_bounds__(256) k_grad_reduce(GradArgs a)
             s.y += v[u].y;
         }
     }
+    a.part[blockIdx.y * E + e] = s;
+}
+
+// grad_h[r][lm] = the segments' partial sums added in segment order.
+__global__ void __launch_bounds__(256) k_grad_segments(GradArgs a)
+{
+    const int64_t E = (int64_t)(a.Lh + 1) * (a.Lh + 1) * a.Rh;
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= E) return;
+    float2 s = make_float2(0.f, 0.f);
+    for (int sg = 0; sg < a.n_seg; ++sg) {
+        const float2 v = a.part[sg * E + e];
+        s.x += v.x;
+        s.y += v.y;
+    }
     a.grad_h[e] = s;
+}
+
+int grad_segments(int64_t E, int P)
+{
+    const int64_t blocks = (E + 255) / 256;
+    const int64_t want = (2048 + blocks - 1) / blocks;  // about 2048 workgroups in the partial sums
+    return (int)std::max<int64_t>(1, std::min<int64_t>({want, 64, (int64_t)std::max(P, 1)}));
 }
 
 size_t grad_smem_bytes(int Lmax)
@@ -226,8 +252,15 @@ hipError_t launch_grad(const GradArgs &a, hipStream_t s)
     hipLaunchKernelGGL(k_grad_particle, dim3(a.P), dim3(kAdjThreads), grad_smem_bytes(a.L_max), s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !a.grad_h) return e;
+    GradArgs b = a;
     const int64_t n = (int64_t)(a.Lh + 1) * (a.Lh + 1) * a.Rh;
-    hipLaunchKernelGGL(k_grad_reduce, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, a);
+    b.n_seg = grad_segments(n, a.P);
+    b.seg_len = (a.P + b.n_seg - 1) / b.n_seg;
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(nb, (unsigned)b.n_seg), dim3(256), 0, s, b);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_grad_segments, dim3(nb), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

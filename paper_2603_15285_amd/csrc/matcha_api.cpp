@@ -230,7 +230,8 @@ size_t assemble_ws_need(int P, bool mixed) { return mixed ? sizeof(int32_t) * (s
 constexpr size_t kMarchWs = 256;
 
 // Adjoint: P int64 offsets of the particles' template terms (packed by the library, whatever
-// f_offset is), then the terms, R_p (L_p+1)^2 complex float32 each.
+// f_offset is), the partial sums of the segments of particles (grad_segments of them, each
+// R_h (L_h+1)^2 complex float32), then the terms, R_p (L_p+1)^2 complex float32 each.
 size_t grad_terms(const matcha_batch *b)
 {
     size_t n = 0;
@@ -238,9 +239,14 @@ size_t grad_terms(const matcha_batch *b)
         n += (size_t)b->R_host[p] * (size_t)(b->L_host[p] + 1) * (size_t)(b->L_host[p] + 1);
     return n;
 }
+size_t grad_part_bytes(const matcha_batch *b)
+{
+    const int64_t E = (int64_t)b->R_h * (b->L_h + 1) * (b->L_h + 1);
+    return align256((size_t)grad_segments(E, b->n_particles) * (size_t)E * sizeof(float2));
+}
 size_t grad_ws_need(const matcha_batch *b)
 {
-    return align256(sizeof(int64_t) * (size_t)b->n_particles) + grad_terms(b) * sizeof(float2);
+    return align256(sizeof(int64_t) * (size_t)b->n_particles) + grad_part_bytes(b) + grad_terms(b) * sizeof(float2);
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
@@ -842,8 +848,10 @@ matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, c
     a.grad_h = reinterpret_cast<float2 *>(grad_h);
     if (grad_h) {
         char *base = static_cast<char *>(ws);
+        const size_t off_bytes = align256(sizeof(int64_t) * (size_t)a.P);
         a.ws_off = reinterpret_cast<int64_t *>(base);
-        a.ws = reinterpret_cast<float2 *>(base + align256(sizeof(int64_t) * (size_t)a.P));
+        a.part = reinterpret_cast<float2 *>(base + off_bytes);
+        a.ws = reinterpret_cast<float2 *>(base + off_bytes + grad_part_bytes(batch));
     }
     a.pinfo = ctx->pinfo;
     a.tab = ctx->tab;

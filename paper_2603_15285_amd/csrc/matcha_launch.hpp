@@ -109,6 +109,8 @@ struct GradArgs {
     float2 *grad_f;           // may be null
     float2 *ws;               // per-particle grad_h terms at ws_off[p] (null if grad_h is null)
     int64_t *ws_off;          // [P] packed offsets of the terms, written by the first kernel
+    float2 *part;             // [n_seg][R_h][(L_h+1)^2] partial sums over segments of particles
+    int n_seg, seg_len;       // set by the launcher (grad_segments)
     float2 *grad_h;           // may be null
     const PairInfo *pinfo;
     const float4 *tab;
@@ -136,6 +138,9 @@ hipError_t launch_march_any(const MarchArgs &a, int P, int nc, bool f64, hipStre
 hipError_t launch_evaluate(const EvalArgs &a, int P, hipStream_t s);
 
 size_t grad_smem_bytes(int Lmax);
+// Segments of particles whose template terms the adjoint sums separately before adding the
+// segments in order (E = R_h (L_h+1)^2 template entries).
+int grad_segments(int64_t E, int P);
 hipError_t launch_grad(const GradArgs &a, hipStream_t s);
 
 }  // namespace matcha

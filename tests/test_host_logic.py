@@ -76,7 +76,9 @@ def test_workspace_size_is_the_largest_call_need():
     matcha_grad_workspace_size = the adjoint's offsets and per-particle template terms."""
     L, R = [32, 10, 3], [32, 5, 2]
     b, keep = host_batch(L, R, 32, 32)
-    grad = align256(8 * 3) + 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
+    E = 32 * 33 * 33  # template entries
+    seg = min(64, 3, -(-2048 // -(-E // 256)))
+    grad = align256(8 * 3) + align256(seg * E * 8) + 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
     assert M.lib().matcha_grad_workspace_size(ct.byref(b)) == grad
     assert M.lib().matcha_workspace_size(None, ct.byref(b), None, None) == 256  # the march's work counter
     soft = M._SoftCfg(3, 12, 4)
@@ -124,7 +126,9 @@ def test_workspace_too_small_is_reported_before_the_context():
                                 None)
     assert rc == M.ERR_WORKSPACE  # misaligned
     # adjoint with grad_h: offsets and terms
-    need = align256(8 * 3) + 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
+    E = 4 * 9 * 9
+    seg = min(64, 3, -(-2048 // -(-E // 256)))
+    need = align256(8 * 3) + align256(seg * E * 8) + 8 * sum(r * (l + 1) ** 2 for l, r in zip(L, R))
     args = (None, ct.byref(b), dev, dev, dev, dev, dev, dev, None, M.FP32)
     assert lib.matcha_grad_template(*args, dev, need - 1, None) == M.ERR_WORKSPACE
     assert lib.matcha_grad_template(*args, dev, need, None) == M.ERR_INVALID_ARG

@@ -311,6 +311,49 @@ matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, c
 matcha_status matcha_soft_search_noalloc(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
                                          const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream);
 
+/* ---- ball-harmonic front end ---------------------------------------------- */
+/* The step before the path (App. A.1): coefficients of real volumes in the ball-harmonic
+ * (Fourier-Bessel) basis of the unit ball, psi_klm(x) = c_lk j_l(lam_lk |x|) Y_lm(x / |x|), with
+ * lam_lk the k-th positive zero of the spherical Bessel function j_l, c_lk = sqrt(2) / |j_{l+1}(lam_lk)|
+ * (orthonormal on the ball), Y_lm orthonormal with the Condon-Shortley phase, and the index set
+ * I_Lambda = {(k, l, m): lam_lk <= Lambda}: |K_l| radial indices at degree l, falling with l, up to
+ * the largest degree L with a zero <= Lambda.  A volume is N^3 samples at the voxel centres
+ * -1 + (2/N)(i + 1/2) per axis (the ball inscribed in the grid), float32 [N][N][N] with x fastest,
+ * then y, then z; its coefficients are the voxel-sum inner products
+ *     u_klm = (2/N)^3 sum over the voxels with |x_v| < 1 of u(x_v) conj(psi_klm(x_v)),
+ * computed exactly (no fast transform; the error against the continuous inner product is the
+ * quadrature's, O(1/N) for a volume with a jump at the sphere).  Output layout:
+ * [n_volumes][Kmax][(L+1)^2] complex float32 (packed lm = l^2 + l + m), zero where k >= |K_l|:
+ * the per-shell layout of f and h with R = Kmax shells, so the path takes it directly with unit
+ * shell weights (then C^l_mn is the paper's sigma_lmn summed over K_l). */
+#define MATCHA_BALL_MAX_L 63
+#define MATCHA_BALL_MAX_LAMBDA 71.0
+#define MATCHA_BALL_MAX_N 256
+#define MATCHA_BALL_MAX_TABLE_BYTES ((size_t)16 << 30)
+
+/* The index set of Lambda (host only, FP64 zeros by bracketing and bisection): *L, *Kmax = |K_0|;
+ * nk_l (optional, >= L + 1 entries) = |K_l|; zeros (optional, [L+1][Kmax], zero-padded) = lam_lk.
+ * Pass NULL for both to learn L and Kmax first.  MATCHA_ERR_INVALID_ARG unless
+ * pi <= Lambda <= MATCHA_BALL_MAX_LAMBDA (below pi, the first zero of j_0, the set is empty);
+ * MATCHA_BALL_MAX_LAMBDA keeps L <= 62, within MATCHA_BALL_MAX_L. */
+matcha_status matcha_ball_index(double Lambda, int32_t *L, int32_t *Kmax, int32_t *nk_l, double *zeros);
+
+/* Builds the transform's tables for an N^3 grid and Lambda (host FP64, rounded to FP32) and keeps
+ * them on the context's device until matcha_destroy: the voxel list, the radial values
+ * (2/N)^3 c_lk j_l(lam_lk r_v) and the angular values conj Y_lm(x_v / r_v), m >= 0; about
+ * 2 N^3 (sum_l |K_l| + (L+1)(L+2)) bytes (Lambda = 38, N = 64: 0.68 GB).  Idempotent per
+ * (N, Lambda).  MATCHA_ERR_INVALID_ARG unless 2 <= N <= MATCHA_BALL_MAX_N and Lambda is accepted by
+ * matcha_ball_index; MATCHA_ERR_UNSUPPORTED above MATCHA_BALL_MAX_TABLE_BYTES. */
+matcha_status matcha_ball_prepare(matcha_ctx *ctx, int32_t N, double Lambda);
+
+/* u: device float32 [n_volumes][N][N][N]; coef: device, [n_volumes][Kmax][(L+1)^2] complex float32,
+ * every entry written (u_{k,l,-m} = (-1)^m conj(u_klm) for real volumes).  One GEMM per degree over
+ * the voxels on the matrix cores (FP32 inputs, FP32 accumulation), rows (volume, k), columns
+ * (m >= 0, real / imaginary part).  n_volumes = 0 does nothing; MATCHA_ERR_NOT_PREPARED if
+ * matcha_ball_prepare(ctx, N, Lambda) has not run. */
+matcha_status matcha_ball_transform(matcha_ctx *ctx, int32_t N, double Lambda, int32_t n_volumes, const float *u,
+                                    float *coef, void *stream);
+
 /* ---- batching: graphs and tuning ------------------------------------------ */
 typedef struct matcha_graph matcha_graph;
 

@@ -91,6 +91,16 @@ def ball_transform(u: np.ndarray, lam: float) -> np.ndarray:
     return out
 
 
+def ball_coefficient(u: np.ndarray, lam: float, k: int, l: int, m: int) -> complex:
+    """One coefficient u_klm of the voxel sum (zero when k >= |K_l|), for sampling large volumes."""
+    N = u.shape[0]
+    L, zeros = ball_index(lam)
+    if l > L or k >= zeros[l].size:
+        return 0j
+    pts, inside = voxel_centres(N)
+    return complex((2.0 / N) ** 3 * np.sum(u[inside].astype(np.float64) * np.conj(psi(l, m, zeros[l][k], pts[inside]))))
+
+
 def ball_synthesize(coef: np.ndarray, lam: float, pts: np.ndarray) -> np.ndarray:
     """u(x) = sum over I_Lam of coef psi at the points pts [..., 3] (real part: coef is assumed
     Hermitian-symmetric, coef_{k,l,-m} = (-1)^m conj(coef_klm))."""

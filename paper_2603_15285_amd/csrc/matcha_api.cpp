@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/matcha.h"
+#include "matcha_ball.hpp"
 #include "matcha_launch.hpp"
 
 using namespace matcha;
@@ -28,6 +29,16 @@ struct GridTables {
     int B = 0, n = 0;
     float2 *dgrid = nullptr;  // weighted d^l(b_i) per node and wedge pair (build_grid_table)
     float *dft = nullptr;     // DFT tables of the grid kernel (build_soft_dft)
+};
+
+// Ball-harmonic tables of one prepared (N, Lambda) (k_ball.hip).
+struct BallTables {
+    int N = 0;
+    double lam = 0.0;
+    BallIndex ix;
+    int64_t V = 0;
+    int32_t *vidx = nullptr;
+    float *R = nullptr, *A = nullptr;
 };
 
 }  // namespace
@@ -45,6 +56,7 @@ struct matcha_ctx {
     double2 *tab64 = nullptr;  // (A, AC) of tab in FP64
     PairInfo *pinfo = nullptr;
     std::vector<GridTables> grids;  // every prepared (B, n); freed by matcha_destroy only
+    std::vector<BallTables> balls;  // every prepared (N, Lambda); freed by matcha_destroy only
     matcha_tuning tune{0, 0, 0, 0, 0};
     std::string tune_path;  // tune cache file, empty: none
     std::map<std::string, matcha_tuning> tune_cache;
@@ -179,6 +191,12 @@ void free_tables(matcha_ctx *ctx)
         if (g.dft) (void)hipFree(g.dft);
     }
     ctx->grids.clear();
+    for (BallTables &b : ctx->balls) {
+        if (b.vidx) (void)hipFree(b.vidx);
+        if (b.R) (void)hipFree(b.R);
+        if (b.A) (void)hipFree(b.A);
+    }
+    ctx->balls.clear();
     ctx->tab = nullptr;
     ctx->tab64 = nullptr;
     ctx->pinfo = nullptr;
@@ -508,6 +526,43 @@ bool tune_cache_store(const matcha_ctx *ctx, const std::string &key, const match
     std::fprintf(fp, "%s %d %d %d %d %d\n", key.c_str(), t.march_nc, t.soft_threads, t.asm_tiles, t.grid_nodes,
                  t.march_persistent);
     return std::fclose(fp) == 0;
+}
+
+const BallTables *find_ball(const matcha_ctx *ctx, int N, double lam)
+{
+    for (const BallTables &b : ctx->balls)
+        if (b.N == N && b.lam == lam) return &b;
+    return nullptr;
+}
+
+// The index set of Lambda within what the transform supports (degrees <= MATCHA_BALL_MAX_L).
+matcha_status ball_index_checked(double lam, BallIndex &ix)
+{
+    if (!(lam > 0.0) || !(lam <= MATCHA_BALL_MAX_LAMBDA)) return MATCHA_ERR_INVALID_ARG;
+    if (!ball_index(lam, ix)) return MATCHA_ERR_INVALID_ARG;
+    if (ix.L > MATCHA_BALL_MAX_L) return MATCHA_ERR_UNSUPPORTED;
+    return MATCHA_OK;
+}
+
+// Device bytes of the tables of (N, ix): vidx, R, A.
+size_t ball_table_bytes(int N, const BallIndex &ix, int64_t V)
+{
+    (void)N;
+    return (size_t)V * (sizeof(int32_t) + sizeof(float) * ((size_t)ix.nk + (size_t)(ix.L + 1) * (ix.L + 2)));
+}
+
+// Voxel count of the ball inscribed in the N^3 grid (centres strictly inside the unit sphere).
+int64_t ball_voxels(int N)
+{
+    int64_t V = 0;
+    for (int i = 0; i < N; ++i)
+        for (int j = 0; j < N; ++j)
+            for (int k = 0; k < N; ++k) {
+                const double z = -1.0 + (2.0 / N) * (i + 0.5), y = -1.0 + (2.0 / N) * (j + 0.5),
+                             x = -1.0 + (2.0 / N) * (k + 0.5);
+                V += std::sqrt(x * x + y * y + z * z) < 1.0;
+            }
+    return V;
 }
 
 }  // namespace
@@ -1049,6 +1104,82 @@ matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const 
     }
     *best_tuning = ctx->tune;
     return st;
+}
+
+// ---- ball-harmonic front end ----------------------------------------------------------------
+matcha_status matcha_ball_index(double Lambda, int32_t *L, int32_t *Kmax, int32_t *nk_l, double *zeros)
+{
+    if (!L || !Kmax) return MATCHA_ERR_INVALID_ARG;
+    BallIndex ix;
+    const matcha_status st = ball_index_checked(Lambda, ix);
+    if (st != MATCHA_OK) return st;
+    *L = ix.L;
+    *Kmax = ix.Kmax;
+    for (int l = 0; l <= ix.L; ++l) {
+        const auto &z = ix.zeros[(size_t)l];
+        if (nk_l) nk_l[l] = (int32_t)z.size();
+        if (zeros)
+            for (int k = 0; k < ix.Kmax; ++k) zeros[(size_t)l * ix.Kmax + k] = k < (int)z.size() ? z[(size_t)k] : 0.0;
+    }
+    return MATCHA_OK;
+}
+
+matcha_status matcha_ball_prepare(matcha_ctx *ctx, int32_t N, double Lambda)
+{
+    if (!ctx || N < 2 || N > MATCHA_BALL_MAX_N) return MATCHA_ERR_INVALID_ARG;
+    BallIndex ix;
+    matcha_status st = ball_index_checked(Lambda, ix);
+    if (st != MATCHA_OK) return st;
+    if (find_ball(ctx, N, Lambda)) return MATCHA_OK;
+    if (ball_table_bytes(N, ix, ball_voxels(N)) > MATCHA_BALL_MAX_TABLE_BYTES) return MATCHA_ERR_UNSUPPORTED;
+    BallTables t;
+    t.N = N;
+    t.lam = Lambda;
+    std::vector<int32_t> vidx;
+    std::vector<float> R, A;
+    ball_build_tables(N, ix, vidx, R, A);
+    t.V = (int64_t)vidx.size();
+    t.ix = std::move(ix);
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    st = upload(vidx, &t.vidx);
+    if (st == MATCHA_OK) st = upload(R, &t.R);
+    if (st == MATCHA_OK) st = upload(A, &t.A);
+    if (st != MATCHA_OK) {
+        if (t.vidx) (void)hipFree(t.vidx);
+        if (t.R) (void)hipFree(t.R);
+        return st;
+    }
+    ctx->balls.push_back(std::move(t));
+    return MATCHA_OK;
+}
+
+matcha_status matcha_ball_transform(matcha_ctx *ctx, int32_t N, double Lambda, int32_t n_volumes, const float *u,
+                                    float *coef, void *stream)
+{
+    if (!ctx || N < 2 || N > MATCHA_BALL_MAX_N || n_volumes < 0) return MATCHA_ERR_INVALID_ARG;
+    if (n_volumes == 0) return MATCHA_OK;
+    if (!u || !coef) return MATCHA_ERR_INVALID_ARG;
+    const BallTables *t = find_ball(ctx, N, Lambda);
+    if (!t) return MATCHA_ERR_NOT_PREPARED;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    BallArgs a{};
+    a.u = u;
+    a.out = coef;
+    a.vidx = t->vidx;
+    a.R = t->R;
+    a.A = t->A;
+    a.V = t->V;
+    a.N = N;
+    a.P = n_volumes;
+    a.L = t->ix.L;
+    a.Kmax = t->ix.Kmax;
+    int off = 0;
+    for (int l = 0; l <= a.L; ++l) {
+        a.nk_l[l] = (int)t->ix.zeros[(size_t)l].size();
+        a.rk_off[l] = off;
+        off += a.nk_l[l];
+    }
+    return launched(launch_ball(a, static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

@@ -26,8 +26,10 @@ EXPORTED = ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_status_
             "matcha_get_tuning", "matcha_c_elems", "matcha_f_elems", "matcha_workspace_size", "matcha_lpt_order",
             "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton", "matcha_evaluate",
             "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch", "matcha_graph_destroy",
-            "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc", "matcha_grad_workspace_size"]
+            "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc", "matcha_grad_workspace_size",
+            "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_transform"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
+BALL_MAX_L, BALL_MAX_LAMBDA, BALL_MAX_N = 63, 71.0, 256
 
 
 class MatchaError(RuntimeError):
@@ -106,10 +108,14 @@ def lib():
         L.matcha_graph_destroy.argtypes = [vp]
         L.matcha_autotune.argtypes = [vp, bp, ct.POINTER(_AlignBufs), ct.POINTER(_SoftCfg), ct.POINTER(_MarchCfg), i32,
                                       vp, sz, ct.POINTER(_Tuning)]
+        L.matcha_ball_index.argtypes = [ct.c_double, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), vp, vp]
+        L.matcha_ball_prepare.argtypes = [vp, i32, ct.c_double]
+        L.matcha_ball_transform.argtypes = [vp, i32, ct.c_double, i32, vp, vp, vp]
         for name in ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_set_tuning", "matcha_get_tuning",
                      "matcha_lpt_order", "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton",
                      "matcha_evaluate", "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch",
-                     "matcha_graph_destroy", "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc"]:
+                     "matcha_graph_destroy", "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc",
+                     "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_transform"]:
             getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -513,6 +519,47 @@ def c_unpack(L: int, C_wedge: np.ndarray) -> np.ndarray:
     out = np.zeros((L + 1) * (2 * L + 1) * (2 * L + 3) // 3, dtype=np.complex64)
     _check(lib().matcha_c_unpack(int(L), cw.ctypes.data, out.ctypes.data), "matcha_c_unpack")
     return out
+
+
+# ------------------------------------------------------------ ball-harmonic front end
+def ball_index(lam: float):
+    """matcha_ball_index: (L, zeros) with zeros[l] the kept lam_lk of degree l (float64 arrays)."""
+    L, K = ct.c_int32(), ct.c_int32()
+    _check(lib().matcha_ball_index(float(lam), ct.byref(L), ct.byref(K), None, None), "matcha_ball_index")
+    nk = np.zeros(L.value + 1, dtype=np.int32)
+    z = np.zeros((L.value + 1, K.value), dtype=np.float64)
+    _check(lib().matcha_ball_index(float(lam), ct.byref(L), ct.byref(K), nk.ctypes.data, z.ctypes.data),
+           "matcha_ball_index")
+    return L.value, [z[l, :nk[l]].copy() for l in range(L.value + 1)]
+
+
+def ball_prepare(ctx: Context, N: int, lam: float):
+    """matcha_ball_prepare: the transform's tables for an N^3 grid and Lambda (synchronous)."""
+    _check(lib().matcha_ball_prepare(ctx.handle, int(N), float(lam)), "matcha_ball_prepare")
+
+
+def ball_transform(ctx: Context, u: torch.Tensor, lam: float, out: torch.Tensor | None = None, stream=None):
+    """matcha_ball_transform of real volumes u (float32 CUDA [P, N, N, N] or [N, N, N], index
+    (z, y, x)); returns complex64 [P, Kmax, (L+1)^2] (or [Kmax, (L+1)^2]).  The tables for
+    (N, lam) are built on first use."""
+    _need(u, torch.float32, "u")
+    single = u.dim() == 3
+    uu = u.unsqueeze(0) if single else u
+    if uu.dim() != 4 or not (uu.shape[1] == uu.shape[2] == uu.shape[3]):
+        raise MatchaError("u must be [P, N, N, N] or [N, N, N]")
+    P, N = int(uu.shape[0]), int(uu.shape[1])
+    L, K = ct.c_int32(), ct.c_int32()
+    _check(lib().matcha_ball_index(float(lam), ct.byref(L), ct.byref(K), None, None), "matcha_ball_index")
+    ball_prepare(ctx, N, lam)
+    shape = (P, K.value, (L.value + 1) ** 2)
+    if out is None:
+        out = torch.empty(shape, dtype=torch.complex64, device=u.device)
+    elif tuple(out.shape) != shape:
+        raise MatchaError(f"out must have shape {shape}")
+    _need(out, torch.complex64, "out")
+    _check(lib().matcha_ball_transform(ctx.handle, N, float(lam), P, _ptr(uu), _ptr(out),
+                                       ct.c_void_p(_stream(stream))), "matcha_ball_transform")
+    return out[0] if single else out
 
 
 # ------------------------------------------------------------ layout helpers

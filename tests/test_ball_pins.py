@@ -126,3 +126,12 @@ def test_voxel_sum_converges_to_the_coefficients():
     # sphere, so the midpoint sums converge quickly)
     assert errs[2] < errs[1] < errs[0] and errs[2] < 1e-6, errs
     assert errs[1] / errs[2] > 8, errs
+
+
+def test_single_coefficient_agrees_with_the_full_transform():
+    N, lam = 10, 11.0
+    u = np.random.default_rng(4).standard_normal((N, N, N))
+    a = B.ball_transform(u, lam)
+    L, zeros = B.ball_index(lam)
+    for k, l, m in [(0, 0, 0), (1, 3, -2), (0, L, L), (len(zeros[2]) - 1, 2, 1), (len(zeros[L]), L, 0)]:
+        assert abs(B.ball_coefficient(u, lam, k, l, m) - a[k, l * l + l + m]) <= 1e-15 * np.abs(a).max()

@@ -1,5 +1,5 @@
-"""Host-side logic that needs no GPU: longest-first ordering, workspace sizing and the bench's
-use of the recorded march traffic."""
+"""Host-side logic that needs no GPU: longest-first ordering, workspace sizing, the ball-harmonic
+index set and the bench's use of the recorded march traffic."""
 import ctypes as ct
 
 import numpy as np
@@ -158,3 +158,18 @@ def test_march_traffic_reported_only_for_its_workload_and_sources(tmp_path, monk
     assert bench.measured_march_traffic("L32_R32_B12_K16") is None
     monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "absent.txt"))
     assert bench.measured_march_traffic("L32_R32_B12_K16") is None
+
+
+def test_ball_index_matches_the_oracle_and_rejects_bad_cutoffs():
+    """matcha_ball_index (host FP64 zeros) against the oracle's scipy-based zeros (App. A.1)."""
+    from oracle import ball as OB
+    for lam in (3.2, 9.0, 14.0, 38.0, 71.0):
+        L, zeros = M.ball_index(lam)
+        Lo, zo = OB.ball_index(lam)
+        assert L == Lo and [z.size for z in zeros] == [z.size for z in zo]
+        for a, b in zip(zeros, zo):
+            assert np.abs(a - b).max() <= 4e-15 * lam
+    L, K = ct.c_int32(), ct.c_int32()
+    for lam in (0.0, -1.0, 3.0, 71.5, float("nan")):
+        assert M.lib().matcha_ball_index(lam, ct.byref(L), ct.byref(K), None, None) == M.ERR_INVALID_ARG
+    assert M.lib().matcha_ball_index(9.0, None, ct.byref(K), None, None) == M.ERR_INVALID_ARG

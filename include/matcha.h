@@ -339,20 +339,33 @@ matcha_status matcha_soft_search_noalloc(matcha_ctx *ctx, const matcha_batch *ba
 matcha_status matcha_ball_index(double Lambda, int32_t *L, int32_t *Kmax, int32_t *nk_l, double *zeros);
 
 /* Builds the transform's tables for an N^3 grid and Lambda (host FP64, rounded to FP32) and keeps
- * them on the context's device until matcha_destroy: the voxel list, the radial values
- * (2/N)^3 c_lk j_l(lam_lk r_v) and the angular values conj Y_lm(x_v / r_v), m >= 0; about
- * 2 N^3 (sum_l |K_l| + (L+1)(L+2)) bytes (Lambda = 38, N = 64: 0.68 GB).  Idempotent per
- * (N, Lambda).  MATCHA_ERR_INVALID_ARG unless 2 <= N <= MATCHA_BALL_MAX_N and Lambda is accepted by
- * matcha_ball_index; MATCHA_ERR_UNSUPPORTED above MATCHA_BALL_MAX_TABLE_BYTES. */
+ * them on the context's device until matcha_destroy.  The grid's mirrors x -> -x, y -> -y, z -> -z
+ * permute the voxels, and every real column function (Re and Im of conj psi_klm) is even or odd
+ * under each, so the sum is taken over one octant: the table holds, per column and octant voxel,
+ * (2/N)^3 conj psi_klm / (the number of mirrors that fix the voxel), about
+ * 4 N^3 / 16 sum_l |K_l| (2l + 1) bytes (Lambda = 38, N = 64: 3476 columns, 0.24 GB).  Idempotent
+ * per (N, Lambda).  MATCHA_ERR_INVALID_ARG unless 2 <= N <= MATCHA_BALL_MAX_N and Lambda is accepted
+ * by matcha_ball_index; MATCHA_ERR_UNSUPPORTED above MATCHA_BALL_MAX_TABLE_BYTES. */
 matcha_status matcha_ball_prepare(matcha_ctx *ctx, int32_t N, double Lambda);
 
-/* u: device float32 [n_volumes][N][N][N]; coef: device, [n_volumes][Kmax][(L+1)^2] complex float32,
- * every entry written (u_{k,l,-m} = (-1)^m conj(u_klm) for real volumes).  One GEMM per degree over
- * the voxels on the matrix cores (FP32 inputs, FP32 accumulation), rows (volume, k), columns
- * (m >= 0, real / imaginary part).  n_volumes = 0 does nothing; MATCHA_ERR_NOT_PREPARED if
- * matcha_ball_prepare(ctx, N, Lambda) has not run. */
+/* Workspace bytes of matcha_ball_transform for n_volumes volumes on a prepared (N, Lambda): the
+ * sign-symmetrised volumes (8 x n_volumes x the octant voxel count, float32) and the K-split
+ * partial sums (up to 16 x n_volumes x the column count, float32); 0 if (N, Lambda) is not prepared
+ * or n_volumes <= 0. */
+size_t matcha_ball_workspace_size(const matcha_ctx *ctx, int32_t N, double Lambda, int32_t n_volumes);
+
+/* u: device float32 [n_volumes][N][N][N]; coef: device, [n_volumes][Kmax][(L+1)^2] complex float32
+ * (8-byte aligned), every entry written (u_{k,l,-m} = (-1)^m conj(u_klm) for real volumes); ws:
+ * device, 16-byte aligned, at least matcha_ball_workspace_size bytes (MATCHA_ERR_WORKSPACE
+ * otherwise).  Three kernels on the stream: the 8 sign-symmetrised copies of each volume on the
+ * octant, one product per sign class on the matrix cores (rows = volumes, columns = the class's
+ * (l, k, m, Re / Im), FP32 inputs and accumulation, in up to 16 partial sums over voxel ranges),
+ * and the sum of the partials scattered into the output layout.  The split count depends on
+ * n_volumes and the device's compute-unit count only, so results are reproducible bit for bit on
+ * one device.  n_volumes = 0 does nothing; MATCHA_ERR_NOT_PREPARED if matcha_ball_prepare(ctx, N,
+ * Lambda) has not run. */
 matcha_status matcha_ball_transform(matcha_ctx *ctx, int32_t N, double Lambda, int32_t n_volumes, const float *u,
-                                    float *coef, void *stream);
+                                    float *coef, void *ws, size_t ws_bytes, void *stream);
 
 /* ---- batching: graphs and tuning ------------------------------------------ */
 typedef struct matcha_graph matcha_graph;

@@ -6,15 +6,25 @@
 // (the index set I_Lambda; |K_l| radial indices at degree l).  Voxel centres sit at
 // -1 + (2/N)(i + 1/2) per axis; a volume is [N][N][N] with x fastest, then y, then z.
 //
-// The sum is computed exactly (no fast transform): for each degree l it is a product over the
-// voxels inside the ball,
-//   out_l[(p, k)][(m, re/im)] = sum_v (u_p(v) R_lk(v)) A_lm(v),
-//   R_lk(v) = (2/N)^3 c_lk j_l(lam_lk r_v),  A_lm(v) = conj Y_lm(v) = Ybar_l^m(cos t_v) e^{-i m p_v},
-// with rows (volume, radial index) and columns (m >= 0, real and imaginary part), on the matrix
-// cores.  Real volumes give u_{k,l,-m} = (-1)^m conj(u_klm), written from the m >= 0 columns.  The
-// tables R and A are built once per (N, Lambda) on the host in FP64 (spherical Bessel values by
-// recurrence, zeros by bracketing and bisection, normalised associated Legendre functions by the
-// standard three-term recurrence) and kept on the device in FP32.
+// The sum is computed exactly (no fast transform), folded onto one octant.  The grid is mapped onto
+// itself by the three mirrors x -> -x, y -> -y, z -> -z, and each real column function of the
+// transform has a definite sign under each of them:
+//   Re conj psi_klm = c_lk j_l Ybar_l^m(cos t) cos(m p),  Im conj psi_klm = -c_lk j_l Ybar_l^m(cos t) sin(m p),
+//   z -> -z: (-1)^(l+m) (Ybar_l^m(-t) = (-1)^(l+m) Ybar_l^m(t));  y -> -y: +1 (Re), -1 (Im);
+//   x -> -x: (-1)^m (Re), -(-1)^m (Im)   (p -> pi - p).
+// So with sigma = (s_x, s_y, s_z) the column's signs and, for an octant voxel v0 (x, y, z >= 0),
+//   usym_sigma(v0) = sum over the 8 mirror images g v0 of sign_sigma(g) u(g v0),
+// the coefficient is  sum over octant voxels of usym_sigma(v0) psi*(v0) / |Stab v0|  (a voxel on a
+// mirror plane, odd N only, is its own image: the orbit sum counts it |Stab| times).  Per class sigma
+// that is one plain product over the octant voxels:
+//   out_sigma[p][c] = sum_v0 usym_sigma[p][v0] T[c][v0],  T[c][v0] = (2/N)^3 / |Stab v0| psi*_c(v0),
+// rows = volumes, columns = the (l, k, m, Re/Im) of class sigma (8 classes, 8 times fewer terms than the
+// full-grid sum).  Three kernels: the sign-symmetrised volumes (k_ball_sym), the products on the
+// matrix cores in K-split partial sums (k_ball_gemm), and the sum of the partials scattered into the
+// [Kmax][(L+1)^2] layout with u_{k,l,-m} = (-1)^m conj(u_klm) and zeros where k >= |K_l|
+// (k_ball_scatter).  The table T is built once per (N, Lambda) on the host in FP64 (spherical Bessel
+// values by recurrence, zeros by bracketing and bisection, normalised associated Legendre functions
+// by the standard three-term recurrence) and kept on the device in FP32.
 #include <algorithm>
 #include <cmath>
 #include <thread>
@@ -153,183 +163,288 @@ bool ball_index(double lam, BallIndex &ix)
     return true;
 }
 
-void ball_build_tables(int N, const BallIndex &ix, std::vector<int32_t> &vidx, std::vector<float> &R,
-                       std::vector<float> &A)
+void ball_build_tables(int N, const BallIndex &ix, BallHostTables &t)
 {
-    vidx.clear();
-    std::vector<double> xs, ys, zs;
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j)
-            for (int k = 0; k < N; ++k) {
+    // octant voxels (z, y, x >= 0: indices >= N / 2 rounded down), raster order, and |Stab|
+    const int i0 = N / 2;
+    std::vector<double> xs, ys, zs, wt;
+    t.oct.clear();
+    for (int i = i0; i < N; ++i)
+        for (int j = i0; j < N; ++j)
+            for (int k = i0; k < N; ++k) {
                 const double z = -1.0 + (2.0 / N) * (i + 0.5), y = -1.0 + (2.0 / N) * (j + 0.5),
                              x = -1.0 + (2.0 / N) * (k + 0.5);
-                if (std::sqrt(x * x + y * y + z * z) < 1.0) {
-                    vidx.push_back((int32_t)((i * N + j) * N + k));
-                    xs.push_back(x);
-                    ys.push_back(y);
-                    zs.push_back(z);
-                }
+                if (std::sqrt(x * x + y * y + z * z) >= 1.0) continue;
+                t.oct.push_back((int32_t)((i * N + j) * N + k));
+                xs.push_back(x);
+                ys.push_back(y);
+                zs.push_back(z);
+                const int on_planes = (2 * i + 1 == N) + (2 * j + 1 == N) + (2 * k + 1 == N);
+                wt.push_back(std::pow(2.0 / N, 3) / (double)(1 << on_planes));
             }
-    const int64_t V = (int64_t)vidx.size();
+    const int64_t Vo = (int64_t)t.oct.size();
+    t.Vo = Vo;
+    t.Vo_pad = (Vo + kBallChunk - 1) / kBallChunk * kBallChunk;
     const int L = ix.L;
-    const double dv = std::pow(2.0 / N, 3);
-    // radial table, rows (l, k) in degree-major order: dv c_lk j_l(lam_lk r_v)
-    std::vector<double> clk;
-    std::vector<std::pair<int, double>> lk;
+    // columns by class, in (l, k, m, part) order within a class
+    struct Col {
+        int l, k, m, part;
+    };
+    std::vector<Col> cols[8];
     for (int l = 0; l <= L; ++l)
-        for (double lam : ix.zeros[(size_t)l]) {
-            lk.push_back({l, lam});
-            clk.push_back(std::sqrt(2.0) / std::fabs(sph_jn(l + 1, lam)));
+        for (int k = 0; k < (int)ix.zeros[(size_t)l].size(); ++k)
+            for (int m = 0; m <= l; ++m)
+                for (int part = 0; part < 2; ++part) {
+                    if (part == 1 && m == 0) continue;  // Im conj psi_kl0 = 0
+                    const int sz = (l + m) & 1, sy = part, sx = (m & 1) ^ part;
+                    cols[sx | (sy << 1) | (sz << 2)].push_back({l, k, m, part});
+                }
+    std::vector<Col> all;
+    for (int c = 0; c < 8; ++c) {
+        t.col_off[c] = (int)all.size();
+        all.insert(all.end(), cols[c].begin(), cols[c].end());
+    }
+    t.col_off[8] = (int)all.size();
+    const int64_t nc = (int64_t)all.size();
+    // scatter map: per output entry (k, lm) the columns of Re and Im (-1: none) and the signs
+    const int nlm = (L + 1) * (L + 1);
+    t.map.assign((size_t)ix.Kmax * nlm, BallMapEntry{-1, -1, 1.f, 1.f});
+    for (int64_t c = 0; c < nc; ++c) {
+        const Col &q = all[(size_t)c];
+        for (int sgn : {1, -1}) {
+            if (sgn < 0 && q.m == 0) continue;
+            const int m = sgn * q.m;
+            BallMapEntry &e = t.map[(size_t)q.k * nlm + q.l * q.l + q.l + m];
+            const float par = (q.m & 1) ? -1.f : 1.f;  // u_{k,l,-m} = (-1)^m conj(u_klm)
+            if (q.part == 0) {
+                e.col_re = (int32_t)c;
+                e.s_re = sgn > 0 ? 1.f : par;
+            } else {
+                e.col_im = (int32_t)c;
+                e.s_im = sgn > 0 ? 1.f : -par;
+            }
         }
-    R.assign((size_t)ix.nk * (size_t)V, 0.f);
-    parallel_for((int64_t)lk.size(), [&](int64_t q) {
-        const int l = lk[(size_t)q].first;
-        const double lam = lk[(size_t)q].second, c = dv * clk[(size_t)q];
-        std::vector<double> j((size_t)l + 2);
-        for (int64_t v = 0; v < V; ++v) {
-            const double r = std::sqrt(xs[(size_t)v] * xs[(size_t)v] + ys[(size_t)v] * ys[(size_t)v] +
-                                       zs[(size_t)v] * zs[(size_t)v]);
-            sph_jn_all(l, lam * r, j.data());
-            R[(size_t)q * (size_t)V + (size_t)v] = (float)(c * j[(size_t)l]);
-        }
-    });
-    // angular table, rows (l, m >= 0, re / im): conj Y_lm = Ybar_l^m(cos t) (cos m p - i sin m p)
-    const int ncol = (L + 1) * (L + 2);  // 2 per (l, m >= 0)
-    A.assign((size_t)ncol * (size_t)V, 0.f);
-    parallel_for(V, [&](int64_t v) {
+    }
+    // normalisation c_lk and the table T [nc][Vo_pad], zero in the padding
+    std::vector<double> clk;
+    std::vector<int> clk_off((size_t)L + 2, 0);
+    for (int l = 0; l <= L; ++l) {
+        clk_off[(size_t)l + 1] = clk_off[(size_t)l] + (int)ix.zeros[(size_t)l].size();
+        for (double lam : ix.zeros[(size_t)l]) clk.push_back(std::sqrt(2.0) / std::fabs(sph_jn(l + 1, lam)));
+    }
+    t.T.assign((size_t)nc * (size_t)t.Vo_pad, 0.f);
+    parallel_for(Vo, [&](int64_t v) {
         const double x = xs[(size_t)v], y = ys[(size_t)v], z = zs[(size_t)v];
         const double r = std::sqrt(x * x + y * y + z * z);
-        const double t = r > 0.0 ? std::max(-1.0, std::min(1.0, z / r)) : 1.0;
-        const double s = std::sqrt(std::max(0.0, 1.0 - t * t));
+        const double ct = r > 0.0 ? std::max(-1.0, std::min(1.0, z / r)) : 1.0;
+        const double st = std::sqrt(std::max(0.0, 1.0 - ct * ct));
         const double ph = std::atan2(y, x);
-        std::vector<double> P((size_t)(L + 1) * (L + 2) / 2);
-        legendre_all(L, t, s, P.data());
+        std::vector<double> P((size_t)(L + 1) * (L + 2) / 2), jr((size_t)clk.size()), j((size_t)L + 2);
+        legendre_all(L, ct, st, P.data());
         for (int l = 0; l <= L; ++l)
-            for (int m = 0; m <= l; ++m) {
-                const int col = 2 * (l * (l + 1) / 2 + m);
-                const double p = P[(size_t)(l * (l + 1) / 2 + m)];
-                A[(size_t)col * (size_t)V + (size_t)v] = (float)(p * std::cos(m * ph));
-                A[(size_t)(col + 1) * (size_t)V + (size_t)v] = (float)(-p * std::sin(m * ph));
+            for (int k = 0; k < (int)ix.zeros[(size_t)l].size(); ++k) {
+                sph_jn_all(l, ix.zeros[(size_t)l][(size_t)k] * r, j.data());
+                jr[(size_t)(clk_off[(size_t)l] + k)] = clk[(size_t)(clk_off[(size_t)l] + k)] * j[(size_t)l];
             }
+        for (int64_t c = 0; c < nc; ++c) {
+            const Col &q = all[(size_t)c];
+            const double ang = q.part == 0 ? std::cos(q.m * ph) : -std::sin(q.m * ph);
+            const double val = wt[(size_t)v] * jr[(size_t)(clk_off[(size_t)q.l] + q.k)] *
+                               P[(size_t)(q.l * (q.l + 1) / 2 + q.m)] * ang;
+            t.T[(size_t)c * (size_t)t.Vo_pad + (size_t)v] = (float)val;
+        }
     });
 }
 
 // ---------------------------------------------------------------- device
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kBallThreads = 256;  // 4 waves; the workgroup's tile is 64 rows x all columns of its degree
-constexpr int kBallRows = 64;
-constexpr int kBallChunk = 32;     // voxels per staged chunk (8 matrix-core K steps of 4)
-constexpr int kBallMaxCT = 8;      // 16-column tiles per degree: 2 (l + 1) <= 128, l <= 63
-
-// Entries of radial indices k >= |K_l| are zero.
-__global__ void __launch_bounds__(256) k_ball_zero(BallArgs a)
+// usym[sigma][p][v] for v < Vo_pad (zero in the padding), sigma = s_x | s_y << 1 | s_z << 2 (bit set:
+// odd under that mirror).  One thread per (p, v): the 8 mirror images, then three sum/difference steps.
+__global__ void __launch_bounds__(256) k_ball_sym(BallSymArgs a)
 {
-    const int64_t nlm = (int64_t)(a.L + 1) * (a.L + 1);
-    const int64_t n = (int64_t)a.P * a.Kmax * nlm;
+    const int64_t n = (int64_t)a.P * a.Vo_pad;
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
-        const int64_t lm = e % nlm;
-        const int k = (int)((e / nlm) % a.Kmax);
-        const int l = (int)sqrtf((float)lm + 0.5f);
-        if (k >= a.nk_l[l]) reinterpret_cast<float2 *>(a.out)[e] = make_float2(0.f, 0.f);
+        const int p = (int)(e / a.Vo_pad);
+        const int64_t v = e - (int64_t)p * a.Vo_pad;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        if (v < a.Vo) {
+            const int N = a.N, f = a.oct[v];
+            const int i = f / (N * N), j = (f / N) % N, k = f % N;
+            const float *up = a.u + (int64_t)p * N * N * N;
+            // s[g], g = gx | gy << 1 | gz << 2: the image with the flagged coordinates negated
+#pragma unroll
+            for (int g = 0; g < 8; ++g) {
+                const int ii = (g & 4) ? N - 1 - i : i, jj = (g & 2) ? N - 1 - j : j, kk = (g & 1) ? N - 1 - k : k;
+                s[g] = up[((int64_t)ii * N + jj) * N + kk];
+            }
+            // butterflies: along x (bit 0), y (bit 1), z (bit 2): even part in the low slot, odd in the high
+#pragma unroll
+            for (int b = 1; b < 8; b <<= 1)
+#pragma unroll
+                for (int g = 0; g < 8; ++g)
+                    if (!(g & b)) {
+                        const float lo = s[g], hi = s[g | b];
+                        s[g] = lo + hi;
+                        s[g | b] = lo - hi;
+                    }
+        }
+#pragma unroll
+        for (int sg = 0; sg < 8; ++sg) a.usym[((int64_t)sg * a.P + p) * a.Vo_pad + v] = s[sg];
     }
 }
 
-// One workgroup per (degree l, tile of 64 rows (volume, radial index)), highest degrees first; wave w
-// owns rows 16 w .. 16 w + 15 and every 16-column tile of the degree.  Voxels are staged in chunks
-// of 32: the A tile (u_p(v) R_lk(v), rows x voxels) and the B tile (A_lm(v), voxels x columns) in
-// LDS, zero outside the degree's rows, columns and the voxel count.
-__global__ void __launch_bounds__(kBallThreads) k_ball_gemm(BallArgs a)
+constexpr int kBallThreads = 256;   // 4 waves as 2 x 2, each 32 rows x 64 columns
+constexpr int kBallTileM = 64;      // volumes per workgroup
+constexpr int kBallTileN = 128;     // columns per workgroup
+constexpr int kBallLds = kBallChunk + 4;  // floats per staged row (K contiguous, padded)
+
+// One workgroup: class sigma and a 128-column tile of it (blockIdx.x), 64 volumes (blockIdx.y), one
+// K split (blockIdx.z), over the octant voxels [z kper, min((z + 1) kper, Vo_pad)).  Both operands are
+// K-contiguous rows staged through LDS in chunks of 32 voxels, double-buffered (the next chunk's global
+// loads are in flight during the current chunk's products).  In each 16-voxel group lane (kq, i) takes
+// voxels 4 kq .. 4 kq + 3 of rows / columns i as one float4 and feeds them to four 16x16x4 steps: the
+// voxel order within the group is permuted identically on both operands.  Partial sums go to
+// part[z][p][col].
+__global__ void __launch_bounds__(kBallThreads) k_ball_gemm(BallGemmArgs a)
 {
-    __shared__ float As[kBallRows][kBallChunk + 1];
-    __shared__ float Bs[kBallChunk][16 * kBallMaxCT + 4];
-    int d = 0;
-    while ((int)blockIdx.x >= a.blk_lo[d + 1]) ++d;
-    const int l = a.L - d, rt = blockIdx.x - a.blk_lo[d];
-    const int K = a.nk_l[l], M = a.P * K, NC = 2 * (l + 1), CT = (NC + 15) / 16;
-    const int rbase = a.rk_off[l];  // first row of degree l in the radial table
-    const int cbase = l * (l + 1);  // first column of degree l in the angular table
-    const int wave = threadIdx.x / kWave, lane = threadIdx.x % kWave;
-    const int col = lane % 16, kq = lane / 16;
-    const int64_t V = a.V, N3 = (int64_t)a.N * a.N * a.N;
-    // the staging assignment of this thread: rows / columns t / 32 + 8 i, voxel t % 32
-    const int tv = threadIdx.x % kBallChunk, tr = threadIdx.x / kBallChunk;
-    int prow[kBallRows / 8], krow[kBallRows / 8];
-    bool rok[kBallRows / 8];
+    __shared__ __align__(16) float As[2][kBallTileM][kBallLds];
+    __shared__ __align__(16) float Bs[2][kBallTileN][kBallLds];
+    int sg = 0;
+    while ((int)blockIdx.x >= a.tile_lo[sg + 1]) ++sg;
+    const int c0 = (blockIdx.x - a.tile_lo[sg]) * kBallTileN;     // first column of the tile in its class
+    const int ncls = a.col_off[sg + 1] - a.col_off[sg];
+    const int p0 = blockIdx.y * kBallTileM;
+    const int64_t v_lo = (int64_t)blockIdx.z * a.kper;
+    const int64_t v_hi = min(v_lo + a.kper, a.Vo_pad);
+    const int nch = (int)((v_hi - v_lo) / kBallChunk);
+    const float *Ag = a.usym + ((int64_t)sg * a.P) * a.Vo_pad;
+    const float *Bg = a.T + (int64_t)a.col_off[sg] * a.Vo_pad;
+    // staging: A 64 rows x 8 float4 (2 per thread), B 128 rows x 8 float4 (4 per thread).  Rows past
+    // the last volume and columns past the class's last are loaded from the last one instead: an
+    // output entry depends on its own row and column only, and those entries are not written.
+    const int t = threadIdx.x, sq = t % 8, sr = t / 8;  // float4 sq of rows sr, sr + 32, ...
+    f32x4 ra[2], rb[4];
+    auto load = [&](int ch) {
+        const int64_t v = v_lo + (int64_t)ch * kBallChunk + 4 * sq;
 #pragma unroll
-    for (int i = 0; i < kBallRows / 8; ++i) {
-        const int rg = rt * kBallRows + tr + 8 * i;
-        rok[i] = rg < M;
-        const int rc = min(rg, M - 1);
-        prow[i] = rc / K;
-        krow[i] = rc - prow[i] * K;
+        for (int i = 0; i < 2; ++i)
+            ra[i] = *reinterpret_cast<const f32x4 *>(Ag + (int64_t)min(p0 + sr + 32 * i, a.P - 1) * a.Vo_pad + v);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+            rb[i] = *reinterpret_cast<const f32x4 *>(Bg + (int64_t)min(c0 + sr + 32 * i, ncls - 1) * a.Vo_pad + v);
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) *reinterpret_cast<f32x4 *>(&As[buf][sr + 32 * i][4 * sq]) = ra[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) *reinterpret_cast<f32x4 *>(&Bs[buf][sr + 32 * i][4 * sq]) = rb[i];
+    };
+    const int wave = t / kWave, lane = t % kWave, li = lane % 16, kq = lane / 16;
+    const int wr = 32 * (wave / 2), wc = 64 * (wave % 2);
+    f32x4 acc[2][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+    if (nch > 0) {
+        load(0);
+        store(0);
     }
-    f32x4 acc[kBallMaxCT];
+    __syncthreads();
+    for (int ch = 0; ch < nch; ++ch) {
+        const int buf = ch & 1;
+        if (ch + 1 < nch) load(ch + 1);
 #pragma unroll
-    for (int c = 0; c < kBallMaxCT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
-    for (int64_t v0 = 0; v0 < V; v0 += kBallChunk) {
-        const int64_t v = v0 + tv;
-        const bool vok = v < V;
-        const int64_t vc = vok ? v : V - 1;
-        const int gi = a.vidx[vc];
+        for (int g = 0; g < kBallChunk / 16; ++g) {
+            f32x4 av[2], bv[4];
 #pragma unroll
-        for (int i = 0; i < kBallRows / 8; ++i) {
-            const float u = a.u[(int64_t)prow[i] * N3 + gi];
-            const float r = a.R[(int64_t)(rbase + krow[i]) * V + vc];
-            As[tr + 8 * i][tv] = (rok[i] && vok) ? u * r : 0.f;
+            for (int i = 0; i < 2; ++i) av[i] = *reinterpret_cast<const f32x4 *>(&As[buf][wr + 16 * i + li][16 * g + 4 * kq]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const f32x4 *>(&Bs[buf][wc + 16 * j + li][16 * g + 4 * kq]);
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
         }
-        for (int c = tr; c < 16 * CT; c += kBallThreads / kBallChunk) {
-            const float b = a.A[(int64_t)(cbase + min(c, NC - 1)) * V + vc];
-            Bs[tv][c] = (c < NC && vok) ? b : 0.f;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int ks = 0; ks < kBallChunk / 4; ++ks) {
-            const float av = As[16 * wave + col][4 * ks + kq];
-#pragma unroll
-            for (int c = 0; c < kBallMaxCT; ++c)
-                if (c < CT) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, Bs[4 * ks + kq][16 * c + col], acc[c], 0, 0, 0);
-        }
+        if (ch + 1 < nch) store(buf ^ 1);
         __syncthreads();
     }
-    // lane (kq, col) holds rows 4 kq .. 4 kq + 3 of column col of each tile: write u_klm and, for
-    // m > 0, u_{k,l,-m} = (-1)^m conj(u_klm)
-    const int64_t nlm = (int64_t)(a.L + 1) * (a.L + 1);
+    // lane (kq, li) holds rows 4 kq .. 4 kq + 3 of column li of each 16 x 16 tile
+    float *out = a.part + (int64_t)blockIdx.z * a.P * a.ncol + a.col_off[sg];
 #pragma unroll
-    for (int c = 0; c < kBallMaxCT; ++c) {
-        if (c >= CT) continue;
-        const int cc = 16 * c + col;
-        if (cc >= NC) continue;
-        const int m = cc / 2, part = cc % 2;
-        const float sgn = (m & 1) ? -1.f : 1.f;
+    for (int j = 0; j < 4; ++j) {
+        const int col = c0 + wc + 16 * j + li;
+        if (col >= ncls) continue;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int rg = rt * kBallRows + 16 * wave + 4 * kq + q;
-            if (rg >= M) continue;
-            const int p = rg / K, k = rg - (rg / K) * K;
-            float *o = a.out + 2 * (((int64_t)p * a.Kmax + k) * nlm + (int64_t)l * l + l);
-            o[2 * m + part] = acc[c][q];
-            if (m > 0) o[-2 * m + part] = part ? -sgn * acc[c][q] : sgn * acc[c][q];
-        }
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int row = p0 + wr + 16 * i + 4 * kq + q;
+                if (row < a.P) out[(int64_t)row * a.ncol + col] = acc[i][j][q];
+            }
     }
 }
 
-hipError_t launch_ball(const BallArgs &a0, hipStream_t s)
+// out[p][e] = (s_re sum_z part[z][p][col_re], s_im sum_z part[z][p][col_im]), zero where a column is -1.
+__global__ void __launch_bounds__(256) k_ball_scatter(BallScatterArgs a)
 {
-    BallArgs a = a0;
-    int nb = 0;
-    for (int d = 0; d <= a.L; ++d) {
-        const int l = a.L - d;
-        a.blk_lo[d] = nb;
-        nb += (int)(((int64_t)a.P * a.nk_l[l] + kBallRows - 1) / kBallRows);
+    const int64_t n = (int64_t)a.P * a.n_entries;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
+        const int p = (int)(e / a.n_entries);
+        const BallMapEntry m = a.map[e - (int64_t)p * a.n_entries];
+        float re = 0.f, im = 0.f;
+        for (int z = 0; z < a.S; ++z) {
+            const float *pz = a.part + ((int64_t)z * a.P + p) * a.ncol;
+            if (m.col_re >= 0) re += pz[m.col_re];
+            if (m.col_im >= 0) im += pz[m.col_im];
+        }
+        reinterpret_cast<float2 *>(a.out)[e] = make_float2(m.s_re * re, m.s_im * im);
     }
-    a.blk_lo[a.L + 1] = nb;
-    const int64_t n = (int64_t)a.P * a.Kmax * (a.L + 1) * (a.L + 1);
-    const unsigned zb = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_ball_zero, dim3(std::max(zb, 1u)), dim3(256), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess || nb == 0) return e;
-    hipLaunchKernelGGL(k_ball_gemm, dim3(nb), dim3(kBallThreads), 0, s, a);
+}
+
+int ball_splits(int P, int ncol_tiles, int64_t Vo_pad, int n_cu)
+{
+    const int64_t tiles = (int64_t)((P + kBallTileM - 1) / kBallTileM) * ncol_tiles;
+    const int64_t want = std::max<int64_t>(1, (4LL * n_cu + tiles - 1) / tiles);  // about 4 workgroups per CU
+    const int64_t max_s = std::max<int64_t>(1, Vo_pad / (8 * kBallChunk));           // at least 8 chunks each
+    return (int)std::min<int64_t>(std::min<int64_t>(want, max_s), kBallMaxSplits);
+}
+
+int ball_col_tiles(const int *col_off, int *tile_lo)
+{
+    int nt = 0;
+    for (int c = 0; c < 8; ++c) {
+        if (tile_lo) tile_lo[c] = nt;
+        nt += (col_off[c + 1] - col_off[c] + kBallTileN - 1) / kBallTileN;
+    }
+    if (tile_lo) tile_lo[8] = nt;
+    return nt;
+}
+
+hipError_t launch_ball(const BallSymArgs &sa, const BallGemmArgs &ga0, const BallScatterArgs &ca, hipStream_t s)
+{
+    {
+        const int64_t n = (int64_t)sa.P * sa.Vo_pad;
+        const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 16);
+        hipLaunchKernelGGL(k_ball_sym, dim3(std::max(nb, 1u)), dim3(256), 0, s, sa);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    BallGemmArgs ga = ga0;
+    const int nt = ball_col_tiles(ga.col_off, ga.tile_lo);
+    if (nt > 0) {
+        hipLaunchKernelGGL(k_ball_gemm, dim3(nt, (ga.P + kBallTileM - 1) / kBallTileM, ga.S), dim3(kBallThreads), 0, s,
+                           ga);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const int64_t n = (int64_t)ca.P * ca.n_entries;
+    const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 1 << 16);
+    hipLaunchKernelGGL(k_ball_scatter, dim3(std::max(nb, 1u)), dim3(256), 0, s, ca);
     return hipGetLastError();
 }
 

@@ -36,9 +36,12 @@ struct BallTables {
     int N = 0;
     double lam = 0.0;
     BallIndex ix;
-    int64_t V = 0;
-    int32_t *vidx = nullptr;
-    float *R = nullptr, *A = nullptr;
+    int64_t Vo = 0, Vo_pad = 0;
+    int col_off[9] = {0};
+    int n_entries = 0;  // Kmax (L+1)^2
+    int32_t *oct = nullptr;
+    float *T = nullptr;
+    BallMapEntry *map = nullptr;
 };
 
 }  // namespace
@@ -50,6 +53,7 @@ static __device__ __align__(256) unsigned char scratch[MATCHA_NOALLOC_SCRATCH_BY
 
 struct matcha_ctx {
     int device = 0;
+    int n_cu = 0;
     void *scratch = nullptr;  // this device's address of `scratch`
     // recurrence tables for every l <= kMaxL, built by matcha_create
     float4 *tab = nullptr;
@@ -192,9 +196,9 @@ void free_tables(matcha_ctx *ctx)
     }
     ctx->grids.clear();
     for (BallTables &b : ctx->balls) {
-        if (b.vidx) (void)hipFree(b.vidx);
-        if (b.R) (void)hipFree(b.R);
-        if (b.A) (void)hipFree(b.A);
+        if (b.oct) (void)hipFree(b.oct);
+        if (b.T) (void)hipFree(b.T);
+        if (b.map) (void)hipFree(b.map);
     }
     ctx->balls.clear();
     ctx->tab = nullptr;
@@ -544,25 +548,41 @@ matcha_status ball_index_checked(double lam, BallIndex &ix)
     return MATCHA_OK;
 }
 
-// Device bytes of the tables of (N, ix): vidx, R, A.
-size_t ball_table_bytes(int N, const BallIndex &ix, int64_t V)
+// Columns of the transform of ix: sum_l |K_l| (2l + 1) (Re for m = 0..l, Im for m = 1..l).
+int64_t ball_columns(const BallIndex &ix)
 {
-    (void)N;
-    return (size_t)V * (sizeof(int32_t) + sizeof(float) * ((size_t)ix.nk + (size_t)(ix.L + 1) * (ix.L + 2)));
+    int64_t n = 0;
+    for (int l = 0; l <= ix.L; ++l) n += (int64_t)ix.zeros[(size_t)l].size() * (2 * l + 1);
+    return n;
 }
 
-// Voxel count of the ball inscribed in the N^3 grid (centres strictly inside the unit sphere).
-int64_t ball_voxels(int N)
+// Octant voxels of the N^3 grid inside the ball (coordinates >= 0, centre strictly inside).
+int64_t ball_octant_voxels(int N)
 {
     int64_t V = 0;
-    for (int i = 0; i < N; ++i)
-        for (int j = 0; j < N; ++j)
-            for (int k = 0; k < N; ++k) {
+    for (int i = N / 2; i < N; ++i)
+        for (int j = N / 2; j < N; ++j)
+            for (int k = N / 2; k < N; ++k) {
                 const double z = -1.0 + (2.0 / N) * (i + 0.5), y = -1.0 + (2.0 / N) * (j + 0.5),
                              x = -1.0 + (2.0 / N) * (k + 0.5);
                 V += std::sqrt(x * x + y * y + z * z) < 1.0;
             }
     return V;
+}
+
+// Split count and workspace bytes of a transform of P volumes: the symmetrised volumes
+// [8][P][Vo_pad] and the partial sums [S][P][ncol], each 256-byte aligned.
+int ball_split_count(const matcha_ctx *ctx, const BallTables &t, int P)
+{
+    return ball_splits(P, ball_col_tiles(t.col_off, nullptr), t.Vo_pad, ctx->n_cu > 0 ? ctx->n_cu : 256);
+}
+
+size_t ball_ws_need(const matcha_ctx *ctx, const BallTables &t, int P)
+{
+    if (P <= 0) return 0;
+    const int S = ball_split_count(ctx, t, P);
+    return align256(sizeof(float) * 8 * (size_t)P * (size_t)t.Vo_pad) +
+           align256(sizeof(float) * (size_t)S * (size_t)P * (size_t)t.col_off[8]);
 }
 
 }  // namespace
@@ -584,6 +604,7 @@ matcha_status matcha_create(int device, const char *tune_cache, matcha_ctx **out
         return MATCHA_ERR_HIP;
     }
     c->arch = std::string(prop.gcnArchName) + "_cu" + std::to_string(prop.multiProcessorCount);
+    c->n_cu = prop.multiProcessorCount;
     if (noalloc_scratch_ptr(device, &c->scratch) != MATCHA_OK) {
         delete c;
         return MATCHA_ERR_HIP;
@@ -1127,59 +1148,85 @@ matcha_status matcha_ball_index(double Lambda, int32_t *L, int32_t *Kmax, int32_
 matcha_status matcha_ball_prepare(matcha_ctx *ctx, int32_t N, double Lambda)
 {
     if (!ctx || N < 2 || N > MATCHA_BALL_MAX_N) return MATCHA_ERR_INVALID_ARG;
+    if (find_ball(ctx, N, Lambda)) return MATCHA_OK;
     BallIndex ix;
     matcha_status st = ball_index_checked(Lambda, ix);
     if (st != MATCHA_OK) return st;
-    if (find_ball(ctx, N, Lambda)) return MATCHA_OK;
-    if (ball_table_bytes(N, ix, ball_voxels(N)) > MATCHA_BALL_MAX_TABLE_BYTES) return MATCHA_ERR_UNSUPPORTED;
+    const int64_t Vo_pad = (ball_octant_voxels(N) + kBallChunk - 1) / kBallChunk * kBallChunk;
+    if ((size_t)ball_columns(ix) * (size_t)Vo_pad * sizeof(float) > MATCHA_BALL_MAX_TABLE_BYTES)
+        return MATCHA_ERR_UNSUPPORTED;
+    BallHostTables h;
+    ball_build_tables(N, ix, h);
     BallTables t;
     t.N = N;
     t.lam = Lambda;
-    std::vector<int32_t> vidx;
-    std::vector<float> R, A;
-    ball_build_tables(N, ix, vidx, R, A);
-    t.V = (int64_t)vidx.size();
+    t.Vo = h.Vo;
+    t.Vo_pad = h.Vo_pad;
+    std::copy(h.col_off, h.col_off + 9, t.col_off);
+    t.n_entries = (int)h.map.size();
     t.ix = std::move(ix);
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    st = upload(vidx, &t.vidx);
-    if (st == MATCHA_OK) st = upload(R, &t.R);
-    if (st == MATCHA_OK) st = upload(A, &t.A);
+    st = upload(h.oct, &t.oct);
+    if (st == MATCHA_OK) st = upload(h.T, &t.T);
+    if (st == MATCHA_OK) st = upload(h.map, &t.map);
     if (st != MATCHA_OK) {
-        if (t.vidx) (void)hipFree(t.vidx);
-        if (t.R) (void)hipFree(t.R);
+        if (t.oct) (void)hipFree(t.oct);
+        if (t.T) (void)hipFree(t.T);
         return st;
     }
     ctx->balls.push_back(std::move(t));
     return MATCHA_OK;
 }
 
+size_t matcha_ball_workspace_size(const matcha_ctx *ctx, int32_t N, double Lambda, int32_t n_volumes)
+{
+    if (!ctx || n_volumes <= 0) return 0;
+    const BallTables *t = find_ball(ctx, N, Lambda);
+    return t ? ball_ws_need(ctx, *t, n_volumes) : 0;
+}
+
 matcha_status matcha_ball_transform(matcha_ctx *ctx, int32_t N, double Lambda, int32_t n_volumes, const float *u,
-                                    float *coef, void *stream)
+                                    float *coef, void *ws, size_t ws_bytes, void *stream)
 {
     if (!ctx || N < 2 || N > MATCHA_BALL_MAX_N || n_volumes < 0) return MATCHA_ERR_INVALID_ARG;
     if (n_volumes == 0) return MATCHA_OK;
-    if (!u || !coef) return MATCHA_ERR_INVALID_ARG;
+    if (!u || !coef || ((uintptr_t)coef & 7u) != 0) return MATCHA_ERR_INVALID_ARG;
     const BallTables *t = find_ball(ctx, N, Lambda);
     if (!t) return MATCHA_ERR_NOT_PREPARED;
+    if (!ws || !aligned16(ws) || ws_bytes < ball_ws_need(ctx, *t, n_volumes)) return MATCHA_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
-    BallArgs a{};
-    a.u = u;
-    a.out = coef;
-    a.vidx = t->vidx;
-    a.R = t->R;
-    a.A = t->A;
-    a.V = t->V;
-    a.N = N;
-    a.P = n_volumes;
-    a.L = t->ix.L;
-    a.Kmax = t->ix.Kmax;
-    int off = 0;
-    for (int l = 0; l <= a.L; ++l) {
-        a.nk_l[l] = (int)t->ix.zeros[(size_t)l].size();
-        a.rk_off[l] = off;
-        off += a.nk_l[l];
-    }
-    return launched(launch_ball(a, static_cast<hipStream_t>(stream)));
+    const int P = n_volumes, S = ball_split_count(ctx, *t, P);
+    float *usym = static_cast<float *>(ws);
+    float *part = reinterpret_cast<float *>(static_cast<char *>(ws) +
+                                            align256(sizeof(float) * 8 * (size_t)P * (size_t)t->Vo_pad));
+    BallSymArgs sa{};
+    sa.u = u;
+    sa.oct = t->oct;
+    sa.usym = usym;
+    sa.Vo = t->Vo;
+    sa.Vo_pad = t->Vo_pad;
+    sa.N = N;
+    sa.P = P;
+    BallGemmArgs ga{};
+    ga.usym = usym;
+    ga.T = t->T;
+    ga.part = part;
+    ga.Vo_pad = t->Vo_pad;
+    const int64_t chunks = t->Vo_pad / kBallChunk;
+    ga.kper = (chunks + S - 1) / S * kBallChunk;
+    ga.P = P;
+    ga.ncol = t->col_off[8];
+    ga.S = S;
+    std::copy(t->col_off, t->col_off + 9, ga.col_off);
+    BallScatterArgs ca{};
+    ca.part = part;
+    ca.map = t->map;
+    ca.out = coef;
+    ca.P = P;
+    ca.ncol = ga.ncol;
+    ca.S = S;
+    ca.n_entries = t->n_entries;
+    return launched(launch_ball(sa, ga, ca, static_cast<hipStream_t>(stream)));
 }
 
 }  // extern "C"

@@ -27,7 +27,7 @@ EXPORTED = ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_status_
             "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton", "matcha_evaluate",
             "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch", "matcha_graph_destroy",
             "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc", "matcha_grad_workspace_size",
-            "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_transform"]
+            "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_workspace_size", "matcha_ball_transform"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 BALL_MAX_L, BALL_MAX_LAMBDA, BALL_MAX_N = 63, 71.0, 256
 
@@ -110,7 +110,9 @@ def lib():
                                       vp, sz, ct.POINTER(_Tuning)]
         L.matcha_ball_index.argtypes = [ct.c_double, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), vp, vp]
         L.matcha_ball_prepare.argtypes = [vp, i32, ct.c_double]
-        L.matcha_ball_transform.argtypes = [vp, i32, ct.c_double, i32, vp, vp, vp]
+        L.matcha_ball_workspace_size.argtypes = [vp, i32, ct.c_double, i32]
+        L.matcha_ball_workspace_size.restype = sz
+        L.matcha_ball_transform.argtypes = [vp, i32, ct.c_double, i32, vp, vp, vp, sz, vp]
         for name in ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_set_tuning", "matcha_get_tuning",
                      "matcha_lpt_order", "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton",
                      "matcha_evaluate", "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch",
@@ -162,6 +164,7 @@ class Context:
         self.handle = h
         self.device = dev
         self._prepared = set()
+        self._balls = {}
         self._ws = None
 
     def prepare(self, B: int, n_grid: int):
@@ -548,16 +551,22 @@ def ball_transform(ctx: Context, u: torch.Tensor, lam: float, out: torch.Tensor 
     if uu.dim() != 4 or not (uu.shape[1] == uu.shape[2] == uu.shape[3]):
         raise MatchaError("u must be [P, N, N, N] or [N, N, N]")
     P, N = int(uu.shape[0]), int(uu.shape[1])
-    L, K = ct.c_int32(), ct.c_int32()
-    _check(lib().matcha_ball_index(float(lam), ct.byref(L), ct.byref(K), None, None), "matcha_ball_index")
-    ball_prepare(ctx, N, lam)
-    shape = (P, K.value, (L.value + 1) ** 2)
+    key = (N, float(lam))
+    if key not in ctx._balls:  # the index set and tables are built once per (N, lam)
+        L, K = ct.c_int32(), ct.c_int32()
+        _check(lib().matcha_ball_index(float(lam), ct.byref(L), ct.byref(K), None, None), "matcha_ball_index")
+        ball_prepare(ctx, N, lam)
+        ctx._balls[key] = (L.value, K.value)
+    L, K = ctx._balls[key]
+    nb = int(lib().matcha_ball_workspace_size(ctx.handle, N, float(lam), P))
+    ws = ctx.workspace(nb)
+    shape = (P, K, (L + 1) ** 2)
     if out is None:
         out = torch.empty(shape, dtype=torch.complex64, device=u.device)
     elif tuple(out.shape) != shape:
         raise MatchaError(f"out must have shape {shape}")
     _need(out, torch.complex64, "out")
-    _check(lib().matcha_ball_transform(ctx.handle, N, float(lam), P, _ptr(uu), _ptr(out),
+    _check(lib().matcha_ball_transform(ctx.handle, N, float(lam), P, _ptr(uu), _ptr(out), _ptr(ws), nb,
                                        ct.c_void_p(_stream(stream))), "matcha_ball_transform")
     return out[0] if single else out
 

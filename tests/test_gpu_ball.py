@@ -1,9 +1,10 @@
 """Ball-harmonic front end (matcha_ball_transform, App. A.1) against the FP64 oracle (oracle/ball.py).
 
-Tolerance.  The kernel forms each coefficient as an FP32 sum over the V voxels of products of
-FP32-rounded factors (volume, radial table, angular table); with S = (2/N)^3 sum_v |u psi| the
-absolute sum of the terms, the error stays below about (4 + sqrt(V)) * 4 u32 * S (each product a
-few roundings, the sum's rounding a random walk over V terms), u32 = 2^-24.  A wrong sign, index or
+Tolerance.  The kernels form each coefficient as an FP32 sum over the octant voxels of products of
+an FP32 table entry and a sign-symmetrised volume value (a sum of 8 FP32 samples); with
+S = (2/N)^3 sum_v |u psi| the absolute sum of the full-grid terms, the error stays below about
+(4 + sqrt(V)) * 4 u32 * S (a few roundings per product, the sum's rounding a random walk over the
+terms), u32 = 2^-24, V the voxel count.  A wrong sign, index or
 normalisation moves an entry by its own size, about S / sqrt(V) for a random volume, far above.
 Structural zeros (k >= |K_l|) must be exactly zero.
 """
@@ -84,22 +85,25 @@ def check_against_oracle(got, u, lam):
 
 # ---------------------------------------------------------------- element by element
 @pytest.mark.parametrize("N,lam,P", [
-    (12, 9.0, 3),    # even grid, two radial indices at l = 0
-    (13, 14.0, 37),  # odd grid (a voxel centre at r = 0), 148 rows of degree 0: three row tiles, ragged
-    (20, 14.0, 2),   # several voxel chunks per tile with a ragged tail
+    (12, 9.0, 3),     # even grid, two radial indices at l = 0
+    (13, 14.0, 37),   # odd grid: voxels on the mirror planes and one at r = 0
+    (20, 14.0, 130),  # three 64-volume row tiles, the last ragged; ragged column tiles in every class
+    (31, 20.0, 2),    # odd, several K splits over the octant voxels, partial last chunk
 ])
 def test_ball_transform_matches_oracle(M, ctx, N, lam, P):
     rng = np.random.default_rng(1000 + N)
     u = rng.standard_normal((P, N, N, N)).astype(np.float32)
     print(f"ball N={N} lam={lam} P={P}", flush=True)
     got = M.ball_transform(ctx, torch.from_numpy(u).cuda(), lam).cpu().numpy()
-    for p in range(P):
+    # every volume of small batches; the first, last and tile-edge volumes of the large one
+    sample = range(P) if P <= 40 else sorted({0, 1, 63, 64, 127, P - 2, P - 1})
+    for p in sample:
         check_against_oracle(got[p], u[p], lam)
 
 
 def test_ball_transform_widest_degree(M, ctx):
-    """Lambda = 70.5: L = 62, 126 columns at the top degree (eight 16-column tiles, ragged), 603
-    radial indices, on a small grid."""
+    """Lambda = 70.5: L = 62, 603 radial indices, 23517 columns (about 3000 per sign class, many
+    128-column tiles), on a small grid."""
     N, lam = 8, 70.5
     u = np.random.default_rng(7).standard_normal((N, N, N)).astype(np.float32)
     L, zeros = M.ball_index(lam)
@@ -191,20 +195,26 @@ def test_ball_edges(M, ctx):
     import ctypes as ct
     u = torch.zeros((1, 6, 6, 6), dtype=torch.float32, device="cuda")
     out = torch.zeros((1, 1, 4), dtype=torch.complex64, device="cuda")
+    ws = torch.zeros(1 << 20, dtype=torch.uint8, device="cuda")
     s = ct.c_void_p(torch.cuda.current_stream().cuda_stream)
+    U, O, W = (ct.c_void_p(t.data_ptr()) for t in (u, out, ws))
     # not prepared for N = 6
-    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, 1, ct.c_void_p(u.data_ptr()), ct.c_void_p(out.data_ptr()),
-                                     s) == M.ERR_NOT_PREPARED
+    assert lib.matcha_ball_workspace_size(ctx.handle, 6, 5.0, 1) == 0
+    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, 1, U, O, W, ws.numel(), s) == M.ERR_NOT_PREPARED
     assert lib.matcha_ball_prepare(ctx.handle, 1, 5.0) == M.ERR_INVALID_ARG
     assert lib.matcha_ball_prepare(ctx.handle, 6, 0.0) == M.ERR_INVALID_ARG
     assert lib.matcha_ball_prepare(ctx.handle, 6, 80.0) == M.ERR_INVALID_ARG
     assert lib.matcha_ball_prepare(ctx.handle, 6, 5.0) == M.OK
     assert lib.matcha_ball_prepare(ctx.handle, 6, 5.0) == M.OK  # idempotent
+    need = lib.matcha_ball_workspace_size(ctx.handle, 6, 5.0, 1)
+    assert 0 < need <= ws.numel()
     # zero volumes: nothing written, null pointers allowed
     out.fill_(7.0)
-    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, 0, None, None, s) == M.OK
-    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, -1, None, None, s) == M.ERR_INVALID_ARG
-    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, 1, None, ct.c_void_p(out.data_ptr()), s) == M.ERR_INVALID_ARG
+    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, 0, None, None, None, 0, s) == M.OK
+    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, -1, None, None, None, 0, s) == M.ERR_INVALID_ARG
+    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, 1, None, O, W, need, s) == M.ERR_INVALID_ARG
+    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, 1, U, O, W, need - 1, s) == M.ERR_WORKSPACE
+    assert lib.matcha_ball_transform(ctx.handle, 6, 5.0, 1, U, O, None, need, s) == M.ERR_WORKSPACE
     torch.cuda.synchronize()
     assert torch.all(out == 7.0)
     # a zero volume has zero coefficients; a constant one has the symmetry of the cube, which leaves
@@ -213,3 +223,15 @@ def test_ball_edges(M, ctx):
     assert torch.all(got == 0)
     got = M.ball_transform(ctx, torch.ones((6, 6, 6), dtype=torch.float32, device="cuda"), 9.0).cpu().numpy()
     assert np.abs(got[:, 1:16]).max() <= 1e-5 * np.abs(got[:, 0]).max()
+
+
+def test_repeat_calls_are_bitwise_reproducible(M, ctx):
+    """The split count depends on the volume count and the device only: the same call twice gives
+    the same bits, and a volume's coefficients do not depend on the batch it is in beyond rounding."""
+    N, lam = 20, 14.0
+    u = torch.from_numpy(np.random.default_rng(9).standard_normal((70, N, N, N)).astype(np.float32)).cuda()
+    a = M.ball_transform(ctx, u, lam)
+    b = M.ball_transform(ctx, u, lam)
+    assert torch.equal(a, b)
+    c = M.ball_transform(ctx, u[3:4].contiguous(), lam)
+    assert torch.allclose(a[3], c[0], rtol=0, atol=1e-5 * float(a[3].abs().max()))

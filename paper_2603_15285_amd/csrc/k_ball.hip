@@ -294,41 +294,42 @@ __global__ void __launch_bounds__(256) k_ball_sym(BallSymArgs a)
     }
 }
 
-constexpr int kBallThreads = 256;   // 4 waves as 2 x 2, each 32 rows x 64 columns
-constexpr int kBallTileM = 64;      // volumes per workgroup
+constexpr int kBallThreads = 256;   // 4 waves as 2 x 2
 constexpr int kBallTileN = 128;     // columns per workgroup
 constexpr int kBallLds = kBallChunk + 4;  // floats per staged row (K contiguous, padded)
 
-// One workgroup: class sigma and a 128-column tile of it (blockIdx.x), 64 volumes (blockIdx.y), one
-// K split (blockIdx.z), over the octant voxels [z kper, min((z + 1) kper, Vo_pad)).  Both operands are
-// K-contiguous rows staged through LDS in chunks of 32 voxels, double-buffered (the next chunk's global
-// loads are in flight during the current chunk's products).  In each 16-voxel group lane (kq, i) takes
-// voxels 4 kq .. 4 kq + 3 of rows / columns i as one float4 and feeds them to four 16x16x4 steps: the
-// voxel order within the group is permuted identically on both operands.  Partial sums go to
-// part[z][p][col].
+// One workgroup: class sigma and a 128-column tile of it (blockIdx.x), TM volumes (blockIdx.y), one
+// K split (blockIdx.z), over the octant voxels [z kper, min((z + 1) kper, Vo_pad)); wave (wr, wc)
+// owns TM / 2 rows x 64 columns.  Both operands are K-contiguous rows staged through LDS in chunks
+// of 32 voxels, double-buffered (the next chunk's global loads are in flight during the current
+// chunk's products).  In each 16-voxel group lane (kq, i) takes voxels 4 kq .. 4 kq + 3 of rows /
+// columns i as one float4 and feeds them to four 16x16x4 steps: the voxel order within the group is
+// permuted identically on both operands.  Partial sums go to part[z][p][col].
+template <int TM>
 __global__ void __launch_bounds__(kBallThreads) k_ball_gemm(BallGemmArgs a)
 {
-    __shared__ __align__(16) float As[2][kBallTileM][kBallLds];
+    constexpr int RT = TM / 32;  // 16-row tiles per wave
+    __shared__ __align__(16) float As[2][TM][kBallLds];
     __shared__ __align__(16) float Bs[2][kBallTileN][kBallLds];
     int sg = 0;
     while ((int)blockIdx.x >= a.tile_lo[sg + 1]) ++sg;
     const int c0 = (blockIdx.x - a.tile_lo[sg]) * kBallTileN;     // first column of the tile in its class
     const int ncls = a.col_off[sg + 1] - a.col_off[sg];
-    const int p0 = blockIdx.y * kBallTileM;
+    const int p0 = blockIdx.y * TM;
     const int64_t v_lo = (int64_t)blockIdx.z * a.kper;
     const int64_t v_hi = min(v_lo + a.kper, a.Vo_pad);
     const int nch = (int)((v_hi - v_lo) / kBallChunk);
     const float *Ag = a.usym + ((int64_t)sg * a.P) * a.Vo_pad;
     const float *Bg = a.T + (int64_t)a.col_off[sg] * a.Vo_pad;
-    // staging: A 64 rows x 8 float4 (2 per thread), B 128 rows x 8 float4 (4 per thread).  Rows past
-    // the last volume and columns past the class's last are loaded from the last one instead: an
-    // output entry depends on its own row and column only, and those entries are not written.
+    // staging: A TM rows x 8 float4 (TM / 32 per thread), B 128 rows x 8 float4 (4 per thread).  Rows
+    // past the last volume and columns past the class's last are loaded from the last one instead:
+    // an output entry depends on its own row and column only, and those entries are not written.
     const int t = threadIdx.x, sq = t % 8, sr = t / 8;  // float4 sq of rows sr, sr + 32, ...
-    f32x4 ra[2], rb[4];
+    f32x4 ra[TM / 32], rb[4];
     auto load = [&](int ch) {
         const int64_t v = v_lo + (int64_t)ch * kBallChunk + 4 * sq;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < TM / 32; ++i)
             ra[i] = *reinterpret_cast<const f32x4 *>(Ag + (int64_t)min(p0 + sr + 32 * i, a.P - 1) * a.Vo_pad + v);
 #pragma unroll
         for (int i = 0; i < 4; ++i)
@@ -336,15 +337,15 @@ __global__ void __launch_bounds__(kBallThreads) k_ball_gemm(BallGemmArgs a)
     };
     auto store = [&](int buf) {
 #pragma unroll
-        for (int i = 0; i < 2; ++i) *reinterpret_cast<f32x4 *>(&As[buf][sr + 32 * i][4 * sq]) = ra[i];
+        for (int i = 0; i < TM / 32; ++i) *reinterpret_cast<f32x4 *>(&As[buf][sr + 32 * i][4 * sq]) = ra[i];
 #pragma unroll
         for (int i = 0; i < 4; ++i) *reinterpret_cast<f32x4 *>(&Bs[buf][sr + 32 * i][4 * sq]) = rb[i];
     };
     const int wave = t / kWave, lane = t % kWave, li = lane % 16, kq = lane / 16;
-    const int wr = 32 * (wave / 2), wc = 64 * (wave % 2);
-    f32x4 acc[2][4];
+    const int wr = (TM / 2) * (wave / 2), wc = 64 * (wave % 2);
+    f32x4 acc[RT][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < RT; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
     if (nch > 0) {
@@ -357,15 +358,15 @@ __global__ void __launch_bounds__(kBallThreads) k_ball_gemm(BallGemmArgs a)
         if (ch + 1 < nch) load(ch + 1);
 #pragma unroll
         for (int g = 0; g < kBallChunk / 16; ++g) {
-            f32x4 av[2], bv[4];
+            f32x4 av[RT], bv[4];
 #pragma unroll
-            for (int i = 0; i < 2; ++i) av[i] = *reinterpret_cast<const f32x4 *>(&As[buf][wr + 16 * i + li][16 * g + 4 * kq]);
+            for (int i = 0; i < RT; ++i) av[i] = *reinterpret_cast<const f32x4 *>(&As[buf][wr + 16 * i + li][16 * g + 4 * kq]);
 #pragma unroll
             for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const f32x4 *>(&Bs[buf][wc + 16 * j + li][16 * g + 4 * kq]);
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
-                for (int i = 0; i < 2; ++i)
+                for (int i = 0; i < RT; ++i)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
                         acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
@@ -380,7 +381,7 @@ __global__ void __launch_bounds__(kBallThreads) k_ball_gemm(BallGemmArgs a)
         const int col = c0 + wc + 16 * j + li;
         if (col >= ncls) continue;
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
+        for (int i = 0; i < RT; ++i)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 const int row = p0 + wr + 16 * i + 4 * kq + q;
@@ -406,9 +407,12 @@ __global__ void __launch_bounds__(256) k_ball_scatter(BallScatterArgs a)
     }
 }
 
+int ball_tile_m(int P) { return P >= kBallTileMBig ? 128 : 64; }
+
 int ball_splits(int P, int ncol_tiles, int64_t Vo_pad, int n_cu)
 {
-    const int64_t tiles = (int64_t)((P + kBallTileM - 1) / kBallTileM) * ncol_tiles;
+    const int tm = ball_tile_m(P);
+    const int64_t tiles = (int64_t)((P + tm - 1) / tm) * ncol_tiles;
     const int64_t want = std::max<int64_t>(1, (4LL * n_cu + tiles - 1) / tiles);  // about 4 workgroups per CU
     const int64_t max_s = std::max<int64_t>(1, Vo_pad / (8 * kBallChunk));           // at least 8 chunks each
     return (int)std::min<int64_t>(std::min<int64_t>(want, max_s), kBallMaxSplits);
@@ -437,8 +441,11 @@ hipError_t launch_ball(const BallSymArgs &sa, const BallGemmArgs &ga0, const Bal
     BallGemmArgs ga = ga0;
     const int nt = ball_col_tiles(ga.col_off, ga.tile_lo);
     if (nt > 0) {
-        hipLaunchKernelGGL(k_ball_gemm, dim3(nt, (ga.P + kBallTileM - 1) / kBallTileM, ga.S), dim3(kBallThreads), 0, s,
-                           ga);
+        const int tm = ball_tile_m(ga.P);
+        if (tm == 128)
+            hipLaunchKernelGGL(k_ball_gemm<128>, dim3(nt, (ga.P + 127) / 128, ga.S), dim3(kBallThreads), 0, s, ga);
+        else
+            hipLaunchKernelGGL(k_ball_gemm<64>, dim3(nt, (ga.P + 63) / 64, ga.S), dim3(kBallThreads), 0, s, ga);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }

@@ -8,6 +8,7 @@ namespace matcha {
 
 constexpr int kBallChunk = 32;       // octant voxels per staged chunk; rows are padded to a multiple
 constexpr int kBallMaxSplits = 16;   // K splits of the product
+constexpr int kBallTileMBig = 256;   // from this many volumes on, 128-volume row tiles (else 64)
 
 // I_Lambda: zeros[l] = the kept lam_lk of degree l (|K_l| of them), l <= L.
 struct BallIndex {
@@ -59,6 +60,8 @@ struct BallScatterArgs {
     int P, ncol, S, n_entries;
 };
 
+// Volumes per row tile of the product for P volumes (64 or 128).
+int ball_tile_m(int P);
 // K splits for P volumes: about four workgroups per compute unit, at least 8 chunks per split.
 int ball_splits(int P, int ncol_tiles, int64_t Vo_pad, int n_cu);
 // 128-column tiles over the classes; tile_lo (optional, 9 entries) = first tile of each class.

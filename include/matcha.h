@@ -134,7 +134,8 @@ typedef struct {
 } matcha_soft_cfg;
 
 /* Frequency march (Alg. 1).  levels (host) is the global schedule; particle p
- * runs every level < L_p and then L_p.  steps = M_iter Newton steps per level.
+ * runs every level < L_p and then L_p.  steps = M_iter Newton steps per level (gradient ascent
+ * steps when gd_rate > 0).
  * max_step > 0 clips the largest component of a Newton step (0: pure Newton, as
  * in the paper).  early_stop enables the Sec. 2.4 tests: a level ends once
  * |grad| <= tol_grad |F|, |F - F_prev| <= tol_rel |F| (from its second step on) or the last
@@ -152,6 +153,12 @@ typedef struct {
                               particle's final level L_p and the final values; NULL: C.  The BF16
                               path marches the lower levels on BF16-assembled C and the final level
                               on FP32-assembled C_final. */
+    double gd_rate;        /* 0: Newton steps (the method).  > 0: gradient ascent steps instead, the
+                              first-order comparator of Sec. 4.1 (Fig. newton_v_gd): theta += t grad,
+                              t = gd_rate / ((1 + L_j)^2 |C_{L_j}(theta)|), i.e. the Bernstein bound
+                              of App. A.7 on the Hessian as smoothness constant with gd_rate for
+                              1 / B2; max_step and early_stop apply as for Newton, and the
+                              INDEFINITE / SINGULAR flags are never set. */
 } matcha_march_cfg;
 
 /* Launch shapes and tile shapes.  Zero fields mean "library default".  Results never depend on

@@ -63,7 +63,9 @@ def lib():
         L.mo_schedule.argtypes = [ct.c_int, _ip, ct.c_int, _ip]
         L.mo_schedule.restype = ct.c_int
         L.mo_march.argtypes = [ct.c_int, _dp, ct.c_int, _ip, ct.c_int, ct.c_double, ct.c_int, ct.c_double,
-                               ct.c_double, ct.c_double, ct.c_int, _dp, _up]
+                               ct.c_double, ct.c_double, ct.c_double, ct.c_int, _dp, _up]
+        L.mo_gradient_step.argtypes = [_dp, ct.c_double, ct.c_int, ct.c_double, _dp, _dp]
+        L.mo_gradient_step.restype = ct.c_uint
         L.mo_march.restype = ct.c_int
         L.mo_align_one.argtypes = [ct.c_int, ct.c_int, _dp, _dp, ct.c_int, _dp, ct.c_int, ct.c_int, ct.c_int,
                                    ct.c_int, _ip, ct.c_int, ct.c_double, _dp, _dp, _ip]
@@ -162,6 +164,15 @@ def newton_step(e, theta, max_step: float = 0.0):
     return th, int(st), float(sinf[0])
 
 
+def gradient_step(e, theta, rate: float, L: int, max_step: float = 0.0):
+    """One gradient ascent step (the first-order comparator); returns (theta, status, step_inf)."""
+    e = _f64(e)
+    th = _f64(np.array(theta, dtype=np.float64).copy())
+    sinf = np.zeros(1)
+    st = lib().mo_gradient_step(_d(e), float(rate), int(L), float(max_step), _d(th), _d(sinf))
+    return th, int(st), float(sinf[0])
+
+
 def schedule(Lp: int, levels):
     lv = _i32(levels)
     out = np.zeros(len(levels) + 1, dtype=np.int32)
@@ -170,14 +181,14 @@ def schedule(Lp: int, levels):
 
 
 def march(Lp: int, C, levels, steps: int, cand, max_step: float = 0.0, early_stop: bool = False,
-          tol_grad: float = 1e-9, tol_step: float = 1e-10, tol_rel: float = 1e-13):
+          tol_grad: float = 1e-9, tol_step: float = 1e-10, tol_rel: float = 1e-13, gd_rate: float = 0.0):
     C = _c128(C)
     lv = _i32(levels)
     cand = _f64(np.array(cand, dtype=np.float64).copy())
     Kc = cand.shape[0]
     cst = np.zeros(Kc, dtype=np.uint32)
     best = lib().mo_march(Lp, _d(C), len(levels), lv.ctypes.data_as(_ip), steps, float(max_step), int(early_stop),
-                          tol_grad, tol_step, tol_rel, Kc, _d(cand), cst.ctypes.data_as(_up))
+                          tol_grad, tol_step, tol_rel, float(gd_rate), Kc, _d(cand), cst.ctypes.data_as(_up))
     return cand, int(best), cst
 
 

@@ -306,6 +306,27 @@ static double mo_wrap2pi(double x)
     return x < 0.0 ? x + 2.0 * MO_PI : x;
 }
 
+/* theta += dth (largest component clipped to max_step when positive), b reflected into [0, pi] */
+static void mo_apply_step(double *dth, double max_step, double *th, double *step_inf)
+{
+    double mx = fmax(fabs(dth[0]), fmax(fabs(dth[1]), fabs(dth[2])));
+    if (max_step > 0.0 && mx > max_step) {
+        for (int i = 0; i < 3; ++i) dth[i] *= max_step / mx;
+        mx = max_step;
+    }
+    *step_inf = mx;
+    double a = th[0] + dth[0], b = th[1] + dth[1], c = th[2] + dth[2];
+    b = mo_wrap2pi(b);
+    if (b > MO_PI) {
+        b = 2.0 * MO_PI - b;
+        a += MO_PI;
+        c += MO_PI;
+    }
+    th[0] = mo_wrap2pi(a);
+    th[1] = b;
+    th[2] = mo_wrap2pi(c);
+}
+
 unsigned mo_newton_step(const double *e, double max_step, double *th, double *step_inf)
 {
     /* e = F, Fa, Fb, Fc, Faa, Fab, Fac, Fbb, Fbc, Fcc */
@@ -336,27 +357,33 @@ unsigned mo_newton_step(const double *e, double max_step, double *th, double *st
     }
     double dth[3];
     for (int i = 0; i < 3; ++i) dth[i] = -(A[i][0] * g[0] + A[i][1] * g[1] + A[i][2] * g[2]) / det;
-    double mx = fmax(fabs(dth[0]), fmax(fabs(dth[1]), fabs(dth[2])));
-    if (max_step > 0.0 && mx > max_step) {
-        for (int i = 0; i < 3; ++i) dth[i] *= max_step / mx;
-        mx = max_step;
-    }
-    *step_inf = mx;
-    double a = th[0] + dth[0], b = th[1] + dth[1], c = th[2] + dth[2];
-    b = mo_wrap2pi(b);
-    if (b > MO_PI) {
-        b = 2.0 * MO_PI - b;
-        a += MO_PI;
-        c += MO_PI;
-    }
-    th[0] = mo_wrap2pi(a);
-    th[1] = b;
-    th[2] = mo_wrap2pi(c);
+    mo_apply_step(dth, max_step, th, step_inf);
     return st;
 }
 
+/* ------------------------------------------------------ gradient ascent step
+ * The first-order comparator of Sec. 4.1 (Fig. newton_v_gd): theta <- theta + t grad C_L in the
+ * same chart, t = rate / ((1 + L)^2 |C_L(theta)|).  The paper gives no step rule.  This one takes
+ * the Bernstein bound of App. A.7 on the Hessian, B2 (1 + L)^2 ||C_L||_inf, as the smoothness
+ * constant of a 1/M step, with |C_L| at the current point standing in for the sup norm; rate plays
+ * the part of 1 / B2.  Clipping, reflection and the non-finite flag as for the Newton step; the
+ * Hessian is not used. */
+unsigned mo_gradient_step(const double *e, double rate, int L, double max_step, double *th, double *step_inf)
+{
+    for (int i = 0; i < 4; ++i)
+        if (!isfinite(e[i])) {
+            *step_inf = 0.0;
+            return MO_NONFINITE;
+        }
+    double t = rate / ((1.0 + L) * (1.0 + L) * fmax(fabs(e[0]), 1e-300));
+    double dth[3] = {t * e[1], t * e[2], t * e[3]};
+    mo_apply_step(dth, max_step, th, step_inf);
+    return 0;
+}
+
 /* ------------------------------------------------------------ march + select
- * Alg. 1: from the retained candidates, M_iter Newton steps on C_{L_j} at every
+ * Alg. 1: from the retained candidates, M_iter Newton steps (gradient ascent steps when gd_rate > 0,
+ * the first-order comparator) on C_{L_j} at every
  * cutoff of the schedule (the first cutoff is the SOFFT band L0, i.e. the
  * optional refinement at the search band), then the candidate with the largest C_{L_J} at
  * its final point.  The per-particle schedule is the global one with every
@@ -385,7 +412,8 @@ int mo_schedule(int Lp, const int *levels, int n_levels, int *out)
 }
 
 int mo_march(int Lp, const double complex *C, int n_levels, const int *levels, int steps, double max_step, int early_stop,
-             double tol_grad, double tol_step, double tol_rel, int Kc, double *cand, unsigned *cand_status)
+             double tol_grad, double tol_step, double tol_rel, double gd_rate, int Kc, double *cand,
+             unsigned *cand_status)
 {
     int sched[64];
     int ns = mo_schedule(Lp, levels, n_levels, sched);
@@ -406,7 +434,10 @@ int mo_march(int Lp, const double complex *C, int n_levels, const int *levels, i
                     }
                 }
                 Fprev = e[0];
-                st |= mo_newton_step(e, max_step, th, &sinf);
+                if (gd_rate > 0.0)
+                    st |= mo_gradient_step(e, gd_rate, sched[j], max_step, th, &sinf);
+                else
+                    st |= mo_newton_step(e, max_step, th, &sinf);
                 if (sin(th[1]) < 1e-3) st |= MO_NEAR_POLE;
                 if (early_stop && sinf <= tol_step) {
                     st |= MO_EARLY_STOP;
@@ -451,7 +482,7 @@ unsigned mo_align_one(int Lp, int Rp, const double complex *f, const double comp
         cand[4 * p + 3] = val[p];
     }
     unsigned *cst = malloc(sizeof(unsigned) * Kc);
-    int b = mo_march(Lp, C, n_levels, levels, steps, max_step, 0, 0, 0, 0, Kc, cand, cst);
+    int b = mo_march(Lp, C, n_levels, levels, steps, max_step, 0, 0, 0, 0, 0.0, Kc, cand, cst);
     memcpy(best, cand + 4 * b, 4 * sizeof(double));
     *best_idx = b;
     unsigned st = cst[b] | (nmx < Kc ? MO_FEW_MAXIMA : 0u);

@@ -431,28 +431,10 @@ __device__ inline double wrap2pi(double x)
 // Newton step theta <- theta - H^{-1} grad in FP64 with the explicit 3x3 inverse; the
 // readings for indefinite / singular H, clipping and chart wrapping are those of the
 // interface documentation.  e = F, Fa, Fb, Fc, Faa, Fab, Fac, Fbb, Fbc, Fcc.
-__device__ uint32_t newton_step(const double *e, double max_step, double *th, double *step_inf)
+// theta += d (largest component clipped to max_step when positive), b reflected into [0, pi] with
+// (a + pi, c + pi), a and c wrapped into [0, 2 pi).
+__device__ void apply_step(double d0, double d1, double d2, double max_step, double *th, double *step_inf)
 {
-    for (int i = 0; i < 10; ++i)
-        if (!isfinite(e[i])) {
-            *step_inf = 0.0;
-            return 1u;
-        }
-    const double h00 = e[4], h01 = e[5], h02 = e[6], h11 = e[7], h12 = e[8], h22 = e[9];
-    const double c00 = h11 * h22 - h12 * h12, c01 = h02 * h12 - h01 * h22, c02 = h01 * h12 - h02 * h11;
-    const double c11 = h00 * h22 - h02 * h02, c12 = h02 * h01 - h00 * h12, c22 = h00 * h11 - h01 * h01;
-    const double det = h00 * c00 + h01 * c01 + h02 * c02;
-    double hmax = fmax(fmax(fabs(h00), fabs(h01)), fmax(fmax(fabs(h02), fabs(h11)), fmax(fabs(h12), fabs(h22))));
-    uint32_t st = 0;
-    if (!(-h00 > 0.0 && c22 > 0.0 && -det > 0.0)) st |= 2u;
-    if (!(fabs(det) > 1e-30 * hmax * hmax * hmax)) {
-        *step_inf = 0.0;
-        return st | 4u;
-    }
-    const double g0 = e[1], g1 = e[2], g2 = e[3];
-    double d0 = -(c00 * g0 + c01 * g1 + c02 * g2) / det;
-    double d1 = -(c01 * g0 + c11 * g1 + c12 * g2) / det;
-    double d2 = -(c02 * g0 + c12 * g1 + c22 * g2) / det;
     double mx = fmax(fabs(d0), fmax(fabs(d1), fabs(d2)));
     if (max_step > 0.0 && mx > max_step) {
         const double s = max_step / mx;
@@ -472,6 +454,46 @@ __device__ uint32_t newton_step(const double *e, double max_step, double *th, do
     th[0] = wrap2pi(a);
     th[1] = b;
     th[2] = wrap2pi(c);
+}
+
+// Gradient ascent step, the first-order comparator: theta += t grad with
+// t = rate / ((1 + L)^2 |F|) (the Hessian's Bernstein bound as smoothness constant).
+__device__ uint32_t gradient_step(const double *e, double rate, int L, double max_step, double *th,
+                                  double *step_inf)
+{
+    for (int i = 0; i < 4; ++i)
+        if (!isfinite(e[i])) {
+            *step_inf = 0.0;
+            return 1u;
+        }
+    const double t = rate / ((1.0 + L) * (1.0 + L) * fmax(fabs(e[0]), 1e-300));
+    apply_step(t * e[1], t * e[2], t * e[3], max_step, th, step_inf);
+    return 0u;
+}
+
+__device__ uint32_t newton_step(const double *e, double max_step, double *th, double *step_inf)
+{
+    for (int i = 0; i < 10; ++i)
+        if (!isfinite(e[i])) {
+            *step_inf = 0.0;
+            return 1u;
+        }
+    const double h00 = e[4], h01 = e[5], h02 = e[6], h11 = e[7], h12 = e[8], h22 = e[9];
+    const double c00 = h11 * h22 - h12 * h12, c01 = h02 * h12 - h01 * h22, c02 = h01 * h12 - h02 * h11;
+    const double c11 = h00 * h22 - h02 * h02, c12 = h02 * h01 - h00 * h12, c22 = h00 * h11 - h01 * h01;
+    const double det = h00 * c00 + h01 * c01 + h02 * c02;
+    double hmax = fmax(fmax(fabs(h00), fabs(h01)), fmax(fmax(fabs(h02), fabs(h11)), fmax(fabs(h12), fabs(h22))));
+    uint32_t st = 0;
+    if (!(-h00 > 0.0 && c22 > 0.0 && -det > 0.0)) st |= 2u;
+    if (!(fabs(det) > 1e-30 * hmax * hmax * hmax)) {
+        *step_inf = 0.0;
+        return st | 4u;
+    }
+    const double g0 = e[1], g1 = e[2], g2 = e[3];
+    const double d0 = -(c00 * g0 + c01 * g1 + c02 * g2) / det;
+    const double d1 = -(c01 * g0 + c11 * g1 + c12 * g2) / det;
+    const double d2 = -(c02 * g0 + c12 * g1 + c22 * g2) / det;
+    apply_step(d0, d1, d2, max_step, th, step_inf);
     return st;
 }
 
@@ -571,7 +593,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
                     st.frozen[lane] = 1;
                 } else {
                     double sinf_ = 0.0;
-                    st.st[lane] |= newton_step(e, a.max_step, st.th[lane], &sinf_);
+                    st.st[lane] |= a.gd_rate > 0.0 ? gradient_step(e, a.gd_rate, L, a.max_step, st.th[lane], &sinf_)
+                                                   : newton_step(e, a.max_step, st.th[lane], &sinf_);
                     st.moved[lane] = 1;  // near-pole test at the next prepare_step, from its sin b
                     if (a.early_stop && sinf_ <= a.tol_step) {
                         st.st[lane] |= 32u;

@@ -464,7 +464,7 @@ matcha_status soft_launch(const matcha_ctx *ctx, const matcha_batch *batch, cons
 matcha_status march_check(const matcha_batch *batch, const matcha_march_cfg *cfg, int32_t Kc, int lo)
 {
     if (Kc < 1 || Kc > MATCHA_MAX_KC || cfg->steps < 0 || cfg->n_levels < 1 || cfg->n_levels > MATCHA_MAX_LEVELS ||
-        !cfg->levels || !(cfg->max_step >= 0.0) || lo < 1)
+        !cfg->levels || !(cfg->max_step >= 0.0) || !(cfg->gd_rate >= 0.0) || lo < 1)
         return MATCHA_ERR_INVALID_ARG;
     if (cfg->C_final && !aligned16(cfg->C_final)) return MATCHA_ERR_INVALID_ARG;
     if (cfg->early_stop && !(cfg->tol_grad >= 0.0 && cfg->tol_step >= 0.0 && cfg->tol_rel >= 0.0))
@@ -501,7 +501,7 @@ std::string tune_key(const matcha_ctx *ctx, const matcha_batch *b, const matcha_
                     std::to_string(soft->Kc) + "|lv";
     for (int j = 0; j < march->n_levels; ++j) k += (j ? "," : "") + std::to_string(march->levels[j]);
     k += "|s" + std::to_string(march->steps) + "|f64_" + std::to_string(march->fp64_above) + "|es" +
-         std::to_string(march->early_stop) + "|pr" + std::to_string((int)prec);
+         std::to_string(march->early_stop) + "|pr" + std::to_string((int)prec) + (march->gd_rate > 0.0 ? "|gd" : "");
     for (char &c : k)
         if (c == ' ' || c == '\t' || c == '\n') c = '_';
     return k;
@@ -854,6 +854,7 @@ matcha_status matcha_march_newton(matcha_ctx *ctx, const matcha_batch *batch, co
     a.tol_grad = cfg->tol_grad;
     a.tol_step = cfg->tol_step;
     a.tol_rel = cfg->tol_rel;
+    a.gd_rate = cfg->gd_rate;
     a.Kc = Kc;
     a.cand = reinterpret_cast<float4 *>(cand);
     a.best = reinterpret_cast<float4 *>(best);

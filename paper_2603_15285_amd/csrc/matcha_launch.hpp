@@ -73,6 +73,7 @@ struct MarchArgs {
     double max_step;
     int early_stop;
     double tol_grad, tol_step, tol_rel;
+    double gd_rate;           // > 0: gradient ascent steps instead of Newton steps
     int Kc;
     float4 *cand;
     float4 *best;

@@ -58,7 +58,7 @@ class _MarchCfg(ct.Structure):
     _fields_ = [("levels", ct.POINTER(ct.c_int32)), ("n_levels", ct.c_int32), ("steps", ct.c_int32),
                 ("max_step", ct.c_double), ("early_stop", ct.c_int32),
                 ("tol_grad", ct.c_double), ("tol_step", ct.c_double), ("tol_rel", ct.c_double),
-                ("fp64_above", ct.c_int32), ("C_final", ct.c_void_p)]
+                ("fp64_above", ct.c_int32), ("C_final", ct.c_void_p), ("gd_rate", ct.c_double)]
 
 
 class _AlignBufs(ct.Structure):
@@ -271,11 +271,11 @@ TOL_GRAD, TOL_STEP, TOL_REL = 1e-9, 1e-10, 1e-13
 
 
 def _march_cfg(levels, steps, max_step=0.0, early_stop=False, tol_grad=TOL_GRAD, tol_step=TOL_STEP, tol_rel=TOL_REL,
-               fp64_above=0, C_final=None):
+               fp64_above=0, C_final=None, gd_rate=0.0):
     lv = np.ascontiguousarray(levels, dtype=np.int32)
     cfg = _MarchCfg(lv.ctypes.data_as(ct.POINTER(ct.c_int32)), len(lv), int(steps), float(max_step),
                     int(early_stop), float(tol_grad), float(tol_step), float(tol_rel), int(fp64_above),
-                    None if C_final is None else C_final.data_ptr())
+                    None if C_final is None else C_final.data_ptr(), float(gd_rate))
     cfg._keep = lv  # the levels array must outlive the struct
     return cfg
 
@@ -343,8 +343,9 @@ def march_newton(ctx: Context, batch: Batch, C: torch.Tensor, levels: Sequence[i
                  cand: torch.Tensor, status: torch.Tensor, best: torch.Tensor | None = None,
                  best_idx: torch.Tensor | None = None, max_step: float = 0.0, early_stop: bool = False,
                  tol_grad: float = TOL_GRAD, tol_step: float = TOL_STEP, tol_rel: float = TOL_REL, fp64_above: int = 0,
-                 C_final: torch.Tensor | None = None, stream=None):
-    """C_final (same layout as C): coefficients for each particle's final level (None: C)."""
+                 C_final: torch.Tensor | None = None, gd_rate: float = 0.0, stream=None):
+    """C_final (same layout as C): coefficients for each particle's final level (None: C).
+    gd_rate > 0: gradient ascent steps instead of Newton steps (the first-order comparator)."""
     Kc = int(cand.shape[1])
     if best is None:
         best = torch.empty((batch.n, 4), dtype=torch.float32, device=C.device)
@@ -352,7 +353,7 @@ def march_newton(ctx: Context, batch: Batch, C: torch.Tensor, levels: Sequence[i
         best_idx = torch.empty(batch.n, dtype=torch.int32, device=C.device)
     if C_final is not None:
         _need(C_final, torch.float32, "C_final")
-    cfg = _march_cfg(levels, steps, max_step, early_stop, tol_grad, tol_step, tol_rel, fp64_above, C_final)
+    cfg = _march_cfg(levels, steps, max_step, early_stop, tol_grad, tol_step, tol_rel, fp64_above, C_final, gd_rate)
     bs = batch.c_struct()
     nb = workspace_bytes(batch)
     ws = ctx.workspace(nb)
@@ -415,7 +416,7 @@ def align(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch
           Kc: int, levels: Sequence[int], steps: int, max_step: float = 0.0, fp64_above: int = 0,
           prec: int = FP32, f32: torch.Tensor | None = None, h32: torch.Tensor | None = None,
           early_stop: bool = False, tol_grad: float = TOL_GRAD, tol_step: float = TOL_STEP, tol_rel: float = TOL_REL,
-          bufs: dict | None = None, stream=None):
+          bufs: dict | None = None, gd_rate: float = 0.0, stream=None):
     """The whole path: assembly, SOFFT search, march and selection.  Returns (best, best_idx, status).
 
     prec = BF16_FP32ACC with f32 / h32 given: the final level marches on FP32-assembled coefficients."""
@@ -429,7 +430,7 @@ def align(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch
     best, best_idx, status = march_newton(ctx, batch, C, levels, steps, cand, status, best=b.get("best"),
                                           best_idx=b.get("best_idx"), max_step=max_step, early_stop=early_stop,
                                           tol_grad=tol_grad, tol_step=tol_step, tol_rel=tol_rel,
-                                          fp64_above=fp64_above, C_final=C32, stream=stream)
+                                          fp64_above=fp64_above, C_final=C32, gd_rate=gd_rate, stream=stream)
     if bufs is not None:
         bufs.update(C=C, cand=cand, status=status, best=best, best_idx=best_idx)
         if C32 is not None:

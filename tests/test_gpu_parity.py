@@ -304,6 +304,37 @@ def test_march_from_oracle_candidates(M, ctx):
             assert rot_err(best[p, :3].astype(np.float64), oc[ob, :3]) <= 1e-3
 
 
+@pytest.mark.parametrize("rate", [2.0, 10.0])
+def test_gradient_ascent_march_matches_oracle(M, ctx, rate):
+    """The first-order comparator (gd_rate > 0) from the oracle's SOFFT candidates, 6 steps per
+    level, against the oracle's march with the same rate: every candidate's rotation and value."""
+    wl = S.WORKLOADS["L32_R32_B12_K16"]
+    b = S.make_workload("L32_R32_B12_K16", n_particles=2)
+    batch, f, h, w = upload(M, b)
+    C = M.coeff_assemble(ctx, batch, f, h, w)
+    start = np.zeros((2, wl.Kc, 4), dtype=np.float32)
+    for p in range(2):
+        grid = O.soft_grid(wl.B, oracle_C(b, p), wl.n_grid)
+        idx, val, _ = O.soft_select(grid, wl.Kc)
+        start[p, :, :3] = O.grid_euler(idx, wl.n_grid)
+        start[p, :, 3] = val
+    cand = torch.from_numpy(start).cuda()
+    status = torch.zeros(2, dtype=torch.int32).cuda()
+    best, best_idx, status = M.march_newton(ctx, batch, C, wl.levels, 6, cand, status, gd_rate=rate)
+    cand, best, best_idx, status = cand.cpu().numpy(), best.cpu().numpy(), best_idx.cpu().numpy(), status.cpu().numpy()
+    for p in range(2):
+        oc, ob, ost = O.march(32, oracle_C(b, p), list(wl.levels), 6, start[p].astype(np.float64), gd_rate=rate)
+        assert not np.any(ost & (O.INDEFINITE | O.SINGULAR))  # Newton-only flags
+        Sc = scale(b, p, 32)
+        clean = (ost & (O.NEAR_POLE | O.NONFINITE)) == 0
+        err = rot_err(cand[p, :, :3].astype(np.float64), oc[:, :3])
+        assert np.all(err[clean] <= 1e-3), err[clean]
+        assert np.all(np.abs(cand[p, clean, 3] - oc[clean, 3]) <= 1e-5 * Sc)
+        top = np.sort(oc[:, 3])[::-1]
+        if top[0] - top[1] > 1e-5 * Sc:
+            assert best_idx[p] == ob
+
+
 def test_march_single_steps_of_every_candidate(M, ctx):
     """Every Newton step of every candidate's oracle trajectory, the flagged candidates (indefinite
     or singular H, near a pole) included, replayed one step at a time: from the oracle's iterate

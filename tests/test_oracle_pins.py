@@ -648,3 +648,54 @@ def test_early_stop_noiseless_agrees_with_fixed_steps():
                              S.euler_zyz_to_matrix(fx[:, 0], fx[:, 1], fx[:, 2]))
         assert np.all(err < 1e-8), err
         assert np.all(S.geodesic_deg(b.R_true()[p], S.euler_zyz_to_matrix(es[:, 0], es[:, 1], es[:, 2])) < 1e-8)
+
+
+# --------------------------------------------------------------- gradient ascent comparator
+def test_gradient_step_is_a_first_order_ascent_step():
+    """theta + t grad F with t = rate / ((1+L)^2 |F|): for a small step the objective rises by
+    t |grad F|^2 to first order (the gradient itself is pinned by central differences above)."""
+    b = S.make_batch(12, 6, 1, seed=31, snr=0.5)
+    C = O.coeff_assemble(12, 6, b.f(0), 12, b.h, 12, b.w)
+    rng = np.random.default_rng(3)
+    for _ in range(5):
+        th = np.array([rng.uniform(0, 2 * np.pi), rng.uniform(0.3, 2.8), rng.uniform(0, 2 * np.pi)])
+        e = O.evaluate(12, C, th)
+        rate = 1e-4
+        t = rate / (13.0 ** 2 * abs(e[0]))
+        new, st, sinf = O.gradient_step(e, th, rate, 12)
+        assert st == 0
+        assert np.allclose(new, th + t * np.asarray(e[1:4]), rtol=0, atol=1e-15)
+        rise = O.evaluate_F(12, C, new) - e[0]
+        g2 = float(np.sum(np.asarray(e[1:4]) ** 2))
+        assert abs(rise - t * g2) <= 1e-3 * t * g2
+        assert sinf == pytest.approx(t * np.abs(e[1:4]).max(), rel=1e-14)
+
+
+def test_gradient_ascent_converges_linearly_where_newton_is_quadratic():
+    """Noiseless particle, 3 degrees off: gradient ascent (rate 10) raises F at every step and
+    closes in linearly (a roughly constant factor per step), while Newton from the same start is at
+    the maximum within four steps (Fig. newton_v_gd's contrast)."""
+    b = S.make_batch(16, 8, 1, seed=9, noiseless=True)
+    C = O.coeff_assemble(16, 8, b.f(0), 16, b.h, 16, b.w)
+    Rt = b.R_true()[0]
+    th = _perturbed(Rt, 3.0, 1)
+    F, errs = [], []
+    for _ in range(60):
+        e = O.evaluate(16, C, th)
+        F.append(e[0])
+        th, st, _ = O.gradient_step(e, th, 10.0, 16)
+        assert st == 0
+        errs.append(float(S.geodesic_deg(Rt, S.euler_zyz_to_matrix(*th))))
+    assert all(F[i + 1] >= F[i] - 1e-12 * abs(F[i]) for i in range(len(F) - 1))
+    assert errs[-1] < 1e-3
+    ratios = [errs[i + 1] / errs[i] for i in range(20, 59)]
+    assert 0.5 < min(ratios) and max(ratios) < 0.9  # linear, not quadratic
+    # the march with gd_rate takes exactly these steps at one level
+    cand = np.array([np.r_[_perturbed(Rt, 3.0, 1), 0.0]])
+    out, _, cst = O.march(16, C, [16], 60, cand, gd_rate=10.0)
+    assert np.allclose(out[0, :3], th, rtol=0, atol=1e-12)
+    assert cst[0] == 0
+    thn = _perturbed(Rt, 3.0, 1)
+    for _ in range(4):
+        thn, _, _ = O.newton_step(O.evaluate(16, C, thn), thn)
+    assert S.geodesic_deg(Rt, S.euler_zyz_to_matrix(*thn)) < 1e-9

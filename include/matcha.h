@@ -318,6 +318,24 @@ matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, c
 matcha_status matcha_soft_search_noalloc(matcha_ctx *ctx, const matcha_batch *batch, const float *C,
                                          const matcha_soft_cfg *cfg, float *cand, uint32_t *status, void *stream);
 
+/* ---- low-rank structure of the correlation blocks ------------------------- */
+/* App. A.6 and B.1: per particle and degree l <= L_p the singular values of the block
+ * C^l = sum_r w_r f_l(r) h_l(r)^H (eq. Alpha_l_factorization with shells for the radial index: rank at
+ * most R_p, eq. rank_bound, and unchanged by rotating h) and its effective rank
+ *     r_eff(l) = min { k >= 1 : s_{k+1} / s_k < rho }
+ * (the paper uses rho = 0.2; the number of values min(2l+1, R_p) when no ratio falls below rho; 0
+ * for a zero block).  Computed in FP64 from the R_p x R_p Gram matrices of the shells (pivoted
+ * Cholesky factors X_F, X_H; the singular values of X_F^H X_H by one-sided Jacobi), one wave per
+ * (particle, degree).  f, h, w as for matcha_coeff_assemble in FP32.  Outputs (device):
+ * sv [P][L_max+1][n_sv] float64, descending, zero-padded (entries beyond min(2l+1, R_p) and
+ * degrees above L_p are 0); r_eff [P][L_max+1] int32.  1 <= n_sv <= 64, 0 < rho < 1.
+ * MATCHA_ERR_UNSUPPORTED when max R_p > MATCHA_LOWRANK_MAX_SHELLS (the LDS holds three
+ * R_p x R_p complex FP64 matrices). */
+#define MATCHA_LOWRANK_MAX_SHELLS 48
+matcha_status matcha_lowrank_spectrum(matcha_ctx *ctx, const matcha_batch *batch, const float *f, const float *h,
+                                      const float *w, double rho, int32_t n_sv, double *sv, int32_t *r_eff,
+                                      void *stream);
+
 /* ---- ball-harmonic front end ---------------------------------------------- */
 /* The step before the path (App. A.1): coefficients of real volumes in the ball-harmonic
  * (Fourier-Bessel) basis of the unit ball, psi_klm(x) = c_lk j_l(lam_lk |x|) Y_lm(x / |x|), with

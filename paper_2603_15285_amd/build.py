@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmatcha.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["k_assemble.hip", "k_assemble_bf16.hip", "k_soft.hip", "k_march.hip", "k_adjoint.hip", "k_ball.hip",
+SOURCES = ["k_assemble.hip", "k_assemble_bf16.hip", "k_soft.hip", "k_march.hip", "k_adjoint.hip", "k_ball.hip", "k_lowrank.hip",
            "matcha_api.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -935,6 +935,38 @@ matcha_status matcha_grad_template(matcha_ctx *ctx, const matcha_batch *batch, c
     return launched(launch_grad(a, static_cast<hipStream_t>(stream)));
 }
 
+matcha_status matcha_lowrank_spectrum(matcha_ctx *ctx, const matcha_batch *batch, const float *f, const float *h,
+                                      const float *w, double rho, int32_t n_sv, double *sv, int32_t *r_eff,
+                                      void *stream)
+{
+    int lo, hi, rmax;
+    matcha_status st = check_batch(batch, &lo, &hi, &rmax);
+    if (st != MATCHA_OK) return st;
+    if (!(rho > 0.0 && rho < 1.0) || n_sv < 1 || n_sv > 64) return MATCHA_ERR_INVALID_ARG;
+    if (batch->n_particles == 0) return ctx ? MATCHA_OK : MATCHA_ERR_INVALID_ARG;
+    if (!f || !h || !w || !sv || !r_eff || !batch->f_offset) return MATCHA_ERR_INVALID_ARG;
+    if (rmax > MATCHA_LOWRANK_MAX_SHELLS) return MATCHA_ERR_UNSUPPORTED;
+    if (!ctx) return MATCHA_ERR_INVALID_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    LowRankArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.f = reinterpret_cast<const float2 *>(f);
+    a.f_off = batch->f_offset;
+    a.h = reinterpret_cast<const float2 *>(h);
+    a.w = w;
+    a.Lp = batch->L_dev;
+    a.Rp = batch->R_dev;
+    a.Lh = batch->L_h;
+    a.L_max = hi;
+    a.R_max = rmax;
+    a.P = batch->n_particles;
+    a.rho = rho;
+    a.sv = sv;
+    a.r_eff = r_eff;
+    a.n_sv = n_sv;
+    return launched(launch_lowrank(a, static_cast<hipStream_t>(stream)));
+}
+
 struct matcha_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;

@@ -117,6 +117,20 @@ struct GradArgs {
     const float4 *tab;
 };
 
+struct LowRankArgs {
+    const float2 *f;
+    const int64_t *f_off;
+    const float2 *h;
+    const float *w;
+    const int32_t *Lp;
+    const int32_t *Rp;
+    int Lh, L_max, R_max, P;
+    double rho;
+    double *sv;               // [P][L_max + 1][n_sv], descending, zero-padded
+    int32_t *r_eff;           // [P][L_max + 1]
+    int n_sv;
+};
+
 size_t assemble_smem_bytes(int Lmax, int Rmax);
 hipError_t launch_assemble_f32(const AsmArgs &a, int P, int Lmax, int Rmax, hipStream_t s);
 // by_L[0 .. P-1] = the particle indices ordered by decreasing L_p (equal L_p in any order).
@@ -143,5 +157,7 @@ size_t grad_smem_bytes(int Lmax);
 // segments in order (E = R_h (L_h+1)^2 template entries).
 int grad_segments(int64_t E, int P);
 hipError_t launch_grad(const GradArgs &a, hipStream_t s);
+size_t lowrank_smem_bytes(int Rmax);
+hipError_t launch_lowrank(const LowRankArgs &a, hipStream_t s);
 
 }  // namespace matcha

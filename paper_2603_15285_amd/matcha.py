@@ -27,7 +27,8 @@ EXPORTED = ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_status_
             "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton", "matcha_evaluate",
             "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch", "matcha_graph_destroy",
             "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc", "matcha_grad_workspace_size",
-            "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_workspace_size", "matcha_ball_transform"]
+            "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_workspace_size", "matcha_ball_transform",
+            "matcha_lowrank_spectrum"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 BALL_MAX_L, BALL_MAX_LAMBDA, BALL_MAX_N = 63, 71.0, 256
 
@@ -110,6 +111,7 @@ def lib():
                                       vp, sz, ct.POINTER(_Tuning)]
         L.matcha_ball_index.argtypes = [ct.c_double, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), vp, vp]
         L.matcha_ball_prepare.argtypes = [vp, i32, ct.c_double]
+        L.matcha_lowrank_spectrum.argtypes = [vp, bp, vp, vp, vp, ct.c_double, i32, vp, vp, vp]
         L.matcha_ball_workspace_size.argtypes = [vp, i32, ct.c_double, i32]
         L.matcha_ball_workspace_size.restype = sz
         L.matcha_ball_transform.argtypes = [vp, i32, ct.c_double, i32, vp, vp, vp, sz, vp]
@@ -117,7 +119,7 @@ def lib():
                      "matcha_lpt_order", "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton",
                      "matcha_evaluate", "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch",
                      "matcha_graph_destroy", "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc",
-                     "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_transform"]:
+                     "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_transform", "matcha_lowrank_spectrum"]:
             getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -523,6 +525,28 @@ def c_unpack(L: int, C_wedge: np.ndarray) -> np.ndarray:
     out = np.zeros((L + 1) * (2 * L + 1) * (2 * L + 3) // 3, dtype=np.complex64)
     _check(lib().matcha_c_unpack(int(L), cw.ctypes.data, out.ctypes.data), "matcha_c_unpack")
     return out
+
+
+# ------------------------------------------------------------ low-rank structure
+LOWRANK_MAX_SHELLS = 48
+
+
+def lowrank_spectrum(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tensor, w: torch.Tensor,
+                     rho: float = 0.2, n_sv: int | None = None, stream=None):
+    """matcha_lowrank_spectrum: singular values of every C^l (float64 [P, L_max+1, n_sv], descending)
+    and the effective ranks at rho (int32 [P, L_max+1])."""
+    _need(f, torch.float32, "f")
+    _need(h, torch.float32, "h")
+    L_max = int(batch.L.max()) if batch.n else 0
+    if n_sv is None:
+        n_sv = int(min(64, max(1, int(batch.R.max()) if batch.n else 1)))
+    sv = torch.zeros((batch.n, L_max + 1, n_sv), dtype=torch.float64, device=f.device)
+    r_eff = torch.zeros((batch.n, L_max + 1), dtype=torch.int32, device=f.device)
+    bs = batch.c_struct()
+    _check(lib().matcha_lowrank_spectrum(ctx.handle, ct.byref(bs), _ptr(f), _ptr(h), _ptr(w), float(rho), int(n_sv),
+                                         _ptr(sv), _ptr(r_eff), ct.c_void_p(_stream(stream))),
+           "matcha_lowrank_spectrum")
+    return sv, r_eff
 
 
 # ------------------------------------------------------------ ball-harmonic front end

@@ -19,7 +19,7 @@ LIB = os.path.join(ROOT, "paper_2603_15285_amd", "libmatcha.so")
 LLVM = "/opt/rocm/llvm/bin"
 MAGIC = b"__CLANG_OFFLOAD_BUNDLE__"
 KERNELS = {"k_assemble_f32", "k_assemble_bf16", "k_soft_grid", "k_soft_maxima", "k_soft_rank", "k_march",
-           "k_evaluate", "k_grad_particle", "k_grad_reduce", "k_ball_sym", "k_ball_gemm", "k_ball_scatter"}
+           "k_evaluate", "k_grad_particle", "k_grad_reduce", "k_ball_sym", "k_ball_gemm", "k_ball_scatter", "k_lowrank_sv"}
 
 
 def _disassembly(tmp_path):

@@ -699,3 +699,39 @@ def test_gradient_ascent_converges_linearly_where_newton_is_quadratic():
     for _ in range(4):
         thn, _, _ = O.newton_step(O.evaluate(16, C, thn), thn)
     assert S.geodesic_deg(Rt, S.euler_zyz_to_matrix(*thn)) < 1e-9
+
+
+# --------------------------------------------------------------- low-rank structure (App. A.6, B.1)
+def test_effective_rank_definition_on_known_spectra():
+    from oracle import lowrank as LR
+    assert LR.effective_rank([1.0, 0.5, 0.05, 0.01]) == 2        # 0.05 / 0.5 = 0.1 < 0.2
+    assert LR.effective_rank([1.0, 0.1, 0.09]) == 1
+    assert LR.effective_rank([1.0, 0.9, 0.8]) == 3               # no gap: all of them
+    assert LR.effective_rank([1.0, 0.0, 0.0]) == 1               # exact rank 1
+    assert LR.effective_rank([0.0, 0.0]) == 0
+    assert LR.effective_rank([2.0, 0.39]) == 1 and LR.effective_rank([2.0, 0.4]) == 2  # strict inequality
+    assert LR.effective_rank([1.0, 0.5, 0.05], rho=0.05) == 3
+
+
+def test_block_singular_values_of_a_constructed_factorisation():
+    """f and h built so that C^l = U diag(s) V^H with orthonormal U, V (shell weights w_r = 1):
+    f_l(r) = s_r u_r, h_l(r) = v_r for r < R, so the singular values are s exactly."""
+    from oracle import lowrank as LR
+    rng = np.random.default_rng(17)
+    L, R = 6, 4
+    f = np.zeros((R, (L + 1) ** 2), dtype=complex)
+    h = np.zeros((R, (L + 1) ** 2), dtype=complex)
+    want = {}
+    for l in range(L + 1):
+        n = 2 * l + 1
+        k = min(n, R)
+        U, _ = np.linalg.qr(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+        V, _ = np.linalg.qr(rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k)))
+        s = np.sort(rng.uniform(0.1, 2.0, k))[::-1]
+        for r in range(k):
+            f[r, l * l:(l + 1) ** 2] = s[r] * U[:, r]
+            h[r, l * l:(l + 1) ** 2] = V[:, r]
+        want[l] = s
+    got = LR.block_singular_values(L, R, f, L, h, L, np.ones(R))
+    for l in range(L + 1):
+        assert np.allclose(got[l], want[l], rtol=0, atol=1e-13)

@@ -336,6 +336,44 @@ matcha_status matcha_lowrank_spectrum(matcha_ctx *ctx, const matcha_batch *batch
                                       const float *w, double rho, int32_t n_sv, double *sv, int32_t *r_eff,
                                       void *stream);
 
+/* ---- translation search and the rotation-translation alternation (App. C) --- */
+/* The 6-D problem maximises <f, g o S_tau h> over rotations g and shifts tau, (S_tau h)(x) = h(x - tau),
+ * by alternating the path (rotations at a fixed shift) with an FFT cross-correlation (shifts at a
+ * fixed rotation), T times from zero shift.  Written with s = g tau, the pose is f = S_s (g o h):
+ * the rotation step aligns f(x + s) to h (so the template, shared by the batch, never moves), and
+ * the translation step maximises c(s) = sum_x f(x) (g o h)(x - s), (g o h)(x) = h(R_g^T x), the
+ * rotated template resampled by trilinear interpolation.  c is evaluated on the integer shifts by
+ * inverse FFT of F conj(U), the best one within a window is refined by an upsampled DFT around it
+ * (+-0.75 voxel at 1/upsample steps: the efficient upsampled correlation the paper cites), and the
+ * shift is returned in voxels along (x, y, z).  tau = R_g^T s.
+ * Volumes: float32 [n][N][N][N], x fastest; spectra: the unnormalised forward transform's half
+ * plane, complex float32 [n][N][N][N/2+1]; shifts and rotations: float4 per volume, (x, y, z, .) and
+ * (a, b, c, .) (the march's best has this layout).  FFTs are hipFFT plans made by matcha_fft_prepare
+ * for one (N, n) and kept until matcha_destroy; their work area comes from the caller's workspace.
+ * Calls on one context share those plans and must be ordered. */
+#define MATCHA_TRANSLATE_MAX_N 256
+#define MATCHA_TRANSLATE_MAX_UPSAMPLE 40
+
+/* Plans for n_volumes N^3 volumes (N even, 4 <= N <= MATCHA_TRANSLATE_MAX_N); idempotent. */
+matcha_status matcha_fft_prepare(matcha_ctx *ctx, int32_t N, int32_t n_volumes);
+/* Workspace bytes of the translation calls for a prepared (N, n_volumes) and an upsampling factor
+ * (1 for matcha_volume_spectrum and matcha_shift_volumes); 0 if not prepared. */
+size_t matcha_translate_workspace_size(const matcha_ctx *ctx, int32_t N, int32_t n_volumes, int32_t upsample);
+/* spec = the forward transforms of vol (device). */
+matcha_status matcha_volume_spectrum(matcha_ctx *ctx, int32_t N, int32_t n_volumes, const float *vol, float *spec,
+                                     void *ws, size_t ws_bytes, void *stream);
+/* out_p(x) = f_p(x + s_p) from f_p's spectrum (cyclic, Nyquist planes dropped): the particles as the
+ * rotation step sees them. */
+matcha_status matcha_shift_volumes(matcha_ctx *ctx, int32_t N, int32_t n_volumes, const float *spec,
+                                   const float *shifts, float *out, void *ws, size_t ws_bytes, void *stream);
+/* The translation step: for each volume, the shift s (|s_i| <= window for the integer search, then
+ * the upsampled refinement) maximising sum_x f_p(x) h(R_p^T (x - s)); shift_out = (s_x, s_y, s_z, c(s)).
+ * spec_f: the particles' spectra; h: device float32 [N^3]; euler: float4 [n] rotations.
+ * MATCHA_ERR_UNSUPPORTED when the refinement's tables exceed 64 KB of LDS. */
+matcha_status matcha_translation_search(matcha_ctx *ctx, int32_t N, int32_t n_volumes, const float *spec_f,
+                                        const float *h, const float *euler, int32_t window, int32_t upsample,
+                                        float *shift_out, void *ws, size_t ws_bytes, void *stream);
+
 /* ---- ball-harmonic front end ---------------------------------------------- */
 /* The step before the path (App. A.1): coefficients of real volumes in the ball-harmonic
  * (Fourier-Bessel) basis of the unit ball, psi_klm(x) = c_lk j_l(lam_lk |x|) Y_lm(x / |x|), with

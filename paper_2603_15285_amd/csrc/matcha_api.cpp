@@ -2,6 +2,7 @@
 // read-only table construction, workspace layout, launch sizing, the tune cache.  Everything
 // numerical runs in the kernels.
 #include <hip/hip_runtime.h>
+#include <hipfft/hipfft.h>
 
 #include <algorithm>
 #include <cmath>
@@ -29,6 +30,13 @@ struct GridTables {
     int B = 0, n = 0;
     float2 *dgrid = nullptr;  // weighted d^l(b_i) per node and wedge pair (build_grid_table)
     float *dft = nullptr;     // DFT tables of the grid kernel (build_soft_dft)
+};
+
+// 3-D FFT plans of one prepared (N, batch): real-to-half-complex and back, work area from the caller.
+struct FftPlans {
+    int N = 0, P = 0;
+    hipfftHandle r2c = 0, c2r = 0;
+    size_t work = 0;
 };
 
 // Ball-harmonic tables of one prepared (N, Lambda) (k_ball.hip).
@@ -61,6 +69,7 @@ struct matcha_ctx {
     PairInfo *pinfo = nullptr;
     std::vector<GridTables> grids;  // every prepared (B, n); freed by matcha_destroy only
     std::vector<BallTables> balls;  // every prepared (N, Lambda); freed by matcha_destroy only
+    std::vector<FftPlans> ffts;     // every prepared (N, batch); destroyed by matcha_destroy only
     matcha_tuning tune{0, 0, 0, 0, 0};
     std::string tune_path;  // tune cache file, empty: none
     std::map<std::string, matcha_tuning> tune_cache;
@@ -201,6 +210,11 @@ void free_tables(matcha_ctx *ctx)
         if (b.map) (void)hipFree(b.map);
     }
     ctx->balls.clear();
+    for (FftPlans &q : ctx->ffts) {
+        if (q.r2c) (void)hipfftDestroy(q.r2c);
+        if (q.c2r) (void)hipfftDestroy(q.c2r);
+    }
+    ctx->ffts.clear();
     ctx->tab = nullptr;
     ctx->tab64 = nullptr;
     ctx->pinfo = nullptr;
@@ -530,6 +544,39 @@ bool tune_cache_store(const matcha_ctx *ctx, const std::string &key, const match
     std::fprintf(fp, "%s %d %d %d %d %d\n", key.c_str(), t.march_nc, t.soft_threads, t.asm_tiles, t.grid_nodes,
                  t.march_persistent);
     return std::fclose(fp) == 0;
+}
+
+const FftPlans *find_fft(const matcha_ctx *ctx, int N, int P)
+{
+    for (const FftPlans &q : ctx->ffts)
+        if (q.N == N && q.P == P) return &q;
+    return nullptr;
+}
+
+// Refinement offsets per axis for an upsampling factor kappa: +-0.75 voxel around the integer peak.
+int ups_points(int kappa) { return 2 * ((3 * kappa + 3) / 4) + 1; }
+
+struct TransWs {
+    size_t vol = 0, spec = 0, spec2 = 0, ups = 0, peak = 0, work = 0, total = 0;
+};
+
+// Workspace layout of the translation calls for P volumes: rotated templates / correlations
+// [P][N^3] float, a spectrum [P][N][N][N/2+1] complex, the refinement partials [P][N][m][m] complex,
+// the integer peaks [P] int4, the FFT work area; each region 256-byte aligned.  The search also
+// keeps a second spectrum (the cross spectrum's copy that the inverse transform consumes).
+TransWs trans_ws(int N, int P, int kappa, size_t fft_work)
+{
+    TransWs w;
+    const size_t n3 = (size_t)N * N * N, nh = (size_t)N * N * (N / 2 + 1);
+    const int m = ups_points(kappa);
+    w.vol = 0;
+    w.spec = w.vol + align256(sizeof(float) * n3 * P);
+    w.spec2 = w.spec + align256(sizeof(float2) * nh * P);
+    w.ups = w.spec2 + align256(sizeof(float2) * nh * P);
+    w.peak = w.ups + align256(sizeof(float2) * (size_t)N * m * m * P);
+    w.work = w.peak + align256(sizeof(int4) * (size_t)P);
+    w.total = w.work + align256(fft_work);
+    return w;
 }
 
 const BallTables *find_ball(const matcha_ctx *ctx, int N, double lam)
@@ -1158,6 +1205,140 @@ matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const 
     }
     *best_tuning = ctx->tune;
     return st;
+}
+
+// ---- translation search (App. C) -------------------------------------------------------------
+matcha_status matcha_fft_prepare(matcha_ctx *ctx, int32_t N, int32_t n_volumes)
+{
+    if (!ctx || N < 4 || N > MATCHA_TRANSLATE_MAX_N || (N & 1) || n_volumes < 1) return MATCHA_ERR_INVALID_ARG;
+    if (find_fft(ctx, N, n_volumes)) return MATCHA_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    FftPlans q;
+    q.N = N;
+    q.P = n_volumes;
+    int n[3] = {N, N, N};
+    size_t w1 = 0, w2 = 0;
+    bool ok = hipfftCreate(&q.r2c) == HIPFFT_SUCCESS && hipfftSetAutoAllocation(q.r2c, 0) == HIPFFT_SUCCESS &&
+              hipfftMakePlanMany(q.r2c, 3, n, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_R2C, n_volumes, &w1) ==
+                  HIPFFT_SUCCESS;
+    ok = ok && hipfftCreate(&q.c2r) == HIPFFT_SUCCESS && hipfftSetAutoAllocation(q.c2r, 0) == HIPFFT_SUCCESS &&
+         hipfftMakePlanMany(q.c2r, 3, n, nullptr, 1, 0, nullptr, 1, 0, HIPFFT_C2R, n_volumes, &w2) == HIPFFT_SUCCESS;
+    if (!ok) {
+        if (q.r2c) (void)hipfftDestroy(q.r2c);
+        if (q.c2r) (void)hipfftDestroy(q.c2r);
+        return MATCHA_ERR_HIP;
+    }
+    q.work = std::max(w1, w2);
+    ctx->ffts.push_back(q);
+    return MATCHA_OK;
+}
+
+size_t matcha_translate_workspace_size(const matcha_ctx *ctx, int32_t N, int32_t n_volumes, int32_t upsample)
+{
+    if (!ctx || upsample < 1 || upsample > MATCHA_TRANSLATE_MAX_UPSAMPLE) return 0;
+    const FftPlans *q = find_fft(ctx, N, n_volumes);
+    return q ? trans_ws(N, n_volumes, upsample, q->work).total : 0;
+}
+
+namespace {
+
+// Checks shared by the translation calls; *q the prepared plans.
+matcha_status trans_check(matcha_ctx *ctx, int N, int P, void *ws, size_t ws_bytes, int kappa, const FftPlans **q)
+{
+    if (!ctx || N < 4 || N > MATCHA_TRANSLATE_MAX_N || (N & 1) || P < 0) return MATCHA_ERR_INVALID_ARG;
+    if (P == 0) return MATCHA_OK;
+    *q = find_fft(ctx, N, P);
+    if (!*q) return MATCHA_ERR_NOT_PREPARED;
+    if (!ws || !aligned16(ws) || ws_bytes < trans_ws(N, P, kappa, (*q)->work).total) return MATCHA_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MATCHA_ERR_HIP;
+    return MATCHA_OK;
+}
+
+matcha_status fft_exec(hipfftHandle plan, void *work, hipStream_t s, const void *in, void *out, bool forward)
+{
+    if (hipfftSetWorkArea(plan, work) != HIPFFT_SUCCESS || hipfftSetStream(plan, s) != HIPFFT_SUCCESS)
+        return MATCHA_ERR_HIP;
+    const hipfftResult r =
+        forward ? hipfftExecR2C(plan, static_cast<hipfftReal *>(const_cast<void *>(in)), static_cast<hipfftComplex *>(out))
+                : hipfftExecC2R(plan, static_cast<hipfftComplex *>(const_cast<void *>(in)), static_cast<hipfftReal *>(out));
+    return r == HIPFFT_SUCCESS ? MATCHA_OK : MATCHA_ERR_HIP;
+}
+
+}  // namespace
+
+matcha_status matcha_volume_spectrum(matcha_ctx *ctx, int32_t N, int32_t n_volumes, const float *vol, float *spec,
+                                     void *ws, size_t ws_bytes, void *stream)
+{
+    const FftPlans *q = nullptr;
+    if (n_volumes > 0 && (!vol || !spec || !aligned16(spec))) return MATCHA_ERR_INVALID_ARG;
+    matcha_status st = trans_check(ctx, N, n_volumes, ws, ws_bytes, 1, &q);
+    if (st != MATCHA_OK || n_volumes == 0) return st;
+    char *base = static_cast<char *>(ws);
+    return fft_exec(q->r2c, base + trans_ws(N, n_volumes, 1, q->work).work, static_cast<hipStream_t>(stream), vol, spec,
+                    true);
+}
+
+matcha_status matcha_shift_volumes(matcha_ctx *ctx, int32_t N, int32_t n_volumes, const float *spec, const float *shifts,
+                                   float *out, void *ws, size_t ws_bytes, void *stream)
+{
+    const FftPlans *q = nullptr;
+    if (n_volumes > 0 && (!spec || !shifts || !out || !aligned16(spec) || !aligned16(shifts)))
+        return MATCHA_ERR_INVALID_ARG;
+    matcha_status st = trans_check(ctx, N, n_volumes, ws, ws_bytes, 1, &q);
+    if (st != MATCHA_OK || n_volumes == 0) return st;
+    const TransWs w = trans_ws(N, n_volumes, 1, q->work);
+    char *base = static_cast<char *>(ws);
+    TransArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.N = N;
+    a.P = n_volumes;
+    a.spec_in = reinterpret_cast<const float2 *>(spec);
+    a.spec_out = reinterpret_cast<float2 *>(base + w.spec);
+    a.shift = reinterpret_cast<const float4 *>(shifts);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    st = launched(launch_phase_shift(a, s));
+    if (st != MATCHA_OK) return st;
+    return fft_exec(q->c2r, base + w.work, s, a.spec_out, out, false);
+}
+
+matcha_status matcha_translation_search(matcha_ctx *ctx, int32_t N, int32_t n_volumes, const float *spec_f,
+                                        const float *h, const float *euler, int32_t window, int32_t upsample,
+                                        float *shift_out, void *ws, size_t ws_bytes, void *stream)
+{
+    const FftPlans *q = nullptr;
+    if (n_volumes > 0 && (!spec_f || !h || !euler || !shift_out || !aligned16(spec_f) || !aligned16(euler) ||
+                          !aligned16(shift_out)))
+        return MATCHA_ERR_INVALID_ARG;
+    if (window < 0 || upsample < 1 || upsample > MATCHA_TRANSLATE_MAX_UPSAMPLE) return MATCHA_ERR_INVALID_ARG;
+    matcha_status st = trans_check(ctx, N, n_volumes, ws, ws_bytes, upsample, &q);
+    if (st != MATCHA_OK || n_volumes == 0) return st;
+    const int m = ups_points(upsample);
+    if (upsample_xy_smem(N, m) > 64 * 1024) return MATCHA_ERR_UNSUPPORTED;
+    const TransWs w = trans_ws(N, n_volumes, upsample, q->work);
+    char *base = static_cast<char *>(ws);
+    TransArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.N = N;
+    a.P = n_volumes;
+    a.h = h;
+    a.euler = reinterpret_cast<const float4 *>(euler);
+    a.vol = reinterpret_cast<float *>(base + w.vol);
+    a.spec_in = reinterpret_cast<const float2 *>(spec_f);
+    a.spec_out = reinterpret_cast<float2 *>(base + w.spec);
+    a.spec_aux = reinterpret_cast<float2 *>(base + w.spec2);
+    a.window = std::min(window, N / 2);
+    a.peak = reinterpret_cast<int4 *>(base + w.peak);
+    a.ups = reinterpret_cast<float2 *>(base + w.ups);
+    a.m = m;
+    a.kappa = upsample;
+    a.shift_out = reinterpret_cast<float4 *>(shift_out);
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    void *work = base + w.work;
+    if ((st = launched(launch_rotate_volume(a, s))) != MATCHA_OK) return st;
+    if ((st = fft_exec(q->r2c, work, s, a.vol, a.spec_out, true)) != MATCHA_OK) return st;
+    if ((st = launched(launch_cross_spectrum(a, s))) != MATCHA_OK) return st;
+    if ((st = fft_exec(q->c2r, work, s, a.spec_aux, a.vol, false)) != MATCHA_OK) return st;
+    return launched(launch_peak_refine(a, s));
 }
 
 // ---- ball-harmonic front end ----------------------------------------------------------------

@@ -131,6 +131,23 @@ struct LowRankArgs {
     int n_sv;
 };
 
+struct TransArgs {
+    int N, P;
+    const float *h;           // [N^3] template volume
+    const float4 *euler;      // [P] rotations (a, b, c, .)
+    float *vol;               // [P][N^3] real volumes (rotated templates, correlations)
+    const float2 *spec_in;    // [P][N][N][N/2+1]
+    float2 *spec_out;         // [P][N][N][N/2+1]
+    float2 *spec_aux;         // [P][N][N][N/2+1] copy of the cross spectrum for the inverse transform
+    const float4 *shift;      // [P] shifts (x, y, z, .) in voxels
+    int window;               // integer search window, |s_i| <= window
+    int4 *peak;               // [P] best integer shift
+    float2 *ups;              // [P][N][m][m] refinement partials
+    int m;                    // refinement offsets per axis
+    double kappa;             // refinement steps per voxel
+    float4 *shift_out;        // [P] refined shift (x, y, z, correlation)
+};
+
 size_t assemble_smem_bytes(int Lmax, int Rmax);
 hipError_t launch_assemble_f32(const AsmArgs &a, int P, int Lmax, int Rmax, hipStream_t s);
 // by_L[0 .. P-1] = the particle indices ordered by decreasing L_p (equal L_p in any order).
@@ -158,6 +175,11 @@ size_t grad_smem_bytes(int Lmax);
 int grad_segments(int64_t E, int P);
 hipError_t launch_grad(const GradArgs &a, hipStream_t s);
 size_t lowrank_smem_bytes(int Rmax);
+hipError_t launch_rotate_volume(const TransArgs &a, hipStream_t s);
+hipError_t launch_phase_shift(const TransArgs &a, hipStream_t s);
+hipError_t launch_cross_spectrum(const TransArgs &a, hipStream_t s);
+size_t upsample_xy_smem(int N, int m);
+hipError_t launch_peak_refine(const TransArgs &a, hipStream_t s);
 hipError_t launch_lowrank(const LowRankArgs &a, hipStream_t s);
 
 }  // namespace matcha

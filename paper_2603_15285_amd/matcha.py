@@ -28,7 +28,8 @@ EXPORTED = ["matcha_create", "matcha_destroy", "matcha_prepare", "matcha_status_
             "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch", "matcha_graph_destroy",
             "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc", "matcha_grad_workspace_size",
             "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_workspace_size", "matcha_ball_transform",
-            "matcha_lowrank_spectrum"]
+            "matcha_lowrank_spectrum", "matcha_fft_prepare", "matcha_translate_workspace_size",
+            "matcha_volume_spectrum", "matcha_shift_volumes", "matcha_translation_search"]
 NOALLOC_SCRATCH_BYTES = 128 << 20
 BALL_MAX_L, BALL_MAX_LAMBDA, BALL_MAX_N = 63, 71.0, 256
 
@@ -112,6 +113,12 @@ def lib():
         L.matcha_ball_index.argtypes = [ct.c_double, ct.POINTER(ct.c_int32), ct.POINTER(ct.c_int32), vp, vp]
         L.matcha_ball_prepare.argtypes = [vp, i32, ct.c_double]
         L.matcha_lowrank_spectrum.argtypes = [vp, bp, vp, vp, vp, ct.c_double, i32, vp, vp, vp]
+        L.matcha_fft_prepare.argtypes = [vp, i32, i32]
+        L.matcha_translate_workspace_size.argtypes = [vp, i32, i32, i32]
+        L.matcha_translate_workspace_size.restype = sz
+        L.matcha_volume_spectrum.argtypes = [vp, i32, i32, vp, vp, vp, sz, vp]
+        L.matcha_shift_volumes.argtypes = [vp, i32, i32, vp, vp, vp, vp, sz, vp]
+        L.matcha_translation_search.argtypes = [vp, i32, i32, vp, vp, vp, i32, i32, vp, vp, sz, vp]
         L.matcha_ball_workspace_size.argtypes = [vp, i32, ct.c_double, i32]
         L.matcha_ball_workspace_size.restype = sz
         L.matcha_ball_transform.argtypes = [vp, i32, ct.c_double, i32, vp, vp, vp, sz, vp]
@@ -119,7 +126,9 @@ def lib():
                      "matcha_lpt_order", "matcha_coeff_assemble", "matcha_soft_search", "matcha_march_newton",
                      "matcha_evaluate", "matcha_grad_template", "matcha_align_graph_create", "matcha_graph_launch",
                      "matcha_graph_destroy", "matcha_autotune", "matcha_c_unpack", "matcha_soft_search_noalloc",
-                     "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_transform", "matcha_lowrank_spectrum"]:
+                     "matcha_ball_index", "matcha_ball_prepare", "matcha_ball_transform", "matcha_lowrank_spectrum",
+                     "matcha_fft_prepare", "matcha_volume_spectrum", "matcha_shift_volumes",
+                     "matcha_translation_search"]:
             getattr(L, name).restype = ct.c_int
         _lib = L
     return _lib
@@ -547,6 +556,93 @@ def lowrank_spectrum(ctx: Context, batch: Batch, f: torch.Tensor, h: torch.Tenso
                                          _ptr(sv), _ptr(r_eff), ct.c_void_p(_stream(stream))),
            "matcha_lowrank_spectrum")
     return sv, r_eff
+
+
+# ------------------------------------------------------------ translations (App. C)
+def fft_prepare(ctx: Context, N: int, n: int):
+    """matcha_fft_prepare: hipFFT plans for n volumes of N^3 (synchronous, once per shape)."""
+    key = ("fft", int(N), int(n))
+    if key not in ctx._prepared:
+        _check(lib().matcha_fft_prepare(ctx.handle, int(N), int(n)), "matcha_fft_prepare")
+        ctx._prepared.add(key)
+
+
+def _trans_ws(ctx: Context, N: int, n: int, upsample: int = 1):
+    fft_prepare(ctx, N, n)
+    nb = int(lib().matcha_translate_workspace_size(ctx.handle, int(N), int(n), int(upsample)))
+    return ctx.workspace(nb), nb
+
+
+def _vols(u: torch.Tensor, name: str):
+    _need(u, torch.float32, name)
+    if u.dim() != 4 or not (u.shape[1] == u.shape[2] == u.shape[3]):
+        raise MatchaError(f"{name} must be [n, N, N, N]")
+    return int(u.shape[0]), int(u.shape[1])
+
+
+def volume_spectrum(ctx: Context, vols: torch.Tensor, stream=None) -> torch.Tensor:
+    """matcha_volume_spectrum: complex64 [n, N, N, N/2+1], the unnormalised forward transforms."""
+    n, N = _vols(vols, "vols")
+    spec = torch.empty((n, N, N, N // 2 + 1), dtype=torch.complex64, device=vols.device)
+    ws, nb = _trans_ws(ctx, N, n)
+    _check(lib().matcha_volume_spectrum(ctx.handle, N, n, _ptr(vols), _ptr(spec), _ptr(ws), nb,
+                                        ct.c_void_p(_stream(stream))), "matcha_volume_spectrum")
+    return spec
+
+
+def shift_volumes(ctx: Context, spec: torch.Tensor, shifts: torch.Tensor, stream=None) -> torch.Tensor:
+    """matcha_shift_volumes: f_p(x + s_p) from the spectra; shifts float32 [n, 4] (x, y, z, .) voxels."""
+    _need(spec, torch.complex64, "spec")
+    _need(shifts, torch.float32, "shifts")
+    n, N = int(spec.shape[0]), int(spec.shape[1])
+    out = torch.empty((n, N, N, N), dtype=torch.float32, device=spec.device)
+    ws, nb = _trans_ws(ctx, N, n)
+    _check(lib().matcha_shift_volumes(ctx.handle, N, n, _ptr(spec), _ptr(shifts), _ptr(out), _ptr(ws), nb,
+                                      ct.c_void_p(_stream(stream))), "matcha_shift_volumes")
+    return out
+
+
+def translation_search(ctx: Context, spec_f: torch.Tensor, h: torch.Tensor, euler: torch.Tensor, window: int,
+                       upsample: int = 10, stream=None) -> torch.Tensor:
+    """matcha_translation_search: float32 [n, 4] (s_x, s_y, s_z, c(s)), the shift maximising
+    sum_x f_p(x) h(R_p^T (x - s)); euler float32 [n, 4] (a, b, c, .)."""
+    _need(spec_f, torch.complex64, "spec_f")
+    _need(h, torch.float32, "h")
+    _need(euler, torch.float32, "euler")
+    n, N = int(spec_f.shape[0]), int(spec_f.shape[1])
+    out = torch.empty((n, 4), dtype=torch.float32, device=spec_f.device)
+    ws, nb = _trans_ws(ctx, N, n, upsample)
+    _check(lib().matcha_translation_search(ctx.handle, N, n, _ptr(spec_f), _ptr(h), _ptr(euler), int(window),
+                                           int(upsample), _ptr(out), _ptr(ws), nb, ct.c_void_p(_stream(stream))),
+           "matcha_translation_search")
+    return out
+
+
+def align6d(ctx: Context, f_vols: torch.Tensor, h_vol: torch.Tensor, lam: float, B: int, n_grid: int, Kc: int,
+            levels: Sequence[int], steps: int, T: int = 3, window: int | None = None, upsample: int = 10,
+            fp64_above: int = 0):
+    """Rotation-translation alternation (App. C), T rounds from zero shift: the ball transform of the
+    shifted particles f_p(x + s_p) and the path against the template's coefficients (rotations),
+    then the translation search at those rotations (shifts).  Returns (best [n, 4] rotations as the
+    march writes them, shifts [n, 4] (s, c(s)), status): f_p ~ S_s (g o h), tau = R_g^T s."""
+    n, N = _vols(f_vols, "f_vols")
+    window = N // 4 if window is None else int(window)
+    spec = volume_spectrum(ctx, f_vols)
+    hc = ball_transform(ctx, h_vol, lam)
+    K, nlm = int(hc.shape[0]), int(hc.shape[1])
+    L = int(round(nlm ** 0.5)) - 1
+    batch = Batch.make([L] * n, [K] * n, L, K)
+    h_flat = hc.contiguous().view(torch.float32).reshape(-1)
+    w = torch.ones(K, dtype=torch.float32, device=f_vols.device)
+    shifts = torch.zeros((n, 4), dtype=torch.float32, device=f_vols.device)
+    best = status = None
+    for t in range(T):
+        fs = f_vols if t == 0 else shift_volumes(ctx, spec, shifts)
+        fc = ball_transform(ctx, fs, lam)
+        best, _, status = align(ctx, batch, fc.contiguous().view(torch.float32).reshape(-1), h_flat, w, B, n_grid,
+                                Kc, levels, steps, fp64_above=fp64_above)
+        shifts = translation_search(ctx, spec, h_vol, best, window, upsample)
+    return best, shifts, status
 
 
 # ------------------------------------------------------------ ball-harmonic front end

@@ -369,7 +369,7 @@ matcha_status matcha_shift_volumes(matcha_ctx *ctx, int32_t N, int32_t n_volumes
 /* The translation step: for each volume, the shift s (|s_i| <= window for the integer search, then
  * the upsampled refinement) maximising sum_x f_p(x) h(R_p^T (x - s)); shift_out = (s_x, s_y, s_z, c(s)).
  * spec_f: the particles' spectra; h: device float32 [N^3]; euler: float4 [n] rotations.
- * MATCHA_ERR_UNSUPPORTED when the refinement's tables exceed 64 KB of LDS. */
+ * MATCHA_ERR_UNSUPPORTED when the refinement's tables exceed 64 KB of LDS or n_volumes > 65535. */
 matcha_status matcha_translation_search(matcha_ctx *ctx, int32_t N, int32_t n_volumes, const float *spec_f,
                                         const float *h, const float *euler, int32_t window, int32_t upsample,
                                         float *shift_out, void *ws, size_t ws_bytes, void *stream);

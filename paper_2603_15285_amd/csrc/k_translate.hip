@@ -9,7 +9,8 @@
 //     is F conj(U), so the inverse DFT gives c on the integer shifts (cyclic), and
 //       c(s) = (1/N^3) Re sum over the half spectrum of w_kx F conj(U)(k) e^{2 pi i k.s / N}
 //     (w = 1 for kx = 0 and N/2, 2 otherwise) evaluates it at any real s: the upsampled refinement
-//     around the best integer shift, as three separable DFT contractions (x, then y, then z).
+//     around the best integer shift, as three separable DFT contractions (x, then y, then z), on a
+//     second copy of F conj(U) (the inverse transform consumes its own).
 // The Nyquist planes of a shifted spectrum are zeroed (a real volume's Nyquist term has no
 // consistent phase at a non-integer shift).
 #include "matcha_launch.hpp"
@@ -19,45 +20,60 @@ namespace matcha {
 __device__ __forceinline__ int signed_freq(int k, int N) { return k <= N / 2 ? k : k - N; }
 
 // u_p(x) = h(R_p^T x): trilinear interpolation of the template at the rotated voxel centre, zero
-// outside the grid.  R_p = Rz(a) Ry(b) Rz(c) from euler[p] = (a, b, c, .) (float4).
+// outside the grid.  R_p = Rz(a) Ry(b) Rz(c) from euler[p] = (a, b, c, .) (float4).  Grid: voxel
+// bricks x particles.
 __global__ void __launch_bounds__(256) k_rotate_volume(TransArgs a)
 {
-    const int N = a.N;
-    const int64_t n3 = (int64_t)N * N * N, total = n3 * a.P;
-    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total; e += (int64_t)gridDim.x * 256) {
-        const int p = (int)(e / n3);
-        const int64_t v = e - (int64_t)p * n3;
-        const int iz = (int)(v / (N * N)), iy = (int)((v / N) % N), ix = (int)(v % N);
+    __shared__ float Rs[9];
+    const int N = a.N, p = blockIdx.y;
+    if (threadIdx.x == 0) {
         const float4 eu = a.euler[p];
         float sa, ca, sb, cb, sc, cc;
         sincosf(eu.x, &sa, &ca);
         sincosf(eu.y, &sb, &cb);
         sincosf(eu.z, &sc, &cc);
-        // R = Rz(a) Ry(b) Rz(c)
-        const float r00 = ca * cb * cc - sa * sc, r01 = -ca * cb * sc - sa * cc, r02 = ca * sb;
-        const float r10 = sa * cb * cc + ca * sc, r11 = -sa * cb * sc + ca * cc, r12 = sa * sb;
-        const float r20 = -sb * cc, r21 = sb * sc, r22 = cb;
-        const float h2 = 2.f / N;
-        const float x = -1.f + h2 * (ix + 0.5f), y = -1.f + h2 * (iy + 0.5f), z = -1.f + h2 * (iz + 0.5f);
-        // q = R^T x, as fractional indices
-        const float qx = r00 * x + r10 * y + r20 * z, qy = r01 * x + r11 * y + r21 * z, qz = r02 * x + r12 * y + r22 * z;
-        const float fx = (qx + 1.f) * (0.5f * N) - 0.5f, fy = (qy + 1.f) * (0.5f * N) - 0.5f, fz = (qz + 1.f) * (0.5f * N) - 0.5f;
-        const int x0 = (int)floorf(fx), y0 = (int)floorf(fy), z0 = (int)floorf(fz);
-        const float tx = fx - x0, ty = fy - y0, tz = fz - z0;
-        float acc = 0.f;
-#pragma unroll
-        for (int dz = 0; dz < 2; ++dz)
-#pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-                for (int dx = 0; dx < 2; ++dx) {
-                    const int xx = x0 + dx, yy = y0 + dy, zz = z0 + dz;
-                    if (xx < 0 || yy < 0 || zz < 0 || xx >= N || yy >= N || zz >= N) continue;
-                    const float wgt = (dx ? tx : 1.f - tx) * (dy ? ty : 1.f - ty) * (dz ? tz : 1.f - tz);
-                    acc = fmaf(wgt, a.h[((int64_t)zz * N + yy) * N + xx], acc);
-                }
-        a.vol[e] = acc;
+        // R = Rz(a) Ry(b) Rz(c), row-major
+        Rs[0] = ca * cb * cc - sa * sc;
+        Rs[1] = -ca * cb * sc - sa * cc;
+        Rs[2] = ca * sb;
+        Rs[3] = sa * cb * cc + ca * sc;
+        Rs[4] = -sa * cb * sc + ca * cc;
+        Rs[5] = sa * sb;
+        Rs[6] = -sb * cc;
+        Rs[7] = sb * sc;
+        Rs[8] = cb;
     }
+    __syncthreads();
+    // a workgroup takes an 8 x 8 x 4 brick (x, y, z) and each wave a 4 x 4 x 4 brick of it, so that
+    // the rotated footprint of a wave's gathers stays compact
+    const int n3 = N * N * N, bx = (N + 7) / 8, by = (N + 7) / 8;
+    const int b = blockIdx.x, bxi = b % bx, byi = (b / bx) % by, bzi = b / (bx * by);
+    const int t = threadIdx.x, wv = t >> 6, ln = t & 63;
+    const int ix = 8 * bxi + 4 * (wv & 1) + (ln & 3), iy = 8 * byi + 4 * (wv >> 1) + ((ln >> 2) & 3),
+              iz = 4 * bzi + (ln >> 4);
+    if (ix >= N || iy >= N || iz >= N) return;
+    const int v = (iz * N + iy) * N + ix;
+    const float h2 = 2.f / N;
+    const float x = -1.f + h2 * (ix + 0.5f), y = -1.f + h2 * (iy + 0.5f), z = -1.f + h2 * (iz + 0.5f);
+    // q = R^T x, as fractional indices
+    const float qx = Rs[0] * x + Rs[3] * y + Rs[6] * z, qy = Rs[1] * x + Rs[4] * y + Rs[7] * z,
+                qz = Rs[2] * x + Rs[5] * y + Rs[8] * z;
+    const float fx = (qx + 1.f) * (0.5f * N) - 0.5f, fy = (qy + 1.f) * (0.5f * N) - 0.5f, fz = (qz + 1.f) * (0.5f * N) - 0.5f;
+    const int x0 = (int)floorf(fx), y0 = (int)floorf(fy), z0 = (int)floorf(fz);
+    const float tx = fx - x0, ty = fy - y0, tz = fz - z0;
+    float acc = 0.f;
+#pragma unroll
+    for (int dz = 0; dz < 2; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx) {
+                const int xx = x0 + dx, yy = y0 + dy, zz = z0 + dz;
+                if (xx < 0 || yy < 0 || zz < 0 || xx >= N || yy >= N || zz >= N) continue;
+                const float wgt = (dx ? tx : 1.f - tx) * (dy ? ty : 1.f - ty) * (dz ? tz : 1.f - tz);
+                acc = fmaf(wgt, a.h[(zz * N + yy) * N + xx], acc);
+            }
+    a.vol[(int64_t)p * n3 + v] = acc;
 }
 
 // out_p(k) = in_p(k) e^{2 pi i k.s_p / N} / N^3 (so that the inverse transform gives f_p(x + s_p)),
@@ -100,25 +116,23 @@ __global__ void __launch_bounds__(256) k_cross_spectrum(TransArgs a)
 }
 
 // Best integer shift of each particle's correlation volume within |s_i| <= window (signed shifts,
-// s = i for i <= N/2 else i - N); ties go to the smaller linear index.  One workgroup per particle.
+// the volume index of s is s mod N); ties go to the smaller volume index.  One workgroup per
+// particle, over the (2 window + 1)^3 shifts only.
 __global__ void __launch_bounds__(256) k_corr_peak(TransArgs a)
 {
     __shared__ float bv[256];
     __shared__ int bi[256];
-    const int N = a.N, p = blockIdx.x;
-    const int64_t n3 = (int64_t)N * N * N;
-    const float *c = a.vol + (int64_t)p * n3;
+    const int N = a.N, p = blockIdx.x, W = a.window, span = 2 * W + 1;
+    const float *c = a.vol + (int64_t)p * N * N * N;
     float best = -INFINITY;
     int besti = 0x7fffffff;
-    for (int64_t v = threadIdx.x; v < n3; v += 256) {
-        const int iz = (int)(v / (N * N)), iy = (int)((v / N) % N), ix = (int)(v % N);
-        if (abs(signed_freq(ix, N)) > a.window || abs(signed_freq(iy, N)) > a.window ||
-            abs(signed_freq(iz, N)) > a.window)
-            continue;
+    for (int t = threadIdx.x; t < span * span * span; t += 256) {
+        const int sx = t % span - W, sy = (t / span) % span - W, sz = t / (span * span) - W;
+        const int v = (((sz + N) % N) * N + (sy + N) % N) * N + (sx + N) % N;
         const float x = c[v];
-        if (x > best || (x == best && (int)v < besti)) {
+        if (x > best || (x == best && v < besti)) {
             best = x;
-            besti = (int)v;
+            besti = v;
         }
     }
     bv[threadIdx.x] = best;
@@ -142,10 +156,30 @@ __global__ void __launch_bounds__(256) k_corr_peak(TransArgs a)
     }
 }
 
-// Upsampled refinement, stage 1 (workgroup per particle and kz): for the m x m offsets (a, b) around
-// the integer peak s0, with delta_j = (j - (m - 1) / 2) / kappa,
-//   A[ky][a] = sum_kx w_kx X[kz][ky][kx] e^{2 pi i kx (s0x + delta_a) / N}    (in LDS)
-//   B[kz][a][b] = sum_ky A[ky][a] e^{2 pi i ky' (s0y + delta_b) / N}          (to the workspace)
+// Phase tables of the refinement, once per particle (workgroup per particle), for the m offsets
+// delta_j = (j - (m - 1) / 2) / kappa around the integer peak s0:
+//   Ex[kx][j] = w_kx e^{2 pi i kx (s0x + delta_j) / N},  Ey[ky][j] = e^{2 pi i ky' (s0y + delta_j) / N}.
+__global__ void __launch_bounds__(256) k_upsample_tables(TransArgs a)
+{
+    const int N = a.N, NH = N / 2 + 1, m = a.m, p = blockIdx.x;
+    float2 *Ex = a.ups_tab + (int64_t)p * (NH + N) * m, *Ey = Ex + NH * m;
+    const int4 s0 = a.peak[p];
+    for (int i = threadIdx.x; i < (NH + N) * m; i += 256) {
+        const bool isx = i < NH * m;
+        const int r = isx ? i : i - NH * m, k = r / m, j = r - (r / m) * m;
+        const double d = (isx ? s0.x : s0.y) + (j - 0.5 * (m - 1)) / a.kappa;
+        double t = (double)(isx ? k : signed_freq(k, N)) * d / N;
+        t -= rint(t);
+        double sn, cs;
+        sincospi(2.0 * t, &sn, &cs);
+        const double w = isx ? ((k == 0 || 2 * k == N) ? 1.0 : 2.0) : 1.0;
+        (isx ? Ex : Ey)[isx ? i : r] = make_float2((float)(w * cs), (float)(w * sn));
+    }
+}
+
+// Stage 1 (workgroup per particle and kz), X = F conj(U) from the cross spectrum:
+//   A[ky][a] = sum_kx X[kz][ky][kx] Ex[kx][a]        (in LDS)
+//   B[kz][a][b] = sum_ky A[ky][a] Ey[ky][b]          (to the workspace)
 __global__ void __launch_bounds__(256) k_upsample_xy(TransArgs a)
 {
     extern __shared__ __align__(16) unsigned char ups_smem[];
@@ -154,33 +188,15 @@ __global__ void __launch_bounds__(256) k_upsample_xy(TransArgs a)
     float2 *Ex = reinterpret_cast<float2 *>(ups_smem);  // [NH][m]
     float2 *Ey = Ex + NH * m;                             // [N][m]
     float2 *A = Ey + N * m;                               // [N][m]
-    const int4 s0 = a.peak[p];
-    for (int i = threadIdx.x; i < NH * m; i += 256) {
-        const int kx = i / m, j = i - (i / m) * m;
-        const double d = s0.x + (j - 0.5 * (m - 1)) / a.kappa;
-        double t = (double)kx * d / N;
-        t -= rint(t);
-        double sn, cs;
-        sincospi(2.0 * t, &sn, &cs);
-        const double w = (kx == 0 || 2 * kx == N) ? 1.0 : 2.0;
-        Ex[i] = make_float2((float)(w * cs), (float)(w * sn));
-    }
-    for (int i = threadIdx.x; i < N * m; i += 256) {
-        const int ky = i / m, j = i - (i / m) * m;
-        const double d = s0.y + (j - 0.5 * (m - 1)) / a.kappa;
-        double t = (double)signed_freq(ky, N) * d / N;
-        t -= rint(t);
-        double sn, cs;
-        sincospi(2.0 * t, &sn, &cs);
-        Ey[i] = make_float2((float)cs, (float)sn);
-    }
+    const float2 *tab = a.ups_tab + (int64_t)p * (NH + N) * m;
+    for (int i = threadIdx.x; i < (NH + N) * m; i += 256) Ex[i] = tab[i];
     __syncthreads();
     const float2 *X = a.spec_out + ((int64_t)p * N + kz) * N * NH;
     for (int i = threadIdx.x; i < N * m; i += 256) {
         const int ky = i / m, j = i - (i / m) * m;
         float re = 0.f, im = 0.f;
         for (int kx = 0; kx < NH; ++kx) {
-            const float2 x = X[(int64_t)ky * NH + kx], e = Ex[kx * m + j];
+            const float2 x = X[ky * NH + kx], e = Ex[kx * m + j];
             re = fmaf(x.x, e.x, fmaf(-x.y, e.y, re));
             im = fmaf(x.x, e.y, fmaf(x.y, e.x, im));
         }
@@ -263,7 +279,8 @@ static unsigned grid_1d(int64_t n) { return (unsigned)std::max<int64_t>(1, std::
 
 hipError_t launch_rotate_volume(const TransArgs &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_rotate_volume, dim3(grid_1d((int64_t)a.N * a.N * a.N * a.P)), dim3(256), 0, s, a);
+    const int nb = ((a.N + 7) / 8) * ((a.N + 7) / 8) * ((a.N + 3) / 4);
+    hipLaunchKernelGGL(k_rotate_volume, dim3(nb, a.P), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -286,6 +303,9 @@ hipError_t launch_peak_refine(const TransArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_corr_peak, dim3(a.P), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_upsample_tables, dim3(a.P), dim3(256), 0, s, a);
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_upsample_xy, dim3(a.P * a.N), dim3(256), upsample_xy_smem(a.N, a.m), s, a);
     e = hipGetLastError();

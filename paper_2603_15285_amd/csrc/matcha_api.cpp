@@ -557,12 +557,13 @@ const FftPlans *find_fft(const matcha_ctx *ctx, int N, int P)
 int ups_points(int kappa) { return 2 * ((3 * kappa + 3) / 4) + 1; }
 
 struct TransWs {
-    size_t vol = 0, spec = 0, spec2 = 0, ups = 0, peak = 0, work = 0, total = 0;
+    size_t vol = 0, spec = 0, spec2 = 0, ups = 0, utab = 0, peak = 0, work = 0, total = 0;
 };
 
 // Workspace layout of the translation calls for P volumes: rotated templates / correlations
 // [P][N^3] float, a spectrum [P][N][N][N/2+1] complex, the refinement partials [P][N][m][m] complex,
-// the integer peaks [P] int4, the FFT work area; each region 256-byte aligned.  The search also
+// the refinement's phase tables [P][(N/2+1) + N][m] complex, the integer peaks [P] int4, the FFT work
+// area; each region 256-byte aligned.  The search also
 // keeps a second spectrum (the cross spectrum's copy that the inverse transform consumes).
 TransWs trans_ws(int N, int P, int kappa, size_t fft_work)
 {
@@ -573,7 +574,8 @@ TransWs trans_ws(int N, int P, int kappa, size_t fft_work)
     w.spec = w.vol + align256(sizeof(float) * n3 * P);
     w.spec2 = w.spec + align256(sizeof(float2) * nh * P);
     w.ups = w.spec2 + align256(sizeof(float2) * nh * P);
-    w.peak = w.ups + align256(sizeof(float2) * (size_t)N * m * m * P);
+    w.utab = w.ups + align256(sizeof(float2) * (size_t)N * m * m * P);
+    w.peak = w.utab + align256(sizeof(float2) * (size_t)(N / 2 + 1 + N) * m * P);
     w.work = w.peak + align256(sizeof(int4) * (size_t)P);
     w.total = w.work + align256(fft_work);
     return w;
@@ -1310,6 +1312,7 @@ matcha_status matcha_translation_search(matcha_ctx *ctx, int32_t N, int32_t n_vo
                           !aligned16(shift_out)))
         return MATCHA_ERR_INVALID_ARG;
     if (window < 0 || upsample < 1 || upsample > MATCHA_TRANSLATE_MAX_UPSAMPLE) return MATCHA_ERR_INVALID_ARG;
+    if (n_volumes > 65535) return MATCHA_ERR_UNSUPPORTED;  // one grid row per volume
     matcha_status st = trans_check(ctx, N, n_volumes, ws, ws_bytes, upsample, &q);
     if (st != MATCHA_OK || n_volumes == 0) return st;
     const int m = ups_points(upsample);
@@ -1329,6 +1332,7 @@ matcha_status matcha_translation_search(matcha_ctx *ctx, int32_t N, int32_t n_vo
     a.window = std::min(window, N / 2);
     a.peak = reinterpret_cast<int4 *>(base + w.peak);
     a.ups = reinterpret_cast<float2 *>(base + w.ups);
+    a.ups_tab = reinterpret_cast<float2 *>(base + w.utab);
     a.m = m;
     a.kappa = upsample;
     a.shift_out = reinterpret_cast<float4 *>(shift_out);

@@ -143,6 +143,7 @@ struct TransArgs {
     int window;               // integer search window, |s_i| <= window
     int4 *peak;               // [P] best integer shift
     float2 *ups;              // [P][N][m][m] refinement partials
+    float2 *ups_tab;          // [P][(N/2+1) + N][m] refinement phase tables
     int m;                    // refinement offsets per axis
     double kappa;             // refinement steps per voxel
     float4 *shift_out;        // [P] refined shift (x, y, z, correlation)

@@ -138,6 +138,24 @@ def check_soft(b, p, cand, status, B, n, Kc):
     assert bool(status & 16) == (nmx < Kc)
 
 
+@pytest.mark.parametrize("name,P", [("smoke_L16", 3), ("L32_R32_B12_K16", 2)])
+def test_soft_grid_every_node_matches_oracle(M, ctx, name, P):
+    """Every node of the SOFFT grid (Wigner-d transform then 2-D DFT, the intermediate the search
+    ranks), read back from the search's workspace ([particle][b_i][a_j][c_k] floats at its head),
+    against the oracle's grid by direct evaluation of C_B at each node: |dC| <= 1e-5 S."""
+    wl = S.WORKLOADS[name]
+    b = S.make_workload(name, n_particles=P)
+    batch, f, h, w = upload(M, b)
+    C = M.coeff_assemble(ctx, batch, f, h, w)
+    M.soft_search(ctx, batch, C, wl.B, wl.n_grid, wl.Kc)
+    torch.cuda.synchronize()
+    n = wl.n_grid
+    grid = ctx._ws[: P * n ** 3 * 4].view(torch.float32).reshape(P, n, n, n).cpu().numpy()
+    for p in range(P):
+        ref = O.soft_grid(wl.B, oracle_C(b, p), n)
+        assert np.abs(grid[p] - ref).max() <= 1e-5 * scale(b, p, wl.B), p
+
+
 @pytest.mark.parametrize("name", ["smoke_L16", "L32_R32_B12_K16"])
 def test_soft_search_matches_oracle(M, ctx, name):
     wl = S.WORKLOADS[name]

@@ -28,6 +28,7 @@
 #include <algorithm>
 #include <cmath>
 #include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "matcha_ball.hpp"
@@ -343,6 +344,8 @@ __global__ void __launch_bounds__(kBallThreads) k_ball_gemm(BallGemmArgs a)
     };
     const int wave = t / kWave, lane = t % kWave, li = lane % 16, kq = lane / 16;
     const int wr = (TM / 2) * (wave / 2), wc = 64 * (wave % 2);
+    // this wave's 16-column tiles that hold columns of the class (wave-uniform)
+    const int ntj = min(4, max(0, (ncls - c0 - wc + 15) / 16));
     f32x4 acc[RT][4];
 #pragma unroll
     for (int i = 0; i < RT; ++i)
@@ -356,21 +359,32 @@ __global__ void __launch_bounds__(kBallThreads) k_ball_gemm(BallGemmArgs a)
     for (int ch = 0; ch < nch; ++ch) {
         const int buf = ch & 1;
         if (ch + 1 < nch) load(ch + 1);
+        // a wave whose 16-column tiles all hold columns of the class runs them unchecked; the last
+        // tile of a class skips the products of its tiles past the class's last column
+        auto products = [&](auto full) {
 #pragma unroll
-        for (int g = 0; g < kBallChunk / 16; ++g) {
-            f32x4 av[RT], bv[4];
-#pragma unroll
-            for (int i = 0; i < RT; ++i) av[i] = *reinterpret_cast<const f32x4 *>(&As[buf][wr + 16 * i + li][16 * g + 4 * kq]);
-#pragma unroll
-            for (int j = 0; j < 4; ++j) bv[j] = *reinterpret_cast<const f32x4 *>(&Bs[buf][wc + 16 * j + li][16 * g + 4 * kq]);
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
+            for (int g = 0; g < kBallChunk / 16; ++g) {
+                f32x4 av[RT], bv[4];
 #pragma unroll
                 for (int i = 0; i < RT; ++i)
+                    av[i] = *reinterpret_cast<const f32x4 *>(&As[buf][wr + 16 * i + li][16 * g + 4 * kq]);
 #pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
-        }
+                for (int j = 0; j < 4; ++j)
+                    bv[j] = *reinterpret_cast<const f32x4 *>(&Bs[buf][wc + 16 * j + li][16 * g + 4 * kq]);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int i = 0; i < RT; ++i)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (decltype(full)::value || j < ntj)
+                                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[i][s], bv[j][s], acc[i][j], 0, 0, 0);
+            }
+        };
+        if (ntj == 4)
+            products(std::true_type{});
+        else
+            products(std::false_type{});
         if (ch + 1 < nch) store(buf ^ 1);
         __syncthreads();
     }
@@ -413,7 +427,7 @@ int ball_splits(int P, int ncol_tiles, int64_t Vo_pad, int n_cu)
 {
     const int tm = ball_tile_m(P);
     const int64_t tiles = (int64_t)((P + tm - 1) / tm) * ncol_tiles;
-    const int64_t want = std::max<int64_t>(1, (4LL * n_cu + tiles - 1) / tiles);  // about 4 workgroups per CU
+    const int64_t want = std::max<int64_t>(1, (8LL * n_cu + tiles - 1) / tiles);  // about 8 workgroups per CU
     const int64_t max_s = std::max<int64_t>(1, Vo_pad / (8 * kBallChunk));           // at least 8 chunks each
     return (int)std::min<int64_t>(std::min<int64_t>(want, max_s), kBallMaxSplits);
 }

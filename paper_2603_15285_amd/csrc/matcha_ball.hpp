@@ -62,7 +62,7 @@ struct BallScatterArgs {
 
 // Volumes per row tile of the product for P volumes (64 or 128).
 int ball_tile_m(int P);
-// K splits for P volumes: about four workgroups per compute unit, at least 8 chunks per split.
+// K splits for P volumes: about eight workgroups per compute unit, at least 8 chunks per split.
 int ball_splits(int P, int ncol_tiles, int64_t Vo_pad, int n_cu);
 // 128-column tiles over the classes; tile_lo (optional, 9 entries) = first tile of each class.
 int ball_col_tiles(const int *col_off, int *tile_lo);

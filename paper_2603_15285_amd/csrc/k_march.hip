@@ -565,6 +565,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))
         const float4 *Cl = j + 1 < ns ? Cp : Cf;
         if (lane < NC) st.frozen[lane] = 0;
         for (int s = 0; s < a.steps; ++s) {
+            if (a.early_stop) {
+                // every candidate of the wave has stopped at this level: its later steps change nothing
+                int all = 1;
+#pragma unroll
+                for (int c = 0; c < NC; ++c) all &= st.frozen[c];
+                if (__builtin_amdgcn_readfirstlane(all)) break;
+            }
             prepare_step<NC, true>(st, ws, L, lane);
             eval_level_any<NC, true, F64>(Cl, a.tab, a.tab64, a.pinfo, L, a.fp64_above, st.bc, ws, acc, lane);
             wave_reduce<NC, 10>(acc, st, lane);

@@ -18,6 +18,8 @@
 
 #include "matcha_launch.hpp"
 
+#include <type_traits>
+
 namespace matcha {
 
 
@@ -172,6 +174,21 @@ struct Coef<double> {
     }
 };
 
+// f(integral_constant<int, B>), ..., f(integral_constant<int, E - 1>), unrolled at compile time.
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
+
+// Rows in flight in the value-only evaluation.  Its row costs a quarter of a derivative row's
+// arithmetic, so two rows in flight (the derivative evaluation's depth) leave it waiting on the
+// loads; the registers that the derivative state would hold carry the deeper prefetch.
+constexpr int kValueDepth = 8;
+
 template <typename T>
 __device__ inline void seed_T(int m, int n, double lbh2, const BetaConst &k, T &d0, T &d1, T &d2);
 template <>
@@ -239,14 +256,32 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         // same array) and past row L (row L is re-read, never used), so no load needs a branch.
         int l = mlo;
         int row = (int)wedge_row(mlo);
-        float4 tb0 = ld_row(tab, row, lb), cc0 = ld_row(Cp, row, lb);
+        float4 tb0, cc0, tb1, cc1;
         T A0, AC0, A1, AC1;
-        Coef<T>::get(tb0, tab64, row, lb, A0, AC0);
-        row += (l + 1) * (l + 1);
-        int r1 = min(row, rowL);
-        float4 tb1 = ld_row(tab, r1, lb), cc1 = ld_row(Cp, r1, lb);
-        Coef<T>::get(tb1, tab64, r1, lb, A1, AC1);
-        row += (l + 2) * (l + 2);
+        int r1;
+        float4 tbk[kValueDepth], cck[kValueDepth];
+        T Ak[kValueDepth], ACk[kValueDepth];
+        if constexpr (DERIV) {
+            tb0 = ld_row(tab, row, lb);
+            cc0 = ld_row(Cp, row, lb);
+            Coef<T>::get(tb0, tab64, row, lb, A0, AC0);
+            row += (l + 1) * (l + 1);
+            r1 = min(row, rowL);
+            tb1 = ld_row(tab, r1, lb);
+            cc1 = ld_row(Cp, r1, lb);
+            Coef<T>::get(tb1, tab64, r1, lb, A1, AC1);
+            row += (l + 2) * (l + 2);
+        } else {
+            // rows mlo .. mlo + depth - 1 (clamped to row L) in flight before the first is used
+            static_for<0, kValueDepth>([&](auto jc) {
+                constexpr int J = decltype(jc)::value;
+                const int r = min(row, rowL);
+                tbk[J] = ld_row(tab, r, lb);
+                cck[J] = ld_row(Cp, r, lb);
+                Coef<T>::get(tbk[J], tab64, r, lb, Ak[J], ACk[J]);
+                row += (l + J + 1) * (l + J + 1);
+            });
+        }
 
         // edge values of every lane's pair, computed once per tile without divergence
         T sd0[NC], sd1[NC], sd2[NC];
@@ -284,26 +319,67 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         row += (l + 4) * (l + 4);                                                                        \
         __builtin_amdgcn_sched_barrier(0);                                                               \
     } while (0)
-        // rows where pairs of the tile start (mlo .. mhi, rounded up to an even count, at most L)
-        const int lseed = min(mhi + ((mhi - mlo) & 1 ? 0 : 1), L);
-        MARCH_ROW0(true, 1);
-        MARCH_LOAD0();
-        if (l < L) MARCH_ROW1(true, 2);
-        MARCH_LOAD1();
-        for (l += 2; l <= lseed; l += 2) {
-            MARCH_ROW0(true, 0);
+        if constexpr (DERIV) {
+            // rows where pairs of the tile start (mlo .. mhi, rounded up to an even count, at most L)
+            const int lseed = min(mhi + ((mhi - mlo) & 1 ? 0 : 1), L);
+            MARCH_ROW0(true, 1);
             MARCH_LOAD0();
-            if (l < L) MARCH_ROW1(true, 0);
+            if (l < L) MARCH_ROW1(true, 2);
             MARCH_LOAD1();
+            for (l += 2; l <= lseed; l += 2) {
+                MARCH_ROW0(true, 0);
+                MARCH_LOAD0();
+                if (l < L) MARCH_ROW1(true, 0);
+                MARCH_LOAD1();
+            }
+            // rows where every pair of the tile has started
+            for (; l + 1 <= L; l += 2) {
+                MARCH_ROW0(false, 0);
+                MARCH_LOAD0();
+                MARCH_ROW1(false, 0);
+                MARCH_LOAD1();
+            }
+            if (l <= L) MARCH_ROW0(false, 0);
+        } else {
+            // Trips of kValueDepth rows l .. l + depth - 1: row l + J comes from set J, which then
+            // takes row l + J + depth (clamped to row L, never used past it).  The state alternates
+            // between D and Dm with the row's parity (the depth is even).  GUARD: rows past L are
+            // skipped (the loads are not, so none sits behind a branch).
+            auto trip = [&](auto seed_c, auto first_c, auto guard_c) {
+                constexpr bool SEEDR = decltype(seed_c)::value;
+                constexpr bool FIRSTT = decltype(first_c)::value;
+                constexpr bool GUARD = decltype(guard_c)::value;
+                static_for<0, kValueDepth>([&](auto jc) {
+                    constexpr int J = decltype(jc)::value;
+                    constexpr int FST = FIRSTT ? (J == 0 ? 1 : J == 1 ? 2 : 0) : 0;
+                    const int lr = l + J;
+                    if (!GUARD || lr <= L) {
+                        if constexpr (J % 2 == 0)
+                            row_step<NC, false, SEEDR, T, FST>(Ak[J], ACk[J], tbk[J], cck[J], m == lr, sd0, sd1, sd2,
+                                                               cbv, sbv, chv, D, Dm, D1, D1m, D2, D2m, U);
+                        else
+                            row_step<NC, false, SEEDR, T, FST>(Ak[J], ACk[J], tbk[J], cck[J], m == lr, sd0, sd1, sd2,
+                                                               cbv, sbv, chv, Dm, D, D1m, D1, D2m, D2, U);
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+                    const int r = min(row, rowL);
+                    tbk[J] = ld_row(tab, r, lb);
+                    cck[J] = ld_row(Cp, r, lb);
+                    Coef<T>::get(tbk[J], tab64, r, lb, Ak[J], ACk[J]);
+                    row += (lr + kValueDepth + 1) * (lr + kValueDepth + 1);
+                    __builtin_amdgcn_sched_barrier(0);
+                });
+                l += kValueDepth;
+            };
+            using yes = std::true_type;
+            using no = std::false_type;
+            // the first trip holds row mlo (FIRST) and the rows where pairs start up to mhi
+            trip(yes{}, yes{}, yes{});
+            while (l <= mhi) trip(yes{}, no{}, yes{});
+            // rows where every pair of the tile has started
+            while (l + kValueDepth - 1 <= L) trip(no{}, no{}, no{});
+            if (l <= L) trip(no{}, no{}, yes{});
         }
-        // rows where every pair of the tile has started
-        for (; l + 1 <= L; l += 2) {
-            MARCH_ROW0(false, 0);
-            MARCH_LOAD0();
-            MARCH_ROW1(false, 0);
-            MARCH_LOAD1();
-        }
-        if (l <= L) MARCH_ROW0(false, 0);
 #undef MARCH_ROW0
 #undef MARCH_ROW1
 #undef MARCH_LOAD0

@@ -411,13 +411,28 @@ __global__ void __launch_bounds__(256) k_ball_scatter(BallScatterArgs a)
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < n; e += (int64_t)gridDim.x * 256) {
         const int p = (int)(e / a.n_entries);
         const BallMapEntry m = a.map[e - (int64_t)p * a.n_entries];
-        float re = 0.f, im = 0.f;
-        for (int z = 0; z < a.S; ++z) {
-            const float *pz = a.part + ((int64_t)z * a.P + p) * a.ncol;
-            if (m.col_re >= 0) re += pz[m.col_re];
-            if (m.col_im >= 0) im += pz[m.col_im];
+        // unconditional loads (column 0 stands in for a missing column, masked afterwards), so that
+        // the partials' loads are all in flight together rather than one behind each branch
+        const int cre = max(m.col_re, 0), cim = max(m.col_im, 0);
+        const float *pz = a.part + (int64_t)p * a.ncol;
+        const int64_t zs = (int64_t)a.P * a.ncol;
+        float vr[kBallMaxSplits], vi[kBallMaxSplits];
+#pragma unroll
+        for (int z = 0; z < kBallMaxSplits; ++z) {
+            const int64_t o = (int64_t)min(z, a.S - 1) * zs;  // splits past S re-read the last one
+            vr[z] = pz[o + cre];
+            vi[z] = pz[o + cim];
         }
-        reinterpret_cast<float2 *>(a.out)[e] = make_float2(m.s_re * re, m.s_im * im);
+        float re = 0.f, im = 0.f;
+#pragma unroll
+        for (int z = 0; z < kBallMaxSplits; ++z)
+            if (z < a.S) {
+                re += vr[z];
+                im += vi[z];
+            }
+        re = m.col_re >= 0 ? m.s_re * re : 0.f;
+        im = m.col_im >= 0 ? m.s_im * im : 0.f;
+        reinterpret_cast<float2 *>(a.out)[e] = make_float2(re, im);
     }
 }
 

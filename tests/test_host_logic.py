@@ -173,3 +173,17 @@ def test_ball_index_matches_the_oracle_and_rejects_bad_cutoffs():
     for lam in (0.0, -1.0, 3.0, 71.5, float("nan")):
         assert M.lib().matcha_ball_index(lam, ct.byref(L), ct.byref(K), None, None) == M.ERR_INVALID_ARG
     assert M.lib().matcha_ball_index(9.0, None, ct.byref(K), None, None) == M.ERR_INVALID_ARG
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and says why, before any GPU work."""
+    import os
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True, text=True,
+                       timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""

@@ -153,3 +153,22 @@ def test_lowrank_edges(M, ctx):
                               [np.zeros_like(h[:8])])
     sv, reff = M.lowrank_spectrum(ctx, batch, f, hh, ww)
     assert torch.all(sv == 0) and torch.all(reff == 0)
+
+
+def test_maximum_shell_count_matches_oracle(M, ctx):
+    """MATCHA_LOWRANK_MAX_SHELLS = 48 shells (the kernel's LDS then holds three 48 x 48 complex
+    FP64 matrices, 110.6 KB) at degrees up to 30, where 2l + 1 crosses the shell count: ranks are
+    min(2l + 1, 48) for generic inputs."""
+    rng = np.random.default_rng(48)
+    Lh, Rh = 30, 48
+    var = 1.0 / (1.0 + np.arange(Lh + 1))
+    h = S.hermitian_gaussian(rng, Rh, Lh, var)
+    w = 1.0 + rng.uniform(0.0, 1.0, Rh)
+    L = np.array([30, 12])
+    R = np.array([48, 48])
+    f_parts = [S.hermitian_gaussian(rng, int(r), int(l), var[: l + 1]) for l, r in zip(L, R)]
+    b = dict(L=L, R=R, Lh=Lh, Rh=Rh, h=h, w=w)
+    batch, f, hh, ww = upload(M, b, f_parts)
+    sv, reff = M.lowrank_spectrum(ctx, batch, f, hh, ww, rho=0.2, n_sv=64)
+    sv, reff = sv.cpu().numpy(), reff.cpu().numpy()
+    check(sv, reff, f_parts, b)

@@ -144,6 +144,7 @@ __device__ __forceinline__ void wigner_sums(const float4 *__restrict__ Cp, const
 // threads on consecutive pairs, so the node tables are read coalesced.  The entries (0, n < 0),
 // the Hermitian mirrors of (0, -n), are written as zero by the (0, 0) pair's task.
 constexpr int kWignerThreads = 256;
+constexpr int kWignerStage = 4;  // polar nodes staged in LDS at a time
 
 template <bool CP_LDS>
 __global__ void __launch_bounds__(kWignerThreads) k_soft_wigner(SoftArgs a)
@@ -161,14 +162,44 @@ __global__ void __launch_bounds__(kWignerThreads) k_soft_wigner(SoftArgs a)
         Cp = cs;
     }
     const int64_t drow = wedge_row(B + 1);
-    float2 *Sp = a.S + (int64_t)pl * N * (B + 1) * W;
+    const int SW = (B + 1) * W;
+    float2 *Sp = a.S + (int64_t)pl * N * SW;
+    if (CP_LDS) {
+        // kWignerStage nodes at a time into LDS (every entry of a node's array is written: the
+        // partners fill the entries past the wedge), then out as one contiguous run, so the
+        // partners' transposed positions never reach memory as scattered 8-byte writes
+        float2 *sb = reinterpret_cast<float2 *>(cs + wedge_row(B + 1));
+        for (int i0 = 0; i0 < N; i0 += kWignerStage) {
+            const int g = min(kWignerStage, N - i0);
+            for (int t = threadIdx.x; t < g * npairs; t += kWignerThreads) {
+                const int il = t / npairs, q = t - (t / npairs) * npairs;
+                const PairInfo pi = a.pinfo[q];
+                const int m = pi.m, n = pi.n;
+                float2 u0, u1;
+                wigner_sums(Cp, a.dgrid + (i0 + il) * drow, m, q, B, u0, u1);
+                float2 *S = sb + il * SW;
+                S[m * W + n + B] = u0;
+                if (n != m && n != -m) {  // diagonal pairs are their own partners
+                    const int a2 = n >= 0 ? n : -n, b2 = n >= 0 ? m : -m;
+                    S[a2 * W + b2 + B] = u1;
+                }
+                if (q == 0)
+                    for (int k = 0; k < B; ++k) S[k] = make_float2(0.f, 0.f);
+            }
+            __syncthreads();
+            float2 *dst = Sp + (int64_t)i0 * SW;
+            for (int t = threadIdx.x; t < g * SW; t += kWignerThreads) dst[t] = sb[t];
+            __syncthreads();
+        }
+        return;
+    }
     for (int t = threadIdx.x; t < N * npairs; t += kWignerThreads) {
         const int i = t / npairs, q = t - (t / npairs) * npairs;
         const PairInfo pi = a.pinfo[q];
         const int m = pi.m, n = pi.n;
         float2 u0, u1;
         wigner_sums(Cp, a.dgrid + i * drow, m, q, B, u0, u1);
-        float2 *S = Sp + (int64_t)i * (B + 1) * W;
+        float2 *S = Sp + (int64_t)i * SW;
         S[m * W + n + B] = u0;
         if (n != m && n != -m) {  // diagonal pairs are their own partners
             const int a2 = n >= 0 ? n : -n, b2 = n >= 0 ? m : -m;
@@ -179,7 +210,11 @@ __global__ void __launch_bounds__(kWignerThreads) k_soft_wigner(SoftArgs a)
     }
 }
 
-inline bool soft_wigner_cp_lds(int B) { return wedge_row(B + 1) * sizeof(float4) <= 64 * 1024; }
+inline size_t soft_wigner_smem(int B)
+{
+    return wedge_row(B + 1) * sizeof(float4) + sizeof(float2) * kWignerStage * (size_t)(B + 1) * (2 * B + 1);
+}
+inline bool soft_wigner_cp_lds(int B) { return soft_wigner_smem(B) <= 64 * 1024; }
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 constexpr int kGridChunk = 8;  // K steps whose operands are loaded before their MFMAs
@@ -1022,8 +1057,7 @@ size_t soft_select_smem_bytes(int n, int threads)
 hipError_t launch_soft_wigner(const SoftArgs &a, int P, hipStream_t s)
 {
     if (soft_wigner_cp_lds(a.B))
-        hipLaunchKernelGGL(k_soft_wigner<true>, dim3(P), dim3(kWignerThreads), wedge_row(a.B + 1) * sizeof(float4), s,
-                           a);
+        hipLaunchKernelGGL(k_soft_wigner<true>, dim3(P), dim3(kWignerThreads), soft_wigner_smem(a.B), s, a);
     else
         hipLaunchKernelGGL(k_soft_wigner<false>, dim3(P), dim3(kWignerThreads), 0, s, a);
     return hipGetLastError();

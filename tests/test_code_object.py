@@ -19,7 +19,7 @@ LIB = os.path.join(ROOT, "paper_2603_15285_amd", "libmatcha.so")
 LLVM = "/opt/rocm/llvm/bin"
 MAGIC = b"__CLANG_OFFLOAD_BUNDLE__"
 KERNELS = {"k_assemble_f32", "k_assemble_bf16", "k_soft_grid", "k_soft_maxima", "k_soft_rank", "k_march",
-           "k_evaluate", "k_grad_particle", "k_grad_reduce", "k_ball_sym", "k_ball_gemm", "k_ball_scatter", "k_lowrank_sv",
+           "k_evaluate", "k_grad_particle", "k_grad_reduce", "k_ball_sym", "k_ball_gemm", "k_ball_scatter", "k_ball_scatter_vol", "k_lowrank_sv",
            "k_rotate_volume", "k_phase_shift", "k_cross_spectrum", "k_corr_peak", "k_upsample_tables", "k_upsample_xy", "k_upsample_z"}
 
 

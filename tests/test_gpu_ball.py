@@ -90,6 +90,7 @@ def check_against_oracle(got, u, lam):
     (20, 14.0, 130),  # three 64-volume row tiles, the last ragged; ragged column tiles in every class
     (31, 20.0, 2),    # odd, several K splits over the octant voxels, partial last chunk
     (12, 9.0, 300),   # 128-volume row tiles (from 256 volumes on), the last one ragged
+    (14, 9.0, 600),   # from 512 volumes on the partial sums are reduced per volume through LDS
 ])
 def test_ball_transform_matches_oracle(M, ctx, N, lam, P):
     rng = np.random.default_rng(1000 + N)
@@ -97,7 +98,7 @@ def test_ball_transform_matches_oracle(M, ctx, N, lam, P):
     print(f"ball N={N} lam={lam} P={P}", flush=True)
     got = M.ball_transform(ctx, torch.from_numpy(u).cuda(), lam).cpu().numpy()
     # every volume of small batches; the first, last and tile-edge volumes of the large one
-    sample = range(P) if P <= 40 else sorted({0, 1, 63, 64, 127, 128, 255, 256, P - 2, P - 1} & set(range(P)))
+    sample = range(P) if P <= 40 else sorted({0, 1, 63, 64, 127, 128, 255, 256, 511, 512, P - 2, P - 1} & set(range(P)))
     for p in sample:
         check_against_oracle(got[p], u[p], lam)
 

@@ -98,7 +98,7 @@ typedef enum {
 #define MATCHA_ST_FEW_MAXIMA 16u /* the SOFFT grid had fewer than Kc local maxima         */
 #define MATCHA_ST_EARLY_STOP 32u /* early stopping ended a level before M_iter steps      */
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define MATCHA_MAX_L 64
 #define MATCHA_MAX_KC 64
 #define MATCHA_MAX_LEVELS 16

@@ -238,6 +238,25 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
     const int rowL = (int)wedge_row(L);
     // each tile loads the next tile's pairs while it runs
     PairInfo pn = pinfo[min(lane, npairs - 1)];
+    // Derivative evaluation: a tile's first two rows are loaded before the previous tile's phase
+    // and weighting work, so that work covers their latency (the recurrence state is dead by then,
+    // so the loads take no extra registers).  ml: the tile's smallest m; lbx: the lane's offset.
+    float4 tb0, cc0, tb1, cc1;
+    T A0, AC0, A1, AC1;
+    int row_next = 0;
+    auto first_rows = [&](int ml, uint32_t lbx) {
+        int rw = (int)wedge_row(ml);
+        tb0 = ld_row(tab, rw, lbx);
+        cc0 = ld_row(Cp, rw, lbx);
+        Coef<T>::get(tb0, tab64, rw, lbx, A0, AC0);
+        rw += (ml + 1) * (ml + 1);
+        const int rr = min(rw, rowL);
+        tb1 = ld_row(tab, rr, lbx);
+        cc1 = ld_row(Cp, rr, lbx);
+        Coef<T>::get(tb1, tab64, rr, lbx, A1, AC1);
+        row_next = rw + (ml + 2) * (ml + 2);
+    };
+    if constexpr (DERIV) first_rows(__builtin_amdgcn_readfirstlane(pn.m), (uint32_t)min(lane, npairs - 1) * 16u);
     for (int t = 0; t < ntiles; ++t) {
         const int q0 = t * kWave;
         const int q = q0 + lane;
@@ -256,21 +275,11 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         // same array) and past row L (row L is re-read, never used), so no load needs a branch.
         int l = mlo;
         int row = (int)wedge_row(mlo);
-        float4 tb0, cc0, tb1, cc1;
-        T A0, AC0, A1, AC1;
         int r1;
         float4 tbk[kValueDepth], cck[kValueDepth];
         T Ak[kValueDepth], ACk[kValueDepth];
         if constexpr (DERIV) {
-            tb0 = ld_row(tab, row, lb);
-            cc0 = ld_row(Cp, row, lb);
-            Coef<T>::get(tb0, tab64, row, lb, A0, AC0);
-            row += (l + 1) * (l + 1);
-            r1 = min(row, rowL);
-            tb1 = ld_row(tab, r1, lb);
-            cc1 = ld_row(Cp, r1, lb);
-            Coef<T>::get(tb1, tab64, r1, lb, A1, AC1);
-            row += (l + 2) * (l + 2);
+            row = row_next;  // rows mlo and mlo + 1 are in flight since the previous tile
         } else {
             // rows mlo .. mlo + depth - 1 (clamped to row L) in flight before the first is used
             static_for<0, kValueDepth>([&](auto jc) {
@@ -384,6 +393,10 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
 #undef MARCH_ROW1
 #undef MARCH_LOAD0
 #undef MARCH_LOAD1
+        if constexpr (DERIV) {
+            if (t + 1 < ntiles)  // the next tile's first rows, before this tile's phase work
+                first_rows(__builtin_amdgcn_readfirstlane(pn.m), (uint32_t)min(q + kWave, npairs - 1) * 16u);
+        }
         if (!valid) continue;
         // phases and the m, n weights of the a / c derivatives
         const int an = n >= 0 ? n : -n, b2i = n >= 0 ? m : -m;

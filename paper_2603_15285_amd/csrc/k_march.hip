@@ -256,7 +256,26 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         Coef<T>::get(tb1, tab64, rr, lbx, A1, AC1);
         row_next = rw + (ml + 2) * (ml + 2);
     };
-    if constexpr (DERIV) first_rows(__builtin_amdgcn_readfirstlane(pn.m), (uint32_t)min(lane, npairs - 1) * 16u);
+    // Value-only evaluation: likewise, a tile's first kValueDepth rows are loaded before the previous
+    // tile's phase work.
+    float4 tbk[kValueDepth], cck[kValueDepth];
+    T Ak[kValueDepth], ACk[kValueDepth];
+    auto first_rows_v = [&](int ml, uint32_t lbx) {
+        int rw = (int)wedge_row(ml);
+        static_for<0, kValueDepth>([&](auto jc) {
+            constexpr int J = decltype(jc)::value;
+            const int r = min(rw, rowL);
+            tbk[J] = ld_row(tab, r, lbx);
+            cck[J] = ld_row(Cp, r, lbx);
+            Coef<T>::get(tbk[J], tab64, r, lbx, Ak[J], ACk[J]);
+            rw += (ml + J + 1) * (ml + J + 1);
+        });
+        row_next = rw;
+    };
+    if constexpr (DERIV)
+        first_rows(__builtin_amdgcn_readfirstlane(pn.m), (uint32_t)min(lane, npairs - 1) * 16u);
+    else
+        first_rows_v(__builtin_amdgcn_readfirstlane(pn.m), (uint32_t)min(lane, npairs - 1) * 16u);
     for (int t = 0; t < ntiles; ++t) {
         const int q0 = t * kWave;
         const int q = q0 + lane;
@@ -276,21 +295,9 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
         int l = mlo;
         int row = (int)wedge_row(mlo);
         int r1;
-        float4 tbk[kValueDepth], cck[kValueDepth];
-        T Ak[kValueDepth], ACk[kValueDepth];
-        if constexpr (DERIV) {
-            row = row_next;  // rows mlo and mlo + 1 are in flight since the previous tile
-        } else {
-            // rows mlo .. mlo + depth - 1 (clamped to row L) in flight before the first is used
-            static_for<0, kValueDepth>([&](auto jc) {
-                constexpr int J = decltype(jc)::value;
-                const int r = min(row, rowL);
-                tbk[J] = ld_row(tab, r, lb);
-                cck[J] = ld_row(Cp, r, lb);
-                Coef<T>::get(tbk[J], tab64, r, lb, Ak[J], ACk[J]);
-                row += (l + J + 1) * (l + J + 1);
-            });
-        }
+        // the tile's first rows (two, or kValueDepth for the value only) are in flight since the
+        // previous tile
+        row = row_next;
 
         // edge values of every lane's pair, computed once per tile without divergence
         T sd0[NC], sd1[NC], sd2[NC];
@@ -393,9 +400,11 @@ __device__ void eval_level(const float4 *__restrict__ Cp, const float4 *__restri
 #undef MARCH_ROW1
 #undef MARCH_LOAD0
 #undef MARCH_LOAD1
-        if constexpr (DERIV) {
-            if (t + 1 < ntiles)  // the next tile's first rows, before this tile's phase work
+        if (t + 1 < ntiles) {  // the next tile's first rows, before this tile's phase work
+            if constexpr (DERIV)
                 first_rows(__builtin_amdgcn_readfirstlane(pn.m), (uint32_t)min(q + kWave, npairs - 1) * 16u);
+            else
+                first_rows_v(__builtin_amdgcn_readfirstlane(pn.m), (uint32_t)min(q + kWave, npairs - 1) * 16u);
         }
         if (!valid) continue;
         // phases and the m, n weights of the a / c derivatives

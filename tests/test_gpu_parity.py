@@ -322,6 +322,35 @@ def test_march_from_oracle_candidates(M, ctx):
             assert rot_err(best[p, :3].astype(np.float64), oc[ob, :3]) <= 1e-3
 
 
+def test_march_single_tile_levels(M, ctx):
+    """Levels of at most 64 wedge pairs (L <= 7: one tile, its lanes partly past the last pair),
+    where the march's look-ahead of the next tile's rows never fires: the same bar as above."""
+    Lmax, B, n, Kc, levels, steps = 6, 3, 12, 8, (3, 6), 2
+    b = S.make_batch(Lmax, 6, 3, seed=77, snr=1.0)
+    batch, f, h, w = upload(M, b)
+    C = M.coeff_assemble(ctx, batch, f, h, w)
+    start = np.zeros((3, Kc, 4), dtype=np.float32)
+    for p in range(3):
+        grid = O.soft_grid(B, oracle_C(b, p), n)
+        idx, val, _ = O.soft_select(grid, Kc)
+        start[p, :, :3] = O.grid_euler(idx, n)
+        start[p, :, 3] = val
+    cand = torch.from_numpy(start).cuda()
+    status = torch.zeros(3, dtype=torch.int32).cuda()
+    best, best_idx, status = M.march_newton(ctx, batch, C, levels, steps, cand, status)
+    cand, best, best_idx = cand.cpu().numpy(), best.cpu().numpy(), best_idx.cpu().numpy()
+    for p in range(3):
+        oc, ob, ost = O.march(Lmax, oracle_C(b, p), list(levels), steps, start[p].astype(np.float64))
+        Sc = scale(b, p, Lmax)
+        clean = (ost & (O.INDEFINITE | O.SINGULAR | O.NEAR_POLE | O.NONFINITE)) == 0
+        err = rot_err(cand[p, :, :3].astype(np.float64), oc[:, :3])
+        assert np.all(err[clean] <= 1e-3), err[clean]
+        assert np.all(np.abs(cand[p, clean, 3] - oc[clean, 3]) <= 1e-5 * Sc)
+        top = np.sort(oc[:, 3])[::-1]
+        if top[0] - top[1] > 1e-5 * Sc:
+            assert best_idx[p] == ob
+
+
 @pytest.mark.parametrize("rate", [2.0, 10.0])
 def test_gradient_ascent_march_matches_oracle(M, ctx, rate):
     """The first-order comparator (gd_rate > 0) from the oracle's SOFFT candidates, 6 steps per

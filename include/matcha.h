@@ -462,7 +462,8 @@ matcha_status matcha_graph_destroy(matcha_graph *g);
 
 /* Autotuner: when the context's tune cache holds a result for this device, batch shape and
  * configuration, applies it and returns it without timing.  Otherwise times, on this batch
- * (hipEvents, `reps` repetitions each after one warm-up), one field of matcha_tuning at a time with
+ * (hipEvents, `reps` repetitions after one warm-up, in two interleaved rounds of which each value
+ * keeps its faster), one field of matcha_tuning at a time with
  * the others at their best so far: the assembly's row tiles per wave (bufs->f, h, w, prec into
  * bufs->C), the SOFFT ranking workgroup and grid-kernel nodes per wave, then the march's candidates
  * per wave and launch form (each march trial re-runs the search so that it starts from fresh

@@ -169,7 +169,7 @@ typedef struct {
  *     maxima list holds twice as many keys).
  *   asm_tiles: 16-row output tiles per wave and workgroup of the assembly (1, 2, 4 or 8;
  *     default 4).
- *   grid_nodes: polar nodes per wave of the register-resident SOFFT grid kernel (8, 16 or 32;
+ *   grid_nodes: polar nodes per wave of the register-resident SOFFT grid kernel (8, 16, 32, 48 or 64;
  *     default 16).
  *   march_persistent: 1 launches the march as a persistent grid (as many workgroups as are resident
  *     at once, each taking the next particle from a counter in the workspace); 0 (default): one

@@ -730,7 +730,7 @@ matcha_status matcha_set_tuning(matcha_ctx *ctx, const matcha_tuning *t)
     const int at = t->asm_tiles;
     if (at != 0 && at != 1 && at != 2 && at != 4 && at != 8) return MATCHA_ERR_INVALID_ARG;
     const int gn = t->grid_nodes;
-    if (gn != 0 && gn != 8 && gn != 16 && gn != 32) return MATCHA_ERR_INVALID_ARG;
+    if (gn != 0 && gn != 8 && gn != 16 && gn != 32 && gn != 48 && gn != 64) return MATCHA_ERR_INVALID_ARG;
     if (t->march_persistent != 0 && t->march_persistent != 1) return MATCHA_ERR_INVALID_ARG;
     ctx->tune = *t;
     return MATCHA_OK;
@@ -1182,7 +1182,7 @@ matcha_status matcha_autotune(matcha_ctx *ctx, const matcha_batch *batch, const 
     };
     tune_field(&matcha_tuning::asm_tiles, {1, 2, 4, 8}, assemble);
     tune_field(&matcha_tuning::soft_threads, {256, 512}, search);
-    tune_field(&matcha_tuning::grid_nodes, {8, 16, 32}, search);
+    tune_field(&matcha_tuning::grid_nodes, {8, 16, 32, 48, 64}, search);
     std::vector<int32_t> ncs;
     for (int nc : {2, 4, 8})
         if ((soft->Kc + nc - 1) / nc <= 8) ncs.push_back(nc);

@@ -74,12 +74,13 @@ def test_autotune_keeps_results(M):
     refC = M.coeff_assemble(c, batch, f, h, w).clone()
     t = M.autotune(c, batch, f, h, w, wl.B, wl.n_grid, wl.Kc, wl.levels, wl.steps, reps=1)
     assert t["march_nc"] in (2, 4, 8) and t["soft_threads"] in (256, 512) and t["asm_tiles"] in (1, 2, 4, 8)
-    assert t["grid_nodes"] in (8, 16, 32) and t["march_persistent"] in (0, 1)
+    assert t["grid_nodes"] in (8, 16, 32, 48, 64) and t["march_persistent"] in (0, 1)
     assert c.get_tuning() == t
     got = eager(M, c, batch, f, h, w, wl)
     for x, y in zip(got, ref):
         assert torch.equal(x, y)
-    for shape in [(2, 256, 1, 8, 1), (8, 512, 8, 32, 0), (4, 256, 2, 16, 1), (1, 0, 0, 0, 1)]:
+    for shape in [(2, 256, 1, 8, 1), (8, 512, 8, 32, 0), (4, 256, 2, 16, 1), (4, 256, 4, 48, 1), (2, 512, 2, 64, 0),
+                  (1, 0, 0, 0, 1)]:
         c.set_tuning(*shape)
         assert torch.equal(M.coeff_assemble(c, batch, f, h, w), refC), shape
         got = eager(M, c, batch, f, h, w, wl)

@@ -6,8 +6,9 @@
 // k_soft_wigner forms, for every polar node b_i = pi (2i+1) / (2n) of a particle, the Wigner-d
 // transform over l of the coefficients,
 //   S_i[m, n] = sum_{l <= B} C^l_mn d^l_mn(b_i)   on the half plane {m > 0} U {m = 0, n >= 0},
-// one workgroup per particle with its coefficients staged in LDS, one step of the sum serving a
-// pair and its partner; the d values at the nodes come from a table shared by all particles.
+// two workgroups per particle (half its nodes each) with its coefficients staged in LDS, one step
+// of the sum serving a pair and its partner; the d values at the nodes come from a table shared
+// by all particles.
 //
 // k_soft_grid_reg (small bands, operands in registers) or k_soft_grid (any band, operands in LDS)
 // synthesises C_B on the n^3 grid (a_j = 2 pi j / n, c_k = 2 pi k / n) with the 2-D inverse DFT
@@ -139,12 +140,23 @@ __device__ __forceinline__ void wigner_sums(const float4 *__restrict__ Cp, const
 
 // Wigner-d transform of every polar node of the launch's particles into the half-plane array
 // S[m][n + B] of the workspace; the pair's value goes to (m, n), its partner's to (n, m) (n >= 0)
-// or (-n, -m) (n < 0).  One workgroup per particle: its coefficients up to band B are staged in
-// LDS once (when they fit, CP_LDS), and each thread takes (node, pair) tasks with consecutive
-// threads on consecutive pairs, so the node tables are read coalesced.  The entries (0, n < 0),
-// the Hermitian mirrors of (0, -n), are written as zero by the (0, 0) pair's task.
+// or (-n, -m) (n < 0).  kWignerSplit workgroups per particle, each taking a run of its nodes in
+// whole LDS stages (with 4096 particles, 2 against 1 shortens the last partial round of resident
+// workgroups: 279 against 287 us; 3, 4 and 6 took 291, 301 and 326 us, re-staging C each time).
+// Each stages the particle's coefficients up to band B in LDS once (when they fit, CP_LDS), and
+// each thread takes (node, pair) tasks with consecutive threads on consecutive pairs, so the node
+// tables are read coalesced.  The entries (0, n < 0), the Hermitian mirrors of (0, -n), are
+// written as zero by the (0, 0) pair's task.
 constexpr int kWignerThreads = 256;
 constexpr int kWignerStage = 4;  // polar nodes staged in LDS at a time
+constexpr int kWignerSplit = 2;  // workgroups per particle, each taking a run of its polar nodes
+
+// Polar nodes per workgroup: n split kWignerSplit ways, in whole LDS stages.
+__host__ __device__ inline int soft_wigner_span(int n)
+{
+    const int per = (n + kWignerSplit - 1) / kWignerSplit;
+    return (per + kWignerStage - 1) / kWignerStage * kWignerStage;
+}
 
 template <bool CP_LDS>
 __global__ void __launch_bounds__(kWignerThreads) k_soft_wigner(SoftArgs a)
@@ -152,7 +164,10 @@ __global__ void __launch_bounds__(kWignerThreads) k_soft_wigner(SoftArgs a)
     extern __shared__ __align__(16) float4 cs[];
     const int B = a.B, N = a.n, W = 2 * B + 1;
     const int npairs = (B + 1) * (B + 1);
-    const int pl = blockIdx.x, p = a.p0 + pl;
+    const int span = soft_wigner_span(N);
+    const int nsplit = (N + span - 1) / span;
+    const int pl = blockIdx.x / nsplit, p = a.p0 + pl;
+    const int ib = (blockIdx.x - pl * nsplit) * span, ie = min(ib + span, N);  // this workgroup's nodes
     const float4 *Cg = a.C + a.C_off[p] / 2;
     const float4 *Cp = Cg;
     if (CP_LDS) {
@@ -169,8 +184,8 @@ __global__ void __launch_bounds__(kWignerThreads) k_soft_wigner(SoftArgs a)
         // partners fill the entries past the wedge), then out as one contiguous run, so the
         // partners' transposed positions never reach memory as scattered 8-byte writes
         float2 *sb = reinterpret_cast<float2 *>(cs + wedge_row(B + 1));
-        for (int i0 = 0; i0 < N; i0 += kWignerStage) {
-            const int g = min(kWignerStage, N - i0);
+        for (int i0 = ib; i0 < ie; i0 += kWignerStage) {
+            const int g = min(kWignerStage, ie - i0);
             for (int t = threadIdx.x; t < g * npairs; t += kWignerThreads) {
                 const int il = t / npairs, q = t - (t / npairs) * npairs;
                 const PairInfo pi = a.pinfo[q];
@@ -193,7 +208,7 @@ __global__ void __launch_bounds__(kWignerThreads) k_soft_wigner(SoftArgs a)
         }
         return;
     }
-    for (int t = threadIdx.x; t < N * npairs; t += kWignerThreads) {
+    for (int t = ib * npairs + threadIdx.x; t < ie * npairs; t += kWignerThreads) {
         const int i = t / npairs, q = t - (t / npairs) * npairs;
         const PairInfo pi = a.pinfo[q];
         const int m = pi.m, n = pi.n;
@@ -1056,10 +1071,11 @@ size_t soft_select_smem_bytes(int n, int threads)
 
 hipError_t launch_soft_wigner(const SoftArgs &a, int P, hipStream_t s)
 {
+    const int span = soft_wigner_span(a.n), wsplit = (a.n + span - 1) / span;
     if (soft_wigner_cp_lds(a.B))
-        hipLaunchKernelGGL(k_soft_wigner<true>, dim3(P), dim3(kWignerThreads), soft_wigner_smem(a.B), s, a);
+        hipLaunchKernelGGL(k_soft_wigner<true>, dim3(P * wsplit), dim3(kWignerThreads), soft_wigner_smem(a.B), s, a);
     else
-        hipLaunchKernelGGL(k_soft_wigner<false>, dim3(P), dim3(kWignerThreads), 0, s, a);
+        hipLaunchKernelGGL(k_soft_wigner<false>, dim3(P * wsplit), dim3(kWignerThreads), 0, s, a);
     return hipGetLastError();
 }
 

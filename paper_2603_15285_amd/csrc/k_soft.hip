@@ -142,13 +142,14 @@ __device__ __forceinline__ void wigner_sums(const float4 *__restrict__ Cp, const
 // S[m][n + B] of the workspace; the pair's value goes to (m, n), its partner's to (n, m) (n >= 0)
 // or (-n, -m) (n < 0).  kWignerSplit workgroups per particle, each taking a run of its nodes in
 // whole LDS stages (with 4096 particles, 2 against 1 shortens the last partial round of resident
-// workgroups: 279 against 287 us; 3, 4 and 6 took 291, 301 and 326 us, re-staging C each time).
+// workgroups: 279 against 287 us at four nodes per stage; 3, 4 and 6 took 291, 301 and 326 us,
+// re-staging C each time).  Three nodes per stage then took 264 us (2, 4 and 6: 286, 279, 288).
 // Each stages the particle's coefficients up to band B in LDS once (when they fit, CP_LDS), and
 // each thread takes (node, pair) tasks with consecutive threads on consecutive pairs, so the node
 // tables are read coalesced.  The entries (0, n < 0), the Hermitian mirrors of (0, -n), are
 // written as zero by the (0, 0) pair's task.
 constexpr int kWignerThreads = 256;
-constexpr int kWignerStage = 4;  // polar nodes staged in LDS at a time
+constexpr int kWignerStage = 3;  // polar nodes staged in LDS at a time
 constexpr int kWignerSplit = 2;  // workgroups per particle, each taking a run of its polar nodes
 
 // Polar nodes per workgroup: n split kWignerSplit ways, in whole LDS stages.
